@@ -1,0 +1,133 @@
+"""CPU oracle for robust generalized eigenvectors of a real Schur pencil.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline leg
+of the benchmark may import this package; the product library never does.
+
+The arithmetic is plain C (``oracle_impl.h``), built here with gcc into
+``liboracle_tgevc.so`` and called through ctypes.  It computes each eigenvector on
+its own by scalar robust back-substitution (Sections 2 and 4 of the paper), in
+double precision and, as an independent conditioning check, in x86 extended
+precision.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle_tgevc.so")
+_SRC = [os.path.join(_HERE, "tgevc_oracle.c"), os.path.join(_HERE, "oracle_impl.h")]
+
+_lib = None
+
+
+def build() -> str:
+    """Compile the oracle with gcc (no fast-math, no contraction)."""
+    cmd = ["gcc", "-O3", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+           "-o", _SO + ".tmp", _SRC[0], "-lm"]
+    subprocess.run(cmd, check=True, cwd=_HERE)
+    os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        i64, i32p, dp = ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
+        for suf in ("_d", "_ld"):
+            f = getattr(L, "oracle_tgevc" + suf)
+            f.restype = ctypes.c_int
+            f.argtypes = [i64, dp, i64, dp, i64, i32p, dp, i64, i32p, ctypes.c_int, ctypes.c_int]
+            f = getattr(L, "oracle_eigvals" + suf)
+            f.restype = ctypes.c_int
+            f.argtypes = [i64, dp, i64, dp, i64, dp, dp, dp]
+            f = getattr(L, "oracle_blocks" + suf)
+            f.restype = ctypes.c_int
+            f.argtypes = [i64, dp, i64, ctypes.POINTER(ctypes.c_int8)]
+        L.oracle_pd_d.restype = ctypes.c_int
+        L.oracle_pd_d.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.oracle_pu_d.restype = ctypes.c_int
+        L.oracle_pu_d.argtypes = [ctypes.c_double] * 3
+        L.oracle_pd_ld_dbl.restype = ctypes.c_int
+        L.oracle_pd_ld_dbl.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.oracle_pu_ld_dbl.restype = ctypes.c_int
+        L.oracle_pu_ld_dbl.argtypes = [ctypes.c_double] * 3
+        L.oracle_cdiv_d.restype = None
+        L.oracle_cdiv_d.argtypes = [ctypes.c_double] * 4 + [dp, dp]
+        L.oracle_omega_exp_d.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ld_of(A: np.ndarray) -> int:
+    if A.dtype != np.float64 or A.ndim != 2 or A.strides[0] != 8:
+        raise ValueError("expected a column-major float64 matrix")
+    return A.strides[1] // 8 if A.shape[1] > 1 else max(A.shape[0], 1)
+
+
+OMEGA_EXP = 1020
+
+
+def pd(b: float, t: float, precision: str = "double") -> int:
+    """ProtectDivision exponent q (xi = 2^-q)."""
+    f = lib().oracle_pd_d if precision == "double" else lib().oracle_pd_ld_dbl
+    return int(f(float(b), float(t)))
+
+
+def pu(t: float, x: float, y: float, precision: str = "double") -> int:
+    """ProtectUpdate exponent q (xi = 2^-q) with bound xi (t x + y) <= Omega."""
+    f = lib().oracle_pu_d if precision == "double" else lib().oracle_pu_ld_dbl
+    return int(f(float(t), float(x), float(y)))
+
+
+def cdiv(a: float, b: float, c: float, d: float):
+    e, f = ctypes.c_double(), ctypes.c_double()
+    lib().oracle_cdiv_d(a, b, c, d, ctypes.byref(e), ctypes.byref(f))
+    return e.value, f.value
+
+
+def blocks(S: np.ndarray):
+    m = S.shape[0]
+    blk = np.zeros(max(m, 1), dtype=np.int8)
+    info = lib().oracle_blocks_d(m, _dp(S), _ld_of(S), blk.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
+    return blk[:m], int(info)
+
+
+def eigvals(S: np.ndarray, T: np.ndarray, precision: str = "double"):
+    """Normalised (alpha_re, alpha_im, beta) and info bits."""
+    m = S.shape[0]
+    ar, ai, be = (np.zeros(max(m, 1)) for _ in range(3))
+    f = lib().oracle_eigvals_d if precision == "double" else lib().oracle_eigvals_ld
+    info = f(m, _dp(S), _ld_of(S), _dp(T), _ld_of(T), _dp(ar), _dp(ai), _dp(be))
+    return ar[:m], ai[:m], be[:m], int(info)
+
+
+def tgevc(S: np.ndarray, T: np.ndarray, select=None, normalize: bool = True,
+          precision: str = "double", threads: int | None = None):
+    """All (or the selected) right eigenvectors.  Returns (Z, scales, info)."""
+    m = S.shape[0]
+    if threads is None:
+        threads = os.cpu_count() or 1
+    Z = np.zeros((m, m), dtype=np.float64, order="F")
+    scales = np.zeros(max(m, 1), dtype=np.int32)
+    sel = None
+    if select is not None:
+        sel = np.ascontiguousarray(np.asarray(select, dtype=np.int32))
+        if sel.shape != (m,):
+            raise ValueError("select must have length m")
+    f = lib().oracle_tgevc_d if precision == "double" else lib().oracle_tgevc_ld
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    info = f(m, _dp(S), _ld_of(S), _dp(T), _ld_of(T),
+             sel.ctypes.data_as(i32p) if sel is not None else None,
+             _dp(Z), max(m, 1), scales.ctypes.data_as(i32p), int(bool(normalize)), int(threads))
+    return Z, scales[:m], int(info)

@@ -1,0 +1,127 @@
+"""Seeded synthetic real Schur pencils (S, T).
+
+This module only draws random numbers and places them; it contains none of the
+eigenvector method's arithmetic.  Both the HIP path and the CPU oracle take their
+inputs from here.
+
+The pencils have the structure of a generalized real Schur form (Section 2 of the
+paper): S is quasi-upper-triangular with 1x1 and 2x2 diagonal blocks, T is upper
+triangular, and each 2x2 block of (S, T) carries a complex-conjugate eigenvalue
+pair (assumption 2 of Section 2).
+
+Recipe (per pencil, seed ``seed``):
+
+* block walk: a stream keyed by ``(seed, 0)`` gives one uniform number per visited
+  position k; a 2x2 block starts at (k, k+1) when k <= m-2 and the number is below
+  1/3, else k is a 1x1 block.  About half of the eigenvalues then lie in pairs.
+* column j has its own stream keyed by ``(seed, j + 1)`` so that any column can be
+  regenerated alone.  If j is the first column of its diagonal block, the stream
+  first draws the block's diagonal values:
+    - 1x1: s ~ N(0, 1), t ~ U[0.5, 2];
+    - 2x2: S_b = [[a, b], [c, a]] with a ~ N(0, 1), b ~ U[0.5, 2], c = -U[0.5, 2],
+      and T_b = t * I with one t ~ U[0.5, 2] (a single t keeps the pair complex).
+  Then it draws S[0:b0, j] ~ N(0, 1) and T[0:b0, j] ~ N(0, 1), where b0 is the first
+  row of j's diagonal block.
+* ``kind="stress"``: every diagonal t is 10**U[-12, -6] and every off-diagonal entry
+  of S and T is multiplied by 1e100 (the 2x2 internals a, b, c stay unscaled), so
+  unscaled substitution overflows within a few rows.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+KINDS = ("normal", "stress")
+
+
+def _stream(seed: int, j: int) -> np.random.Generator:
+    return np.random.Generator(np.random.Philox(key=(int(seed) << 64) | (j & 0xFFFFFFFFFFFFFFFF)))
+
+
+def block_starts(m: int, seed: int) -> np.ndarray:
+    """Return int8 array ``kind[k]``: 0 = 1x1 block, 1 = first row of a 2x2 block,
+    2 = second row of a 2x2 block."""
+    u = _stream(seed, 0).random(max(m, 1))
+    kind = np.zeros(m, dtype=np.int8)
+    k = 0
+    while k < m:
+        if k <= m - 2 and u[k] < 1.0 / 3.0:
+            kind[k] = 1
+            kind[k + 1] = 2
+            k += 2
+        else:
+            k += 1
+    return kind
+
+
+def _tdiag(rng: np.random.Generator, kind: str) -> float:
+    if kind == "stress":
+        return float(10.0 ** rng.uniform(-12.0, -6.0))
+    return float(rng.uniform(0.5, 2.0))
+
+
+def fill_columns(S: np.ndarray, T: np.ndarray, kind_arr: np.ndarray, seed: int,
+                 j0: int, j1: int, kind: str = "normal") -> None:
+    """Write columns [j0, j1) of S and T (arrays indexed [row, col], any strides)."""
+    m = kind_arr.shape[0]
+    offscale = 1e100 if kind == "stress" else 1.0
+    for j in range(j0, j1):
+        rng = _stream(seed, j + 1)
+        b0 = j - 1 if kind_arr[j] == 2 else j
+        if kind_arr[j] == 0:
+            S[j, j] = rng.standard_normal()
+            T[j, j] = _tdiag(rng, kind)
+        elif kind_arr[j] == 1:
+            a = rng.standard_normal()
+            b = rng.uniform(0.5, 2.0)
+            c = -rng.uniform(0.5, 2.0)
+            t = _tdiag(rng, kind)
+            S[j, j] = a
+            S[j, j + 1] = b
+            S[j + 1, j] = c
+            S[j + 1, j + 1] = a
+            T[j, j] = t
+            T[j + 1, j + 1] = t
+            T[j, j + 1] = 0.0
+        if b0 > 0:
+            s = rng.standard_normal(b0)
+            t = rng.standard_normal(b0)
+            if offscale != 1.0:
+                s *= offscale
+                t *= offscale
+            S[:b0, j] = s
+            T[:b0, j] = t
+    del m
+
+
+def schur_pencil(m: int, seed: int, kind: str = "normal", ld: int | None = None,
+                 threads: int = 1):
+    """Return (S, T, blockkind) with S, T column-major float64 of shape (m, m).
+
+    If ``ld`` > m the arrays are views of column-major (ld, m) buffers, so the
+    leading dimension seen through ``S.strides`` is ``ld``.
+    """
+    if kind not in KINDS:
+        raise ValueError(f"kind must be one of {KINDS}")
+    ld = m if ld is None else int(ld)
+    if ld < max(m, 1):
+        raise ValueError("ld must be >= m")
+    Sb = np.zeros((ld, m), dtype=np.float64, order="F")
+    Tb = np.zeros((ld, m), dtype=np.float64, order="F")
+    S, T = Sb[:m], Tb[:m]
+    kind_arr = block_starts(m, seed)
+    if threads <= 1 or m < 2048:
+        fill_columns(S, T, kind_arr, seed, 0, m, kind)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        # columns have cost ~ j, so deal them out in interleaved chunks
+        chunk = 64
+        ranges = [(j, min(j + chunk, m)) for j in range(0, m, chunk)]
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(lambda r: fill_columns(S, T, kind_arr, seed, r[0], r[1], kind), ranges))
+    return S, T, kind_arr
+
+
+def batch_sizes(count: int = 512, lo: int = 64, hi: int = 2048, seed: int = 3999) -> np.ndarray:
+    """Sizes m_i ~ U{lo..hi} of a batch of independent pencils."""
+    rng = _stream(seed, 0)
+    return rng.integers(lo, hi + 1, size=count)

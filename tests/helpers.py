@@ -1,0 +1,65 @@
+"""Shared test helpers: residuals and normalised comparisons (no method arithmetic
+beyond checking the defining equation S V D - T V B = 0)."""
+from __future__ import annotations
+
+import numpy as np
+
+
+def block_kinds_from_S(S: np.ndarray) -> np.ndarray:
+    m = S.shape[0]
+    kind = np.zeros(m, dtype=np.int8)
+    k = 0
+    while k < m:
+        if k + 1 < m and S[k + 1, k] != 0.0:
+            kind[k], kind[k + 1] = 1, 2
+            k += 2
+        else:
+            k += 1
+    return kind
+
+
+def residuals(S, T, Z, ar, ai, be, cols=None):
+    """eta_c = ||S Z_c D - T Z_c B||_1 / ((||S||_1 + ||T||_1) ||Z_c||_1) for each
+    selected column c, with (alpha, beta) rescaled so max(beta, |a|+|b|) = 1
+    (equation of Section 2.2, large-matrix form, column by column)."""
+    m = S.shape[0]
+    kind = block_kinds_from_S(S)
+    nS = np.abs(S).sum(axis=0).max() if m else 0.0
+    nT = np.abs(T).sum(axis=0).max() if m else 0.0
+    if cols is None:
+        cols = range(m)
+    out = {}
+    for c in cols:
+        p = c - 1 if kind[c] == 2 else c
+        a, b, bt = float(ar[p]), float(ai[p]), float(be[p])
+        s = max(bt, abs(a) + abs(b))
+        if s > 0:
+            a, b, bt = a / s, b / s, bt / s
+        if kind[p] == 0:
+            z = Z[:, p]
+            r = bt * (S @ z) - a * (T @ z)
+            zn = np.abs(z).sum()
+        else:
+            x, y = Z[:, p], Z[:, p + 1]
+            # S [x y] beta I - T [x y] [[a, b], [-b, a]]
+            Sx, Sy, Tx, Ty = S @ x, S @ y, T @ x, T @ y
+            rx = bt * Sx - (a * Tx - b * Ty)
+            ry = bt * Sy - (b * Tx + a * Ty)
+            r = rx if c == p else ry
+            zn = np.abs(Z[:, c]).sum()
+        den = (nS + nT) * zn
+        out[c] = float(np.abs(r).sum() / den) if den > 0 else 0.0
+    return out
+
+
+def normalized_columns(Z, kind, cols):
+    """Each eigenvector divided by max_i(|x_i| + |y_i|) (pairs) or max_i |x_i|."""
+    Zn = {}
+    for c in cols:
+        p = c - 1 if kind[c] == 2 else c
+        if kind[p] == 1:
+            n = (np.abs(Z[:, p]) + np.abs(Z[:, p + 1])).max()
+        else:
+            n = np.abs(Z[:, p]).max()
+        Zn[c] = Z[:, c] / n if n > 0 else Z[:, c].copy()
+    return Zn
