@@ -1,0 +1,115 @@
+/*
+ * rtgevc -- robust right generalized eigenvectors of a real Schur pencil on MI355X.
+ *
+ * C ABI of librtgevc.so.  Every pointer argument named "device" must point to
+ * device memory of the current HIP device; sizes are element counts; matrices are
+ * column-major with a leading dimension >= max(1, m).  No HIP or torch types
+ * appear in the signatures: a stream is passed as `void *` holding a hipStream_t
+ * (NULL = the default stream).
+ *
+ * The problem (Kjelgaard Mikkelsen & Myllykoski, "Parallel Robust Computation of
+ * Generalized Eigenvectors of Matrix Pencils"):
+ *   - Section 2: S is quasi-upper-triangular with 1x1 and 2x2 diagonal blocks, T is
+ *     upper triangular, both of order m (a generalized real Schur form).  A 1x1
+ *     block carries a real eigenvalue, a 2x2 block a complex-conjugate pair, and
+ *     all eigenvalues are distinct.  Eigenvalues are pairs (alpha, beta), beta >= 0.
+ *   - Section 2.1/2.2: with D = diag(beta_j) and B block diagonal holding a_j (1x1)
+ *     or [[a_j, b_j], [-b_j, a_j]] (2x2), the eigenvectors V solve S V D - T V B = 0.
+ *   - Section 3, Algorithm 1: the blocked solver over an M x M tile grid that never
+ *     splits a 2x2 block; Section 4: overflow protection with augmented matrices
+ *     (a mantissa tile plus one power-of-two scale factor per eigenvector column),
+ *     ProtectDivision and ProtectUpdate, Algorithms 2 and 3; Section 5: pre-
+ *     processing (tile norms), solve, update and post-processing (consistent
+ *     scaling) tasks, integer scale exponents, selection closed under conjugation.
+ *
+ * Output layout: Z is m x m.  Column c of a real eigenvalue holds its eigenvector;
+ * for a complex pair in columns (p, p+1), column p holds x and column p+1 holds y
+ * where z = x + i y is the eigenvector of the eigenvalue with positive imaginary
+ * part (the lemma of Section 2.1).  The phase is fixed by the tip convention: a real
+ * eigenvector has z_p = 1 at its own row p; a complex one has z_{p+1} = 1.  Rows
+ * below an eigenvector's diagonal block are zero.  Unselected columns are zero.
+ *
+ * Errors: a negative return is a synchronous error (nothing was enqueued):
+ *   -i          argument i (1-based) is invalid;
+ *   -1000 - e   a HIP call failed with hipError_t e.
+ * Numerical conditions never abort: they are reported as bits of the device int32
+ * *info, readable after the stream has been synchronised (RTGEVC_INFO_*).
+ * All calls are asynchronous with respect to the host and allocate nothing: the
+ * caller provides a device workspace of at least rtgevc_workspace_size() bytes.
+ * Calls sharing one workspace must be ordered (same stream, or synchronised).
+ */
+#ifndef RTGEVC_H
+#define RTGEVC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* info bits */
+#define RTGEVC_INFO_NONFINITE      1   /* NaN or Inf in S or T                              */
+#define RTGEVC_INFO_BAD_STRUCTURE  2   /* two consecutive non-zero sub-diagonal entries      */
+#define RTGEVC_INFO_REAL_PAIR      4   /* a 2x2 block with real eigenvalues (assumption 2)   */
+#define RTGEVC_INFO_INDEFINITE     8   /* alpha = beta = 0 in a 1x1 block: e_p returned      */
+#define RTGEVC_INFO_PERTURBED     16   /* a pivot below smin was replaced (assumption 3)     */
+#define RTGEVC_INFO_SELECT_CLOSED 32   /* select was closed under complex conjugation        */
+#define RTGEVC_INFO_WATCHDOG     128   /* a dependency wait gave up (results invalid)        */
+#define RTGEVC_INFO_PRESCALED    256   /* S and T were scaled by a common power of two       */
+
+/* Tuning options.  Pass NULL for the defaults. */
+typedef struct rtgevc_opts {
+  int32_t mb;         /* tile size: 0 = automatic; else 32, 64 or 128.  Tiles are mb or
+                         mb - 1 rows (a boundary moves up one row rather than split a
+                         2x2 block).                                                   */
+  int32_t normalize;  /* 1 (default when opts is NULL): divide each eigenvector by
+                         max_i(|x_i| + |y_i|) and return scales = 0;
+                         0: return the mantissa in Z and the exponent in scales, so the
+                         eigenvector is 2^scales[c] * Z[:, c].                          */
+  int32_t reserved[6];/* must be zero                                                  */
+} rtgevc_opts;
+
+/* Bytes of device workspace rtgevc() needs for order m with these options
+ * (0 for m < 0). */
+size_t rtgevc_workspace_size(int64_t m, const rtgevc_opts *opts);
+
+/* All selected right eigenvectors of the pencil (S, T).
+ *   m        order (m >= 0; m = 0 is a no-op).
+ *   S, lds   device, column-major, read-only: upper triangle and first sub-diagonal
+ *            are read, the rest is ignored.
+ *   T, ldt   device, column-major, read-only: upper triangle is read.
+ *   select   device int32[m] or NULL (all).  select[c] != 0 selects eigenvalue c;
+ *            either column of a 2x2 block selects both (info bit 32 when applied).
+ *   Z, ldz   device, column-major m x m output (written in full).
+ *   scales   device int32[m] output or NULL: 0 when normalised, else the exponent.
+ *   info     device int32 output or NULL: OR of RTGEVC_INFO_* bits.
+ *   work     device workspace of work_bytes >= rtgevc_workspace_size(m, opts),
+ *            256-byte aligned; its contents on entry are irrelevant.
+ *   opts     NULL or options (see above).
+ *   stream   hipStream_t as void *, NULL = default stream.
+ * S, T, select must not overlap Z, scales, info or work.  Returns 0 when enqueued. */
+int rtgevc(int64_t m, const double *S, int64_t lds, const double *T, int64_t ldt,
+           const int32_t *select, double *Z, int64_t ldz, int32_t *scales, int32_t *info,
+           void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream);
+
+/* Normalised eigenvalues of (S, T) (Section 2): for each column c, alpha = alpha_re[c]
+ * + i alpha_im[c] and beta[c] >= 0, scaled by a power of two so that
+ * max(beta, |Re alpha| + |Im alpha|) lies in (1/2, 1]; a complex pair in (p, p+1) has
+ * alpha_im[p] > 0 and alpha_im[p+1] = -alpha_im[p].  alpha_re, alpha_im, beta are
+ * device double[m]; info as above.  work as for rtgevc with the same m and opts. */
+int rtgevc_eigvals(int64_t m, const double *S, int64_t lds, const double *T, int64_t ldt,
+                   double *alpha_re, double *alpha_im, double *beta, int32_t *info,
+                   void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream);
+
+/* Human-readable text for a negative return code. */
+const char *rtgevc_strerror(int code);
+
+/* Library version, e.g. "0.1.0". */
+const char *rtgevc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTGEVC_H */

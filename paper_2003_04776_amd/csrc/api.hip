@@ -1,0 +1,189 @@
+// C ABI of librtgevc.so: argument checks, workspace carve-up and the launch
+// sequence of the blocked robust solver (Algorithm 1 of Section 3 with the
+// robustness of Section 4 and the task types of Section 5):
+//   pre-processing  ->  for each tile row r from the bottom:
+//                          solve row r   (tips for tile r, diagonal solves for tiles j > r)
+//                          update rows above from row r (every tile column j >= r at once)
+//                   ->  post-processing (consolidation / normalisation).
+// All work is enqueued on the caller's stream; nothing is allocated, nothing waits.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include "../../include/rtgevc.h"
+#include "layout.hpp"
+
+namespace rgev {
+void launch_preprocess(const PencilDesc& P, hipStream_t s);
+void launch_solve(const PencilDesc& P, int r, hipStream_t s);
+void launch_update(const PencilDesc& P, int r, hipStream_t s);
+void launch_consolidate(const PencilDesc& P, hipStream_t s);
+void launch_eigvals_out(const PencilDesc& P, double* are, double* aim, double* bet, hipStream_t s);
+}  // namespace rgev
+
+using namespace rgev;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int resolve_mb(int64_t m, const rtgevc_opts* o) {
+  if (o && o->mb) return o->mb;
+  if (m <= 96) return 32;
+  if (m <= 384) return 64;
+  return 128;
+}
+
+bool opts_ok(const rtgevc_opts* o) {
+  if (!o) return true;
+  if (o->mb != 0 && o->mb != 32 && o->mb != 64 && o->mb != 128) return false;
+  if (o->normalize != 0 && o->normalize != 1) return false;
+  for (int i = 0; i < 6; ++i)
+    if (o->reserved[i] != 0) return false;
+  return true;
+}
+
+struct Carve {
+  size_t off = 0;
+  template <class T>
+  T* take(char* base, size_t count) {
+    T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+    off += up(count * sizeof(T));
+    return p;
+  }
+};
+
+// Lays out the workspace; with base == nullptr it only measures.
+size_t carve(PencilDesc& P, char* base, int64_t m, int mb) {
+  const int Mmax = tile_bound(m, mb);
+  Carve c;
+  P.ctrl = c.take<Ctrl>(base, 1);
+  P.blk = c.take<int8_t>(base, m);
+  P.sel = c.take<int8_t>(base, m);
+  P.tileof = c.take<int32_t>(base, m);
+  P.edges = c.take<int32_t>(base, Mmax + 1);
+  P.ar = c.take<double>(base, m);
+  P.ai = c.take<double>(base, m);
+  P.be = c.take<double>(base, m);
+  P.cnS = c.take<double>(base, m);
+  P.cnT = c.take<double>(base, m);
+  P.nu = c.take<double>(base, (size_t)Mmax * Mmax);
+  P.exps = c.take<int32_t>(base, (size_t)Mmax * m);
+  P.norms = c.take<double>(base, (size_t)Mmax * m);
+  P.W = c.take<double>(base, (size_t)Mmax * w_tile_doubles(mb));
+  P.eW = c.take<int32_t>(base, m);
+  P.nW = c.take<double>(base, m);
+  P.mb = mb;
+  P.Mmax = Mmax;
+  return c.off;
+}
+
+int hip_code(hipError_t e) { return e == hipSuccess ? 0 : -1000 - (int)e; }
+
+int check_common(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt, void* work,
+                 size_t work_bytes, const rtgevc_opts* opts, int i_work, int i_bytes, int i_opts) {
+  if (m < 0) return -1;
+  if (m > 0 && !S) return -2;
+  if (lds < (m > 1 ? m : 1)) return -3;
+  if (m > 0 && !T) return -4;
+  if (ldt < (m > 1 ? m : 1)) return -5;
+  if (!opts_ok(opts)) return -i_opts;
+  if (m > 0) {
+    if (!work || (reinterpret_cast<uintptr_t>(work) % kAlign) != 0) return -i_work;
+    if (work_bytes < rtgevc_workspace_size(m, opts)) return -i_bytes;
+  }
+  return 0;
+}
+
+PencilDesc make_desc(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt,
+                     const int32_t* select, double* Z, int64_t ldz, int32_t* scales, int32_t* info,
+                     void* work, const rtgevc_opts* opts) {
+  PencilDesc P;
+  memset(&P, 0, sizeof(P));
+  P.m = m;
+  P.lds = lds;
+  P.ldt = ldt;
+  P.ldz = ldz;
+  P.S = S;
+  P.T = T;
+  P.Z = Z;
+  P.scales = scales;
+  P.select = select;
+  carve(P, static_cast<char*>(work), m, resolve_mb(m, opts));
+  P.info = info ? info : &P.ctrl->info_local;
+  P.normalize = opts ? opts->normalize : 1;
+  return P;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rtgevc_workspace_size(int64_t m, const rtgevc_opts* opts) {
+  if (m < 0) return 0;
+  if (m == 0) return kAlign;
+  PencilDesc P;
+  memset(&P, 0, sizeof(P));
+  return carve(P, nullptr, m, resolve_mb(m, opts));
+}
+
+int rtgevc(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt, const int32_t* select,
+           double* Z, int64_t ldz, int32_t* scales, int32_t* info, void* work, size_t work_bytes,
+           const rtgevc_opts* opts, void* stream) {
+  int rc = check_common(m, S, lds, T, ldt, work, work_bytes, opts, 11, 12, 13);
+  if (rc) return rc;
+  if (m > 0 && !Z) return -7;
+  if (ldz < (m > 1 ? m : 1)) return -8;
+  if (m == 0) return 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts);
+  launch_preprocess(P, s);
+  for (int r = P.Mmax - 1; r >= 0; --r) {
+    launch_solve(P, r, s);
+    launch_update(P, r, s);
+  }
+  launch_consolidate(P, s);
+  return hip_code(hipGetLastError());
+}
+
+int rtgevc_eigvals(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt, double* alpha_re,
+                   double* alpha_im, double* beta, int32_t* info, void* work, size_t work_bytes,
+                   const rtgevc_opts* opts, void* stream) {
+  int rc = check_common(m, S, lds, T, ldt, work, work_bytes, opts, 10, 11, 12);
+  if (rc) return rc;
+  if (m > 0 && !alpha_re) return -6;
+  if (m > 0 && !alpha_im) return -7;
+  if (m > 0 && !beta) return -8;
+  if (m == 0) return 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PencilDesc P = make_desc(m, S, lds, T, ldt, nullptr, nullptr, m, nullptr, info, work, opts);
+  launch_preprocess(P, s);
+  launch_eigvals_out(P, alpha_re, alpha_im, beta, s);
+  return hip_code(hipGetLastError());
+}
+
+const char* rtgevc_strerror(int code) {
+  if (code == 0) return "success";
+  if (code <= -1000) return hipGetErrorString(static_cast<hipError_t>(-1000 - code));
+  switch (code) {
+    case -1: return "argument 1 (m) is negative";
+    case -2: return "argument 2 (S) is NULL";
+    case -3: return "argument 3 (lds) is below max(1, m)";
+    case -4: return "argument 4 (T) is NULL";
+    case -5: return "argument 5 (ldt) is below max(1, m)";
+    case -6: return "argument 6 is invalid";
+    case -7: return "argument 7 is NULL";
+    case -8: return "argument 8 is invalid (NULL or leading dimension below max(1, m))";
+    case -10: return "argument 10 is invalid";
+    case -11: return "argument 11 is invalid (workspace NULL or not 256-byte aligned, or too small)";
+    case -12: return "argument 12 is invalid (workspace too small, or options)";
+    case -13: return "argument 13 (opts) is invalid";
+    default: return "invalid argument";
+  }
+}
+
+const char* rtgevc_version(void) { return "0.1.0"; }
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// Post-processing (Section 5, fourth task type): enforce one consistent scaling on
+// every eigenvector.  Segment (k, c) represents 2^exps[k][c] * Z[rows of tile k, c];
+// the column's common exponent is E_c = max_k exps[k][c], and each segment is
+// rescaled by the exact power of two 2^(exps[k][c] - E_c) (flushing to zero when the
+// gap exceeds the exponent range).  Optionally each eigenvector is then divided by
+// max_i (|x_i| + |y_i|).  Rows below the eigenvector's tile and unselected columns
+// are zeroed.  One workgroup per eigenvalue (a complex pair is handled as one).
+#include <hip/hip_runtime.h>
+
+#include "layout.hpp"
+#include "robust.hpp"
+
+namespace rgev {
+
+constexpr int kConsThreads = 256;
+
+__device__ __forceinline__ double block_max(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  const int w = threadIdx.x / 64;
+  if (threadIdx.x % 64 == 0) red[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int i = 0; i < kConsThreads / 64; ++i) r = fmax(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kConsThreads) void consolidate_kernel(PencilDesc P) {
+  __shared__ double red[kConsThreads / 64];
+  const int64_t c = blockIdx.x;
+  const int64_t m = P.m;
+  if (c >= m) return;
+  const int kind = P.blk[c];
+  if (kind == 2) return;
+  const bool cplx = kind == 1;
+  const int jt = P.tileof[c];
+  const int64_t rend = P.edges[jt + 1];
+  double* zx = P.Z + c * P.ldz;
+  double* zy = cplx ? zx + P.ldz : nullptr;
+  if (!P.sel[c]) {
+    for (int64_t i = threadIdx.x; i < m; i += kConsThreads) {
+      zx[i] = 0.0;
+      if (cplx) zy[i] = 0.0;
+    }
+    if (threadIdx.x == 0 && P.scales) {
+      P.scales[c] = 0;
+      if (cplx) P.scales[c + 1] = 0;
+    }
+    return;
+  }
+  // common exponent
+  int E = INT_MIN;
+  for (int k = threadIdx.x; k <= jt; k += kConsThreads) E = max(E, P.exps[(int64_t)k * m + c]);
+  double Ed = block_max((double)E, red);   // exponents are exact in double
+  E = (int)Ed;
+  // rescale every segment to the common exponent
+  double nm = 0.0;
+  for (int64_t i = threadIdx.x; i < rend; i += kConsThreads) {
+    const int d = P.exps[(int64_t)P.tileof[i] * m + c] - E;
+    const double x = ldexp(zx[i], d);
+    zx[i] = x;
+    double v = fabs(x);
+    if (cplx) {
+      const double y = ldexp(zy[i], d);
+      zy[i] = y;
+      v += fabs(y);
+    }
+    nm = fmax(nm, v);
+  }
+  nm = block_max(nm, red);
+  if (P.normalize && nm > 0.0) {
+    for (int64_t i = threadIdx.x; i < rend; i += kConsThreads) {
+      zx[i] = zx[i] / nm;
+      if (cplx) zy[i] = zy[i] / nm;
+    }
+  }
+  for (int64_t i = rend + threadIdx.x; i < m; i += kConsThreads) {
+    zx[i] = 0.0;
+    if (cplx) zy[i] = 0.0;
+  }
+  if (threadIdx.x == 0 && P.scales) {
+    const int sc = P.normalize ? 0 : E;
+    P.scales[c] = sc;
+    if (cplx) P.scales[c + 1] = sc;
+  }
+}
+
+void launch_consolidate(const PencilDesc& P, hipStream_t s) {
+  consolidate_kernel<<<(unsigned)P.m, kConsThreads, 0, s>>>(P);
+}
+
+// eigenvalues in the caller's layout: conjugate in the second column of a pair
+__global__ void eigvals_out_kernel(PencilDesc P, double* are, double* aim, double* bet) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= P.m) return;
+  are[c] = P.ar[c];
+  aim[c] = P.blk[c] == 2 ? -P.ai[c] : P.ai[c];
+  bet[c] = P.be[c];
+}
+
+void launch_eigvals_out(const PencilDesc& P, double* are, double* aim, double* bet, hipStream_t s) {
+  eigvals_out_kernel<<<(unsigned)((P.m + 255) / 256), 256, 0, s>>>(P, are, aim, bet);
+}
+
+}  // namespace rgev

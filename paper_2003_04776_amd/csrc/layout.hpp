@@ -1,0 +1,72 @@
+// Per-pencil descriptor shared by the host driver and every kernel, and the
+// carve-up of the caller's workspace.
+//
+// Data layout in HBM (m = order, MB = nominal tile size, Mmax = bound on the tile
+// count M, which is only known on the device after the structure scan):
+//   S, T, Z            caller's column-major matrices (ld >= m)
+//   blk[m]   int8      0 = 1x1 block, 1 = first row of a 2x2 block, 2 = second row
+//   sel[m]   int8      selection after closure under conjugation
+//   tileof[m] int32    tile index of each row/column
+//   edges[Mmax+1]      tile boundaries (greedy: MB rows, or MB-1 if MB would split a pair)
+//   ar, ai, be [m]     normalised eigenvalue of each column (ai > 0 for both columns of a pair)
+//   cnS, cnT [m]       per column: largest |S|, |T| above the column's diagonal block
+//                      inside its own diagonal tile (norms for the diagonal solves)
+//   nu[Mmax*Mmax]      nu[k*Mmax + r] >= max_i sum_l |S_il| + |T_il| over tile pair (k, r)
+//   exps[Mmax*m]       exponent of segment (tile row k, column c): value = 2^e * mantissa
+//   norms[Mmax*m]      infinity norm (upper bound) of that segment's mantissa
+//   W[Mmax * WS]       right-updated tiles of the current source row (Algorithm 2),
+//                      packed in the operand order of the FP64 matrix instruction
+//   eW, nW [m]         exponent and norm bound of W per column
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+namespace rgev {
+
+struct Ctrl {
+  int32_t M;          // number of tiles
+  int32_t pad0;
+  double psc;         // common power-of-two prescale of S and T (1 = none)
+  unsigned long long numax_bits;  // largest scaled tile-pair norm (as bits, >= 0)
+  int32_t info_local; // info target when the caller passed NULL
+  int32_t pad1[9];
+};
+
+struct PencilDesc {
+  int64_t m, lds, ldt, ldz;
+  const double* S;
+  const double* T;
+  double* Z;
+  int32_t* scales;
+  const int32_t* select;
+  int32_t* info;
+  int8_t* blk;
+  int8_t* sel;
+  int32_t* tileof;
+  int32_t* edges;
+  double* ar;
+  double* ai;
+  double* be;
+  double* cnS;
+  double* cnT;
+  double* nu;
+  int32_t* exps;
+  double* norms;
+  double* W;
+  int32_t* eW;
+  double* nW;
+  Ctrl* ctrl;
+  int32_t mb;
+  int32_t Mmax;
+  int32_t normalize;
+  int32_t pad;
+};
+
+// W tile of one (source row, tile column) pair: 2*MB K-rows x MB columns.
+__host__ __device__ constexpr int64_t w_tile_doubles(int mb) { return 2LL * mb * mb; }
+
+__host__ __device__ constexpr int tile_bound(int64_t m, int mb) {
+  return m <= 0 ? 0 : (int)((m + (mb - 2)) / (mb - 1)) + 1;
+}
+
+}  // namespace rgev

@@ -1,0 +1,184 @@
+"""Python binding of librtgevc.so: argument marshalling only.
+
+Every step of the computation runs in the library's HIP kernels; torch supplies
+device memory and the stream.  If the library is missing, every call raises: there
+is no CPU fallback.
+
+Matrices are column-major float64 device tensors: a tensor ``A`` with
+``A.stride(0) == 1`` and ``A.stride(1) == ld >= m`` (for instance ``B.t()`` of a
+contiguous row-major ``B``, or ``colmajor_to_device(numpy_array)``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtgevc.so")
+
+INFO_NONFINITE = 1
+INFO_BAD_STRUCTURE = 2
+INFO_REAL_PAIR = 4
+INFO_INDEFINITE = 8
+INFO_PERTURBED = 16
+INFO_SELECT_CLOSED = 32
+INFO_WATCHDOG = 128
+INFO_PRESCALED = 256
+
+
+class RtgevcError(RuntimeError):
+    pass
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("mb", ctypes.c_int32), ("normalize", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+
+
+_lib = None
+
+
+def load():
+    """Load the built library (raises if it is missing: no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RtgevcError(f"{LIB_PATH} is not built; run paper_2003_04776_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    i64, vp, sz = ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+    op = ctypes.POINTER(Opts)
+    L.rtgevc_workspace_size.restype = sz
+    L.rtgevc_workspace_size.argtypes = [i64, op]
+    L.rtgevc.restype = ctypes.c_int
+    L.rtgevc.argtypes = [i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, vp, sz, op, vp]
+    L.rtgevc_eigvals.restype = ctypes.c_int
+    L.rtgevc_eigvals.argtypes = [i64, vp, i64, vp, i64, vp, vp, vp, vp, vp, sz, op, vp]
+    L.rtgevc_strerror.restype = ctypes.c_char_p
+    L.rtgevc_strerror.argtypes = [ctypes.c_int]
+    L.rtgevc_version.restype = ctypes.c_char_p
+    L.rtgevc_version.argtypes = []
+    _lib = L
+    return L
+
+
+EXPORTED = ("rtgevc_workspace_size", "rtgevc", "rtgevc_eigvals", "rtgevc_strerror", "rtgevc_version")
+
+
+def make_opts(mb: int = 0, normalize: bool = True) -> Opts:
+    o = Opts()
+    o.mb = int(mb)
+    o.normalize = 1 if normalize else 0
+    return o
+
+
+def workspace_size(m: int, mb: int = 0, normalize: bool = True) -> int:
+    o = make_opts(mb, normalize)
+    return int(load().rtgevc_workspace_size(int(m), ctypes.byref(o)))
+
+
+def strerror(code: int) -> str:
+    return load().rtgevc_strerror(int(code)).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise RtgevcError(f"{what} failed ({rc}): {strerror(rc)}")
+
+
+def _ld(A, m: int) -> int:
+    import torch
+    if A.dtype != torch.float64 or A.dim() != 2 or A.device.type != "cuda":
+        raise ValueError("expected a float64 CUDA matrix")
+    if tuple(A.shape) != (m, m):
+        raise ValueError(f"expected shape ({m}, {m}), got {tuple(A.shape)}")
+    if m > 1 and A.stride(0) != 1:
+        raise ValueError("expected a column-major matrix (stride(0) == 1)")
+    return max(A.stride(1), m, 1) if m > 1 else max(m, 1)
+
+
+def colmajor_to_device(A: np.ndarray, device="cuda", ld: int | None = None):
+    """Copy a column-major numpy matrix to a column-major device tensor (ld >= m)."""
+    import torch
+    m, n = A.shape
+    ld = m if ld is None else ld
+    buf = torch.zeros((n, ld), dtype=torch.float64, device=device)
+    buf[:, :m] = torch.from_numpy(np.ascontiguousarray(A.T))
+    return buf.t()[:m]
+
+
+def colmajor_empty(m: int, device="cuda", ld: int | None = None):
+    import torch
+    ld = m if ld is None else ld
+    return torch.empty((m, max(ld, 1)), dtype=torch.float64, device=device).t()[:m]
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+@dataclass
+class Result:
+    Z: object
+    scales: object
+    info: object
+
+
+class Solver:
+    """Holds a workspace for repeated calls of one order m (the workspace is the only
+    allocation, made once by torch; the library itself allocates nothing)."""
+
+    def __init__(self, m: int, mb: int = 0, normalize: bool = True, device="cuda"):
+        import torch
+        self.m = int(m)
+        self.opts = make_opts(mb, normalize)
+        self.nbytes = int(load().rtgevc_workspace_size(self.m, ctypes.byref(self.opts)))
+        self.work = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
+        self.device = device
+
+    def run(self, S, T, select=None, Z=None, scales=None, info=None, stream=None) -> Result:
+        import torch
+        m = self.m
+        lds, ldt = _ld(S, m), _ld(T, m)
+        if Z is None:
+            Z = colmajor_empty(m, self.device)
+        ldz = _ld(Z, m)
+        if scales is None:
+            scales = torch.empty(max(m, 1), dtype=torch.int32, device=self.device)
+        if info is None:
+            info = torch.zeros(1, dtype=torch.int32, device=self.device)
+        sel = None
+        if select is not None:
+            sel = torch.as_tensor(select, dtype=torch.int32, device=self.device).contiguous()
+            if sel.shape != (m,):
+                raise ValueError("select must have length m")
+        rc = load().rtgevc(m, S.data_ptr(), lds, T.data_ptr(), ldt,
+                           sel.data_ptr() if sel is not None else None,
+                           Z.data_ptr(), ldz, scales.data_ptr(), info.data_ptr(),
+                           self.work.data_ptr(), self.nbytes, ctypes.byref(self.opts),
+                           _stream_ptr(stream))
+        _check(rc, "rtgevc")
+        return Result(Z, scales[:m], info)
+
+    def eigvals(self, S, T, stream=None):
+        import torch
+        m = self.m
+        lds, ldt = _ld(S, m), _ld(T, m)
+        out = [torch.empty(max(m, 1), dtype=torch.float64, device=self.device) for _ in range(3)]
+        info = torch.zeros(1, dtype=torch.int32, device=self.device)
+        rc = load().rtgevc_eigvals(m, S.data_ptr(), lds, T.data_ptr(), ldt, out[0].data_ptr(),
+                                   out[1].data_ptr(), out[2].data_ptr(), info.data_ptr(),
+                                   self.work.data_ptr(), self.nbytes, ctypes.byref(self.opts),
+                                   _stream_ptr(stream))
+        _check(rc, "rtgevc_eigvals")
+        return out[0][:m], out[1][:m], out[2][:m], info
+
+
+def tgevc(S, T, select=None, normalize: bool = True, mb: int = 0, stream=None) -> Result:
+    """All (or the selected) right eigenvectors of the Schur pencil (S, T)."""
+    return Solver(S.shape[0], mb=mb, normalize=normalize, device=S.device).run(S, T, select, stream=stream)

@@ -1,0 +1,85 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every
+symbol the header declares, and rejects invalid arguments before touching the GPU."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2003_04776_amd import rtgevc as rt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "rtgevc.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(rtgevc[a-z_]*)\s*\(", text, re.M)))
+
+
+def test_header_symbols_exported():
+    lib = rt.load()
+    syms = _declared_symbols()
+    assert set(syms) == set(rt.EXPORTED), syms
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+def test_version_and_strerror():
+    assert rt.load().rtgevc_version().decode().count(".") == 2
+    assert "success" in rt.strerror(0)
+    assert "m" in rt.strerror(-1)
+
+
+def test_workspace_size_monotone():
+    assert rt.workspace_size(-1) == 0
+    prev = 0
+    for m in (1, 10, 100, 1000, 5000):
+        w = rt.workspace_size(m)
+        assert w >= prev and w % 256 == 0
+        prev = w
+    assert rt.workspace_size(1000, mb=64) != rt.workspace_size(1000, mb=128)
+
+
+def _call(m=4, S=1, lds=4, T=1, ldt=4, sel=None, Z=1, ldz=4, work=256, nbytes=None, opts=None):
+    lib = rt.load()
+    if nbytes is None:
+        nbytes = rt.workspace_size(m) if m >= 0 else 0
+    o = opts if opts is not None else rt.make_opts()
+    return lib.rtgevc(m, S, lds, T, ldt, sel, Z, ldz, None, None, work, nbytes, ctypes.byref(o), None)
+
+
+def test_argument_errors_before_any_gpu_work():
+    # fake non-null pointers: every check fails before a launch
+    assert _call(m=-1) == -1
+    assert _call(S=None) == -2
+    assert _call(lds=3) == -3
+    assert _call(T=None) == -4
+    assert _call(ldt=2) == -5
+    assert _call(Z=None) == -7
+    assert _call(ldz=1) == -8
+    assert _call(work=None) == -11
+    assert _call(work=257) == -11          # not 256-byte aligned
+    assert _call(nbytes=16) == -12
+    bad = rt.make_opts(mb=48)
+    assert _call(opts=bad) == -13
+    bad = rt.make_opts()
+    bad.reserved[2] = 1
+    assert _call(opts=bad) == -13
+    assert _call(m=0, S=None, T=None, Z=None, work=None, lds=1, ldt=1, ldz=1) == 0
+
+
+def test_eigvals_argument_errors():
+    lib = rt.load()
+    o = rt.make_opts()
+    n = rt.workspace_size(4)
+    assert lib.rtgevc_eigvals(4, 1, 4, 1, 4, None, 1, 1, None, 256, n, ctypes.byref(o), None) == -6
+    assert lib.rtgevc_eigvals(4, 1, 4, 1, 4, 1, 1, 1, None, 256, 8, ctypes.byref(o), None) == -11
+
+
+def test_no_cpu_fallback(monkeypatch):
+    monkeypatch.setattr(rt, "_lib", None)
+    monkeypatch.setattr(rt, "LIB_PATH", "/nonexistent/librtgevc.so")
+    with pytest.raises(rt.RtgevcError):
+        rt.load()

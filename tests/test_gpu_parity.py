@@ -1,0 +1,299 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, element by element
+on seeded inputs, plus the residual of S V D - T V B = 0 (Section 2.2), the overflow-
+stress invariants and the edge cases.
+
+Bar: normalised eigenvectors within 1e-10 of the double-precision oracle on every
+well-conditioned column (a column whose double and extended-precision oracle results
+agree to 1e-12); the normwise residual eta_c <= 64 m 2^-53 on every column."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import block_kinds_from_S, residuals, residuals_torch
+from paper_2003_04776_amd import pencils
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+TOL = 1e-10
+WELL = 1e-12
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(S, T, mb=0, select=None, normalize=True, ld=None):
+    torch = _torch()
+    from paper_2003_04776_amd import rtgevc as rt
+    m = S.shape[0]
+    Sd = rt.colmajor_to_device(S, ld=ld)
+    Td = rt.colmajor_to_device(T, ld=ld)
+    solver = rt.Solver(m, mb=mb, normalize=normalize)
+    res = solver.run(Sd, Td, select=select)
+    torch.cuda.synchronize()
+    return res.Z.cpu().numpy(), res.scales.cpu().numpy(), int(res.info.item())
+
+
+def compare(S, T, Zg, select=None, cols=None, tol=TOL):
+    """Max error over well-conditioned columns; also returns the per-column errors."""
+    Zo, _, _ = oracle.tgevc(S, T, select=select)
+    Zl, _, _ = oracle.tgevc(S, T, select=select, precision="ld")
+    m = S.shape[0]
+    cols = range(m) if cols is None else cols
+    errs, worst, nill = [], 0.0, 0
+    for c in cols:
+        e = float(np.max(np.abs(Zg[:, c] - Zo[:, c]))) if m else 0.0
+        errs.append(e)
+        if np.max(np.abs(Zo[:, c] - Zl[:, c])) <= WELL:
+            worst = max(worst, e)
+        else:
+            nill += 1
+    return worst, np.array(errs), nill
+
+
+SMALL = [(1, 32, 0), (2, 32, 1), (3, 32, 2), (5, 32, 3), (17, 32, 4), (31, 32, 5), (32, 32, 6),
+         (33, 32, 7), (64, 32, 8), (65, 64, 9), (100, 32, 10), (129, 64, 11), (200, 64, 12),
+         (256, 0, 0), (257, 128, 13), (300, 128, 14), (513, 128, 15), (700, 64, 16), (1000, 128, 17)]
+
+
+@pytest.mark.parametrize("m,mb,seed", SMALL)
+def test_parity_small(m, mb, seed):
+    _say(f"[parity] m={m} mb={mb} seed={seed}")
+    S, T, blk = pencils.schur_pencil(m, seed)
+    Zg, sc, info = run_gpu(S, T, mb=mb)
+    assert info == 0, info
+    assert np.isfinite(Zg).all()
+    assert (sc == 0).all()
+    worst, errs, nill = compare(S, T, Zg)
+    _say(f"   max err {worst:.3e} (median {np.median(errs):.1e}, ill {nill})")
+    assert worst <= TOL
+    ar, ai, be, _ = oracle.eigvals(S, T)
+    eta = residuals(S, T, Zg, ar, ai, be)
+    assert max(eta.values()) <= 64 * m * U
+
+
+@pytest.mark.parametrize("m,mb,seed", [(60, 32, 200), (300, 64, 201), (521, 128, 202)])
+def test_parity_stress(m, mb, seed):
+    """Overflow-stress pencils: unscaled substitution overflows within a few rows."""
+    _say(f"[stress] m={m} mb={mb} seed={seed}")
+    S, T, blk = pencils.schur_pencil(m, seed, "stress")
+    Zg, sc, info = run_gpu(S, T, mb=mb, normalize=False)
+    assert info & ~16 == 0, info
+    assert np.isfinite(Zg).all()
+    assert (sc >= 0).all() and sc.max() > 1000
+    assert np.abs(Zg).max() <= 2.0 ** 1020
+    Zn, _, _ = run_gpu(S, T, mb=mb)
+    worst, errs, nill = compare(S, T, Zn)
+    _say(f"   max err {worst:.3e} ill {nill} max scale {sc.max()}")
+    assert worst <= TOL
+    ar, ai, be, _ = oracle.eigvals(S, T)
+    eta = residuals(S, T, Zn, ar, ai, be)
+    assert max(eta.values()) <= 64 * m * U
+
+
+def test_unnormalised_representation():
+    """2^scales[c] * Z[:, c] represents the eigenvector: normalising it gives the
+    oracle's normalised eigenvector."""
+    m = 700
+    S, T, blk = pencils.schur_pencil(m, 21)
+    Zu, sc, info = run_gpu(S, T, mb=64, normalize=False)
+    assert info == 0 and (sc >= 0).all()
+    Zo, _, _ = oracle.tgevc(S, T)
+    for c in range(m):
+        p = c - 1 if blk[c] == 2 else c
+        if blk[p] == 1:
+            n = (np.abs(Zu[:, p]) + np.abs(Zu[:, p + 1])).max()
+        else:
+            n = np.abs(Zu[:, p]).max()
+        assert sc[c] == sc[p]
+        assert np.max(np.abs(Zu[:, c] / n - Zo[:, c])) <= TOL
+
+
+def test_leading_dimension_padding():
+    m = 301
+    S, T, blk = pencils.schur_pencil(m, 22, ld=m + 7)
+    Zg, sc, info = run_gpu(S, T, mb=64, ld=m + 7)
+    assert info == 0
+    worst, _, _ = compare(np.asfortranarray(S), np.asfortranarray(T), Zg)
+    assert worst <= TOL
+
+
+def test_select_subset():
+    m = 400
+    S, T, blk = pencils.schur_pencil(m, 23)
+    rng = np.random.default_rng(0)
+    sel = (rng.random(m) < 0.2).astype(np.int32)
+    pairs = np.nonzero(blk == 1)[0]
+    sel[pairs[0]] = 1
+    sel[pairs[0] + 1] = 0           # closure needed
+    Zg, sc, info = run_gpu(S, T, mb=64, select=sel)
+    assert info == 32
+    Zo, _, io = oracle.tgevc(S, T, select=sel)
+    assert io == 32
+    assert np.max(np.abs(Zg - Zo)) <= TOL
+    on = sel.astype(bool) | np.roll(sel.astype(bool) & (blk == 1), 1) | np.roll(sel.astype(bool) & (blk == 2), -1)
+    assert not Zg[:, ~on].any()
+
+
+def test_eigvals_entry_point():
+    torch = _torch()
+    from paper_2003_04776_amd import rtgevc as rt
+    m = 500
+    S, T, blk = pencils.schur_pencil(m, 24)
+    solver = rt.Solver(m)
+    ar, ai, be, info = solver.eigvals(rt.colmajor_to_device(S), rt.colmajor_to_device(T))
+    torch.cuda.synchronize()
+    oa, oi, ob, _ = oracle.eigvals(S, T)
+    assert int(info.item()) == 0
+    for x, y in ((ar, oa), (ai, oi), (be, ob)):
+        x = x.cpu().numpy()
+        assert np.allclose(x, y, rtol=1e-14, atol=1e-15)
+    assert np.all(ob >= 0)
+    s = np.maximum(ob, np.abs(oa) + np.abs(oi))
+    assert np.all((s > 0.5) & (s <= 1.0))
+
+
+def _all_pairs(m, seed):
+    rng = np.random.default_rng(seed)
+    S = np.triu(rng.standard_normal((m, m)))
+    T = np.triu(rng.standard_normal((m, m)))
+    for p in range(0, m - 1, 2):
+        a, b, c, t = rng.standard_normal(), rng.uniform(0.5, 2), -rng.uniform(0.5, 2), rng.uniform(0.5, 2)
+        S[p:p + 2, p:p + 2] = [[a, b], [c, a]]
+        T[p:p + 2, p:p + 2] = [[t, 0], [0, t]]
+    if m % 2:
+        T[m - 1, m - 1] = rng.uniform(0.5, 2)
+    return np.asfortranarray(S), np.asfortranarray(T)
+
+
+@pytest.mark.parametrize("m,mb", [(130, 32), (256, 64), (383, 128)])
+def test_all_pairs_and_all_real(m, mb):
+    S, T = _all_pairs(m, m)
+    Zg, sc, info = run_gpu(S, T, mb=mb)
+    assert info == 0
+    worst, _, _ = compare(S, T, Zg)
+    assert worst <= TOL
+    rng = np.random.default_rng(m)
+    S2 = np.asfortranarray(np.triu(rng.standard_normal((m, m))))
+    T2 = np.asfortranarray(np.triu(rng.standard_normal((m, m))))
+    T2[np.diag_indices(m)] = rng.uniform(0.5, 2, m)
+    Zg, sc, info = run_gpu(S2, T2, mb=mb)
+    assert info == 0
+    worst, _, _ = compare(S2, T2, Zg)
+    assert worst <= TOL
+
+
+def test_pair_on_every_tile_boundary():
+    """A 2x2 block straddles every nominal boundary, so every tile is MB - 1 rows."""
+    m, mb = 320, 32
+    S, T = _all_pairs(m, 5)
+    # shift the pair pattern by one so the pairs sit at (31, 32), (63, 64), ...
+    S = np.asfortranarray(np.pad(S, ((1, 0), (1, 0)))[: m, : m])
+    T = np.asfortranarray(np.pad(T, ((1, 0), (1, 0)))[: m, : m])
+    S[0, 0], T[0, 0] = 0.3, 1.1
+    kind = block_kinds_from_S(S)
+    assert kind[31] == 1 and kind[63] == 1
+    Zg, sc, info = run_gpu(S, T, mb=mb)
+    assert info == 0
+    worst, _, _ = compare(S, T, Zg)
+    assert worst <= TOL
+
+
+def test_info_bits():
+    m = 50
+    S, T, blk = pencils.schur_pencil(m, 25)
+    S2 = S.copy(order="F")
+    S2[3, 7] = np.nan
+    _, _, info = run_gpu(S2, T, mb=32)
+    assert info & 1
+    S3 = S.copy(order="F")
+    k = int(np.nonzero(blk == 1)[0][0])
+    if k + 2 < m:
+        S3[k + 2, k + 1] = 0.7
+        _, _, info = run_gpu(S3, T, mb=32)
+        assert info & 2
+
+
+def test_common_power_of_two_prescale():
+    """Entries near the top of the range: S and T are scaled by a common power of
+    two (eigenvectors unchanged) and the prescale bit is set."""
+    m = 200
+    S, T, blk = pencils.schur_pencil(m, 26)
+    f = 2.0 ** 1010
+    Zg, sc, info = run_gpu(np.asfortranarray(S * f), np.asfortranarray(T * f), mb=64)
+    assert info == 256
+    Zr, _, _ = run_gpu(S, T, mb=64)
+    assert np.max(np.abs(Zg - Zr)) <= 1e-14
+
+
+def test_repeat_is_deterministic():
+    m = 600
+    S, T, _ = pencils.schur_pencil(m, 27)
+    Z1, _, _ = run_gpu(S, T, mb=128)
+    Z2, _, _ = run_gpu(S, T, mb=128)
+    assert np.array_equal(Z1, Z2)
+
+
+# ------------------------------------------------------------- full sizes --
+
+def _full_size(m, seed, kind, nsample, mb=0):
+    torch = _torch()
+    from paper_2003_04776_amd import rtgevc as rt
+    _say(f"[full] m={m} kind={kind} seed={seed}: generating")
+    S, T, blk = pencils.schur_pencil(m, seed, kind, threads=16)
+    Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
+    solver = rt.Solver(m, mb=mb)
+    _say("   running")
+    res = solver.run(Sd, Td)
+    torch.cuda.synchronize()
+    info = int(res.info.item())
+    assert info & ~16 == 0, info
+    Z = res.Z
+    assert bool(torch.isfinite(Z).all())
+    _say("   residuals")
+    ar, ai, be, _ = oracle.eigvals(S, T)
+    eta = residuals_torch(Sd, Td, Z, ar, ai, be, blk)
+    _say(f"   max eta {eta.max():.3e} bound {64 * m * U:.3e}")
+    assert eta.max() <= 64 * m * U
+    # oracle on a deterministic sample of columns spread over the range
+    cols = sorted(set(np.linspace(0, m - 1, nsample).astype(int).tolist()))
+    sel = np.zeros(m, dtype=np.int32)
+    sel[cols] = 1
+    Zo, _, _ = oracle.tgevc(S, T, select=sel)
+    Zl, _, _ = oracle.tgevc(S, T, select=sel, precision="ld")
+    cols = np.nonzero(sel | np.roll(sel & (blk == 1), 1) | np.roll(sel & (blk == 2), -1))[0]
+    Zs = Z[:, torch.from_numpy(cols).to(Z.device)].cpu().numpy()
+    worst, nill = 0.0, 0
+    for i, c in enumerate(cols):
+        e = np.max(np.abs(Zs[:, i] - Zo[:, c]))
+        if np.max(np.abs(Zo[:, c] - Zl[:, c])) <= WELL:
+            worst = max(worst, e)
+        else:
+            nill += 1
+    _say(f"   sampled {len(cols)} columns: max err {worst:.3e} ill {nill}")
+    assert worst <= TOL
+
+
+def test_full_size_8192():
+    _full_size(8192, 100, "normal", 48)
+
+
+def test_full_size_stress_8192():
+    _full_size(8192, 200, "stress", 32)
+
+
+def test_full_size_32768():
+    _full_size(32768, 400, "normal", 12)
