@@ -102,6 +102,24 @@ int rtgevc_eigvals(int64_t m, const double *S, int64_t lds, const double *T, int
                    double *alpha_re, double *alpha_im, double *beta, int32_t *info,
                    void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream);
 
+/* Benchmark variant of rtgevc(): the same work on the same stream, with a HIP event
+ * recorded before and after every kernel launch.  Unlike rtgevc() it synchronises the
+ * stream (after pre-processing and at the end) and creates and destroys events, so it
+ * is not for graph capture.  On success stats (host double[nstats], nstats >=
+ * RTGEVC_TIMED_NSTATS) holds:
+ *   [0] total device time, ms (first to last event)
+ *   [1..4] summed device time of the pre-processing, diagonal-solve, tile-update and
+ *          consolidation launches, ms
+ *   [5..8] number of launches of each of those four classes
+ *   [9] algorithmic flops of the tile updates, sum over k < r <= j of 4 h_k h_r h_j
+ *   [10] number of tiles M;  [11] tile size mb
+ * Returns 0, a negative argument code as rtgevc() (-15: stats), or -1000 - hipError. */
+#define RTGEVC_TIMED_NSTATS 12
+int rtgevc_timed(int64_t m, const double *S, int64_t lds, const double *T, int64_t ldt,
+                 const int32_t *select, double *Z, int64_t ldz, int32_t *scales, int32_t *info,
+                 void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream,
+                 double *stats, int nstats);
+
 /* Human-readable text for a negative return code. */
 const char *rtgevc_strerror(int code);
 

@@ -11,6 +11,9 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
+#include <vector>
+
 #include "../../include/rtgevc.h"
 #include "layout.hpp"
 
@@ -81,6 +84,27 @@ size_t carve(PencilDesc& P, char* base, int64_t m, int mb) {
 }
 
 int hip_code(hipError_t e) { return e == hipSuccess ? 0 : -1000 - (int)e; }
+
+// Events of the timed entry point, created once per device and reused by later calls
+// (held until the process ends).
+std::mutex g_event_mu;
+std::vector<hipEvent_t> g_events[64];
+
+hipError_t get_events(int n, hipEvent_t** out) {
+  int dev = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return err;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::vector<hipEvent_t>& v = g_events[dev];
+  while ((int)v.size() < n) {
+    hipEvent_t e;
+    err = hipEventCreate(&e);
+    if (err != hipSuccess) return err;
+    v.push_back(e);
+  }
+  *out = v.data();
+  return hipSuccess;
+}
 
 int check_common(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt, void* work,
                  size_t work_bytes, const rtgevc_opts* opts, int i_work, int i_bytes, int i_opts) {
@@ -164,6 +188,88 @@ int rtgevc_eigvals(int64_t m, const double* S, int64_t lds, const double* T, int
   return hip_code(hipGetLastError());
 }
 
+int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt, const int32_t* select,
+                 double* Z, int64_t ldz, int32_t* scales, int32_t* info, void* work, size_t work_bytes,
+                 const rtgevc_opts* opts, void* stream, double* stats, int nstats) {
+  int rc = check_common(m, S, lds, T, ldt, work, work_bytes, opts, 11, 12, 13);
+  if (rc) return rc;
+  if (m > 0 && !Z) return -7;
+  if (ldz < (m > 1 ? m : 1)) return -8;
+  if (!stats || nstats < RTGEVC_TIMED_NSTATS) return -15;
+  for (int i = 0; i < nstats; ++i) stats[i] = 0.0;
+  if (m == 0) return 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts);
+  // events bracket every launch on the caller's stream
+  const int nev = 2 * (2 * P.Mmax + 2);
+  std::lock_guard<std::mutex> lock(g_event_mu);
+  hipEvent_t* ev = nullptr;
+  int used = 0;
+  hipError_t err = get_events(nev, &ev);
+  if (err != hipSuccess) return hip_code(err);
+  auto mark = [&]() {
+    const hipError_t e = hipEventRecord(ev[used++], s);
+    if (err == hipSuccess) err = e;
+  };
+  struct Span { int cls, e0, e1; };
+  Span* spans = new Span[2 * P.Mmax + 2];
+  int nsp = 0;
+  mark();
+  launch_preprocess(P, s);
+  mark();
+  spans[nsp++] = Span{0, 0, 1};
+  int32_t M = 0;
+  err = hipMemcpyAsync(&M, &P.ctrl->M, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  for (int r = M - 1; r >= 0 && err == hipSuccess; --r) {
+    const int a = used;
+    mark();
+    launch_solve(P, r, s);
+    mark();
+    spans[nsp++] = Span{1, a, a + 1};
+    if (r > 0) {
+      const int b = used;
+      mark();
+      launch_update(P, r, s);
+      mark();
+      spans[nsp++] = Span{2, b, b + 1};
+    }
+  }
+  const int c0 = used;
+  mark();
+  launch_consolidate(P, s);
+  mark();
+  spans[nsp++] = Span{3, c0, c0 + 1};
+  if (err == hipSuccess) err = hipGetLastError();
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  int32_t* edges = new int32_t[M + 1];
+  if (err == hipSuccess && M > 0) err = hipMemcpy(edges, P.edges, sizeof(int32_t) * (M + 1), hipMemcpyDeviceToHost);
+  if (err == hipSuccess) {
+    float ms = 0.0f;
+    err = hipEventElapsedTime(&ms, ev[0], ev[used - 1]);
+    stats[0] = ms;
+    for (int i = 0; i < nsp && err == hipSuccess; ++i) {
+      err = hipEventElapsedTime(&ms, ev[spans[i].e0], ev[spans[i].e1]);
+      stats[1 + spans[i].cls] += ms;
+      stats[5 + spans[i].cls] += 1.0;
+    }
+    // algorithmic flops of the tile updates: sum over k < r <= j of 2 h_k (2 h_r) h_j
+    double fl = 0.0;
+    for (int r = M - 1; r >= 1; --r) {
+      const double hr = edges[r + 1] - edges[r];
+      const double hj_sum = (double)(edges[M] - edges[r]);   // columns of tiles j >= r
+      const double hk_sum = (double)edges[r];                // rows of tiles k < r
+      fl += 4.0 * hk_sum * hr * hj_sum;
+    }
+    stats[9] = fl;
+    stats[10] = M;
+    stats[11] = P.mb;
+  }
+  delete[] edges;
+  delete[] spans;
+  return hip_code(err);
+}
+
 const char* rtgevc_strerror(int code) {
   if (code == 0) return "success";
   if (code <= -1000) return hipGetErrorString(static_cast<hipError_t>(-1000 - code));
@@ -180,6 +286,7 @@ const char* rtgevc_strerror(int code) {
     case -11: return "argument 11 is invalid (workspace NULL or not 256-byte aligned, or too small)";
     case -12: return "argument 12 is invalid (workspace too small, or options)";
     case -13: return "argument 13 (opts) is invalid";
+    case -15: return "argument 15 (stats) is NULL or too short";
     default: return "invalid argument";
   }
 }

@@ -93,12 +93,56 @@ def fill_columns(S: np.ndarray, T: np.ndarray, kind_arr: np.ndarray, seed: int,
     del m
 
 
+def _fill_worker(job):
+    """Child process: attach the shared buffers and fill a set of column ranges."""
+    from multiprocessing import shared_memory
+    name_s, name_t, ld, m, seed, kind, ranges = job
+    hs = shared_memory.SharedMemory(name=name_s)
+    ht = shared_memory.SharedMemory(name=name_t)
+    try:
+        S = np.ndarray((ld, m), dtype=np.float64, buffer=hs.buf, order="F")[:m]
+        T = np.ndarray((ld, m), dtype=np.float64, buffer=ht.buf, order="F")[:m]
+        kind_arr = block_starts(m, seed)
+        for j0, j1 in ranges:
+            fill_columns(S, T, kind_arr, seed, j0, j1, kind)
+        del S, T
+    finally:
+        hs.close()
+        ht.close()
+    return True
+
+
+def _fill_parallel(Sb, Tb, ld, m, seed, kind, procs):
+    """Fill S and T with `procs` spawned child processes writing into shared memory;
+    the result is identical to the single-process fill (columns are independent)."""
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+    nbytes = ld * m * 8
+    hs = shared_memory.SharedMemory(create=True, size=nbytes)
+    ht = shared_memory.SharedMemory(create=True, size=nbytes)
+    try:
+        chunk = 128
+        ranges = [(j, min(j + chunk, m)) for j in range(0, m, chunk)]
+        jobs = [(hs.name, ht.name, ld, m, seed, kind, ranges[w::procs]) for w in range(procs)]
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(procs) as pool:
+            assert all(pool.map(_fill_worker, jobs))
+        Sb[...] = np.ndarray((ld, m), dtype=np.float64, buffer=hs.buf, order="F")
+        Tb[...] = np.ndarray((ld, m), dtype=np.float64, buffer=ht.buf, order="F")
+    finally:
+        hs.close()
+        hs.unlink()
+        ht.close()
+        ht.unlink()
+
+
 def schur_pencil(m: int, seed: int, kind: str = "normal", ld: int | None = None,
                  threads: int = 1):
     """Return (S, T, blockkind) with S, T column-major float64 of shape (m, m).
 
     If ``ld`` > m the arrays are views of column-major (ld, m) buffers, so the
-    leading dimension seen through ``S.strides`` is ``ld``.
+    leading dimension seen through ``S.strides`` is ``ld``.  ``threads`` > 1 fills
+    the columns in that many child processes (same values).
     """
     if kind not in KINDS:
         raise ValueError(f"kind must be one of {KINDS}")
@@ -109,15 +153,10 @@ def schur_pencil(m: int, seed: int, kind: str = "normal", ld: int | None = None,
     Tb = np.zeros((ld, m), dtype=np.float64, order="F")
     S, T = Sb[:m], Tb[:m]
     kind_arr = block_starts(m, seed)
-    if threads <= 1 or m < 2048:
+    if threads <= 1 or m < 4096:
         fill_columns(S, T, kind_arr, seed, 0, m, kind)
     else:
-        from concurrent.futures import ThreadPoolExecutor
-        # columns have cost ~ j, so deal them out in interleaved chunks
-        chunk = 64
-        ranges = [(j, min(j + chunk, m)) for j in range(0, m, chunk)]
-        with ThreadPoolExecutor(max_workers=threads) as ex:
-            list(ex.map(lambda r: fill_columns(S, T, kind_arr, seed, r[0], r[1], kind), ranges))
+        _fill_parallel(Sb, Tb, ld, m, seed, kind, int(threads))
     return S, T, kind_arr
 
 

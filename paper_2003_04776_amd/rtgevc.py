@@ -56,6 +56,9 @@ def load():
     L.rtgevc.argtypes = [i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, vp, sz, op, vp]
     L.rtgevc_eigvals.restype = ctypes.c_int
     L.rtgevc_eigvals.argtypes = [i64, vp, i64, vp, i64, vp, vp, vp, vp, vp, sz, op, vp]
+    L.rtgevc_timed.restype = ctypes.c_int
+    L.rtgevc_timed.argtypes = [i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, vp, sz, op, vp,
+                               ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     L.rtgevc_strerror.restype = ctypes.c_char_p
     L.rtgevc_strerror.argtypes = [ctypes.c_int]
     L.rtgevc_version.restype = ctypes.c_char_p
@@ -64,7 +67,9 @@ def load():
     return L
 
 
-EXPORTED = ("rtgevc_workspace_size", "rtgevc", "rtgevc_eigvals", "rtgevc_strerror", "rtgevc_version")
+EXPORTED = ("rtgevc_workspace_size", "rtgevc", "rtgevc_eigvals", "rtgevc_timed", "rtgevc_strerror",
+            "rtgevc_version")
+TIMED_NSTATS = 12
 
 
 def make_opts(mb: int = 0, normalize: bool = True) -> Opts:
@@ -164,6 +169,20 @@ class Solver:
                            _stream_ptr(stream))
         _check(rc, "rtgevc")
         return Result(Z, scales[:m], info)
+
+    def run_timed(self, S, T, Z, scales, info, stream=None):
+        """rtgevc_timed: same work, HIP events around every launch; returns the stats
+        dict (synchronises the stream)."""
+        m = self.m
+        lds, ldt, ldz = _ld(S, m), _ld(T, m), _ld(Z, m)
+        st = (ctypes.c_double * TIMED_NSTATS)()
+        rc = load().rtgevc_timed(m, S.data_ptr(), lds, T.data_ptr(), ldt, None, Z.data_ptr(), ldz,
+                                 scales.data_ptr(), info.data_ptr(), self.work.data_ptr(), self.nbytes,
+                                 ctypes.byref(self.opts), _stream_ptr(stream), st, TIMED_NSTATS)
+        _check(rc, "rtgevc_timed")
+        keys = ("total_ms", "pre_ms", "solve_ms", "update_ms", "consolidate_ms", "n_pre", "n_solve",
+                "n_update", "n_consolidate", "update_flops", "M", "mb")
+        return dict(zip(keys, list(st)))
 
     def eigvals(self, S, T, stream=None):
         import torch
