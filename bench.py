@@ -74,6 +74,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--m", type=int, default=32768)
     ap.add_argument("--mb", type=int, default=0)
+    ap.add_argument("--band", type=int, default=0)
     ap.add_argument("--seed", type=int, default=400)
     ap.add_argument("--kind", default="normal", choices=("normal", "stress"))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -97,7 +98,7 @@ def main():
     S, T, blk = pencils.schur_pencil(m, args.seed, args.kind, threads=16)
     log(f"[bench] generated in {time.perf_counter() - t0:.1f} s; uploading")
     Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
-    solver = rt.Solver(m, mb=args.mb, normalize=True)
+    solver = rt.Solver(m, mb=args.mb, normalize=True, band=args.band)
     Z = rt.colmajor_empty(m)
     scales = torch.empty(m, dtype=torch.int32, device="cuda")
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
@@ -140,7 +141,8 @@ def main():
         "config": {
             "workload": f"all right eigenvectors of a real Schur pencil, m={m}, robust FP64 "
                         f"(power-of-two scale exponents), normalised output",
-            "m": m, "mb": int(st0["mb"]), "tiles": int(st0["M"]), "seed": args.seed,
+            "m": m, "mb": int(st0["mb"]), "band": int(solver.opts.band) or 2, "tiles": int(st0["M"]),
+            "seed": args.seed,
             "generator": args.kind, "flops_per_step": F,
         },
         "roofline": {

@@ -67,7 +67,10 @@ typedef struct rtgevc_opts {
                          max_i(|x_i| + |y_i|) and return scales = 0;
                          0: return the mantissa in Z and the exponent in scales, so the
                          eigenvector is 2^scales[c] * Z[:, c].                          */
-  int32_t reserved[6];/* must be zero                                                  */
+  int32_t band;       /* tile rows per update band: 0 = automatic, else 1..8.  After the
+                         rows of a band are solved (with small updates inside the band),
+                         one contraction applies all of them to every tile above it.   */
+  int32_t reserved[5];/* must be zero                                                  */
 } rtgevc_opts;
 
 /* Bytes of device workspace rtgevc() needs for order m with these options

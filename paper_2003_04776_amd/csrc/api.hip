@@ -14,13 +14,13 @@
 #include <mutex>
 #include <vector>
 
-#include "../../include/rtgevc.h"
+#include "rtgevc.h"
 #include "layout.hpp"
 
 namespace rgev {
 void launch_preprocess(const PencilDesc& P, hipStream_t s);
 void launch_solve(const PencilDesc& P, int r, hipStream_t s);
-void launch_update(const PencilDesc& P, int r, hipStream_t s);
+bool launch_update(const PencilDesc& P, int k_lo, int k_hi, int j_lo, int s_lo, int s_hi, hipStream_t s);
 void launch_consolidate(const PencilDesc& P, hipStream_t s);
 void launch_eigvals_out(const PencilDesc& P, double* are, double* aim, double* bet, hipStream_t s);
 }  // namespace rgev
@@ -31,6 +31,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int resolve_band(const rtgevc_opts* o) { return (o && o->band) ? o->band : 2; }
 
 int resolve_mb(int64_t m, const rtgevc_opts* o) {
   if (o && o->mb) return o->mb;
@@ -43,7 +45,8 @@ bool opts_ok(const rtgevc_opts* o) {
   if (!o) return true;
   if (o->mb != 0 && o->mb != 32 && o->mb != 64 && o->mb != 128) return false;
   if (o->normalize != 0 && o->normalize != 1) return false;
-  for (int i = 0; i < 6; ++i)
+  if (o->band < 0 || o->band > kMaxBand) return false;
+  for (int i = 0; i < 5; ++i)
     if (o->reserved[i] != 0) return false;
   return true;
 }
@@ -59,7 +62,7 @@ struct Carve {
 };
 
 // Lays out the workspace; with base == nullptr it only measures.
-size_t carve(PencilDesc& P, char* base, int64_t m, int mb) {
+size_t carve(PencilDesc& P, char* base, int64_t m, int mb, int band) {
   const int Mmax = tile_bound(m, mb);
   Carve c;
   P.ctrl = c.take<Ctrl>(base, 1);
@@ -75,15 +78,45 @@ size_t carve(PencilDesc& P, char* base, int64_t m, int mb) {
   P.nu = c.take<double>(base, (size_t)Mmax * Mmax);
   P.exps = c.take<int32_t>(base, (size_t)Mmax * m);
   P.norms = c.take<double>(base, (size_t)Mmax * m);
-  P.W = c.take<double>(base, (size_t)Mmax * w_tile_doubles(mb));
-  P.eW = c.take<int32_t>(base, m);
-  P.nW = c.take<double>(base, m);
+  P.W = c.take<double>(base, (size_t)band * Mmax * w_tile_doubles(mb));
+  P.eW = c.take<int32_t>(base, (size_t)band * m);
+  P.nW = c.take<double>(base, (size_t)band * m);
   P.mb = mb;
   P.Mmax = Mmax;
+  P.band = band;
   return c.off;
 }
 
 int hip_code(hipError_t e) { return e == hipSuccess ? 0 : -1000 - (int)e; }
+
+// The blocked back-substitution for tile rows [0, rows), bottom band first.  Bands are
+// the rows [R b, R b + R - 1]; inside a band the rows are solved from the bottom up,
+// each followed by the small update of the band rows above it; then one update applies
+// the whole band to every tile row above the band.  mark(kind) is called before and
+// after each launch (kind 1 = solve, 2 = update); rows at or beyond the device's tile
+// count M are no-ops in the kernels.
+template <class Mark>
+void enqueue_rows(const PencilDesc& P, int rows, hipStream_t s, Mark&& mark) {
+  const int R = P.band;
+  for (int b = (rows - 1) / R; b >= 0; --b) {
+    const int r_lo = R * b, r_hi = R * b + R - 1;
+    for (int i = (r_hi < rows ? r_hi : rows - 1); i >= r_lo; --i) {
+      mark(1, true);
+      launch_solve(P, i, s);
+      mark(1, false);
+      if (i > r_lo) {
+        mark(2, true);
+        launch_update(P, r_lo, i, i, i, i, s);
+        mark(2, false);
+      }
+    }
+    if (r_lo > 0) {
+      mark(2, true);
+      launch_update(P, 0, r_lo, r_lo, r_lo, r_hi, s);
+      mark(2, false);
+    }
+  }
+}
 
 // Events of the timed entry point, created once per device and reused by later calls
 // (held until the process ends).
@@ -135,7 +168,7 @@ PencilDesc make_desc(int64_t m, const double* S, int64_t lds, const double* T, i
   P.Z = Z;
   P.scales = scales;
   P.select = select;
-  carve(P, static_cast<char*>(work), m, resolve_mb(m, opts));
+  carve(P, static_cast<char*>(work), m, resolve_mb(m, opts), resolve_band(opts));
   P.info = info ? info : &P.ctrl->info_local;
   P.normalize = opts ? opts->normalize : 1;
   return P;
@@ -150,7 +183,7 @@ size_t rtgevc_workspace_size(int64_t m, const rtgevc_opts* opts) {
   if (m == 0) return kAlign;
   PencilDesc P;
   memset(&P, 0, sizeof(P));
-  return carve(P, nullptr, m, resolve_mb(m, opts));
+  return carve(P, nullptr, m, resolve_mb(m, opts), resolve_band(opts));
 }
 
 int rtgevc(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt, const int32_t* select,
@@ -164,10 +197,7 @@ int rtgevc(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt
   hipStream_t s = static_cast<hipStream_t>(stream);
   PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts);
   launch_preprocess(P, s);
-  for (int r = P.Mmax - 1; r >= 0; --r) {
-    launch_solve(P, r, s);
-    launch_update(P, r, s);
-  }
+  enqueue_rows(P, P.Mmax, s, [](int, bool) {});
   launch_consolidate(P, s);
   return hip_code(hipGetLastError());
 }
@@ -201,7 +231,7 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
   hipStream_t s = static_cast<hipStream_t>(stream);
   PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts);
   // events bracket every launch on the caller's stream
-  const int nev = 2 * (2 * P.Mmax + 2);
+  const int nev = 2 * (3 * P.Mmax + 4);
   std::lock_guard<std::mutex> lock(g_event_mu);
   hipEvent_t* ev = nullptr;
   int used = 0;
@@ -212,7 +242,7 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
     if (err == hipSuccess) err = e;
   };
   struct Span { int cls, e0, e1; };
-  Span* spans = new Span[2 * P.Mmax + 2];
+  Span* spans = new Span[3 * P.Mmax + 4];
   int nsp = 0;
   mark();
   launch_preprocess(P, s);
@@ -221,20 +251,14 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
   int32_t M = 0;
   err = hipMemcpyAsync(&M, &P.ctrl->M, sizeof(int32_t), hipMemcpyDeviceToHost, s);
   if (err == hipSuccess) err = hipStreamSynchronize(s);
-  for (int r = M - 1; r >= 0 && err == hipSuccess; --r) {
-    const int a = used;
-    mark();
-    launch_solve(P, r, s);
-    mark();
-    spans[nsp++] = Span{1, a, a + 1};
-    if (r > 0) {
-      const int b = used;
+  if (err == hipSuccess)
+    enqueue_rows(P, M, s, [&](int kind, bool before) {
       mark();
-      launch_update(P, r, s);
-      mark();
-      spans[nsp++] = Span{2, b, b + 1};
-    }
-  }
+      if (!before) {
+        spans[nsp] = Span{kind, used - 2, used - 1};
+        ++nsp;
+      }
+    });
   const int c0 = used;
   mark();
   launch_consolidate(P, s);

@@ -14,9 +14,10 @@
 //   nu[Mmax*Mmax]      nu[k*Mmax + r] >= max_i sum_l |S_il| + |T_il| over tile pair (k, r)
 //   exps[Mmax*m]       exponent of segment (tile row k, column c): value = 2^e * mantissa
 //   norms[Mmax*m]      infinity norm (upper bound) of that segment's mantissa
-//   W[Mmax * WS]       right-updated tiles of the current source row (Algorithm 2),
-//                      packed in the operand order of the FP64 matrix instruction
-//   eW, nW [m]         exponent and norm bound of W per column
+//   W[R * Mmax * WS]   right-updated tiles of the last R solved source rows (Algorithm 2),
+//                      slot (r % R) * Mmax + j, packed in the operand order of the FP64
+//                      matrix instruction
+//   eW, nW [R * m]     exponent and norm bound of W per source-row slot and column
 #pragma once
 #include <stddef.h>
 #include <stdint.h>
@@ -59,8 +60,10 @@ struct PencilDesc {
   int32_t mb;
   int32_t Mmax;
   int32_t normalize;
-  int32_t pad;
+  int32_t band;       // R: tile rows per update band
 };
+
+constexpr int kMaxBand = 8;
 
 // W tile of one (source row, tile column) pair: 2*MB K-rows x MB columns.
 __host__ __device__ constexpr int64_t w_tile_doubles(int mb) { return 2LL * mb * mb; }

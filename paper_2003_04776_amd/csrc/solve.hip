@@ -312,8 +312,9 @@ __global__ __launch_bounds__(MB) void solve_kernel(PencilDesc P, int r) {
     if (nxb > 1.0) frexp(nxb, &g);
     colG[lc] = g;
     if (inrange) {
-      P.eW[c] = e + g;
-      P.nW[c] = ldexp(nxb, -g);
+      const int64_t slot = (int64_t)(r % P.band) * m;
+      P.eW[slot + c] = e + g;
+      P.nW[slot + c] = ldexp(nxb, -g);
     }
   }
   // ---- write the solved tile to Z (coalesced down each column) ----
@@ -325,10 +326,10 @@ __global__ __launch_bounds__(MB) void solve_kernel(PencilDesc P, int r) {
   // ---- W = 2^-g [X D ; -X B] in operand order: [kstep][col block][lane] ----
   {
     constexpr int CBM = MB / 16;
-    const int KP = (hr + 3) & ~3;          // rows of each half, padded to the K step
+    const int KP = (hr + 15) & ~15;        // rows of each half, padded to the update's K chunk
     const int KS = 2 * KP / 4;
     const int total = KS * CBM * 64;
-    double* Wj = P.W + (int64_t)j * w_tile_doubles(MB);
+    double* Wj = P.W + ((int64_t)(r % P.band) * P.Mmax + j) * w_tile_doubles(MB);
     for (int idx = lc; idx < total; idx += MB) {
       const int s = idx / (CBM * 64);
       const int rem = idx % (CBM * 64);

@@ -8,53 +8,98 @@
 // itself (the product is bounded by the tile norm nu because |W| <= 1, so it cannot
 // overflow), which leaves X untouched for the other tiles that read it.
 //
-// One workgroup per target tile (k, j); wave w owns columns [32w, 32w + 32) of the
-// tile and all of its rows: 16x16x4 FP64 MFMA blocks, MB/16 row blocks by 2 column
-// blocks, accumulators in registers, operands streamed straight from L2/HBM with the
-// next K step prefetched.  Each wave owns whole segments, so the new segment norms
-// need no cross-wave reduction.
+// A launch applies a band of source rows s in [s_lo, s_hi] (only s <= j for tile column
+// j) to the target tiles k in [k_lo, k_hi), j in [j_lo, M): each source's W keeps its
+// own exponent, the per-column factors that bring the band to one exponent are exact
+// powers of two applied while W is staged, and one ProtectUpdate bounds the sum.
+//
+// One workgroup (4 waves) per target tile (k, j).  The K dimension (2 h_s per source, each half
+// padded to 16) is streamed in chunks of 16: the next chunk of [S_kr | T_kr] and of
+// the packed W tile is fetched into registers while the matrix cores work on the
+// current chunk in LDS (one barrier per chunk).  The waves split the tile 2 x 2; each
+// keeps a (MB/2) x (MB/2) block of 16x16x4 FP64 accumulators.  Tiles are visited in
+// 8 x 8 blocks, each XCD taking a contiguous range of blocks, so the S/T and W tiles
+// that neighbouring workgroups share stay in that XCD's L2.
 #include <hip/hip_runtime.h>
 
 #include "layout.hpp"
 #include "robust.hpp"
 
+#include <climits>
+
 namespace rgev {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+constexpr int kUpdThreads = 256;
+constexpr int kChunk = 16;   // K rows per LDS stage
+
+struct UpdRange {
+  int k_lo, k_hi;   // target tile rows [k_lo, k_hi)
+  int j_lo;         // target tile columns [j_lo, M)
+  int s_lo, s_hi;   // source tile rows (all below every target row)
+};
+
 template <int MB>
-__global__ __launch_bounds__(MB * 2) void update_kernel(PencilDesc P, int r) {
-  constexpr int RB = MB / 16;    // row blocks
-  constexpr int CBM = MB / 16;   // column blocks of a W tile
+__global__ __launch_bounds__(kUpdThreads, 2) void update_kernel(PencilDesc P, UpdRange U) {
+  constexpr int WR = MB / 2;            // rows per wave
+  constexpr int WC = MB / 2;            // columns per wave
+  constexpr int RB = WR / 16;           // row blocks per wave
+  constexpr int CB = WC / 16;           // column blocks per wave
+  constexpr int CBM = MB / 16;          // column blocks of a W tile
+  constexpr int TPR = kUpdThreads / MB; // threads per A row in the stage load
+  constexpr int AK = kChunk / TPR;      // A values per thread per stage
+  constexpr int WV = kChunk * MB / kUpdThreads;   // W values per thread per stage
+  __shared__ double As[2][kChunk * MB];          // [k][row]
+  __shared__ double Ws[2][kChunk * MB];          // packed [kstep][col block][lane]
+  __shared__ int sfY[MB], sfA[MB], seN[MB];
+  __shared__ int sg[kMaxBand][MB];   // exponent of each source's W relative to the band's
+  __shared__ int sgany[kMaxBand];
+  __shared__ double red[2][MB];
+
   const int M = P.ctrl->M;
-  if (r >= M || r == 0) return;
-  const int ntiles = r * (M - r);
-  // XCD-aware order: workgroup b runs on XCD b % 8; give each XCD a contiguous range
-  // of tiles (k fastest) so the W tile of a column and neighbouring S/T tiles stay in
-  // that XCD's L2.  The grid is a multiple of 8, so this is a bijection.
+  if (U.j_lo >= M || U.k_hi <= U.k_lo || U.s_lo >= M) return;
+  // ---- tile of this workgroup: 8 x 8 blocks of (k, j), each XCD a contiguous range ----
+  const int nk = U.k_hi - U.k_lo, nj = M - U.j_lo;
+  const int nbk = (nk + 7) / 8, nbj = (nj + 7) / 8;
   const int per = (int)(gridDim.x / 8);
-  const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  if (t >= ntiles) return;
-  const int k = t % r;
-  const int j = r + t / r;
+  const int idx = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (idx >= nbk * nbj * 64) return;
+  const int blk = idx / 64, w64 = idx % 64;
+  const int k = U.k_lo + 8 * (blk % nbk) + (w64 % 8);
+  const int j = U.j_lo + 8 * (blk / nbk) + (w64 / 8);
+  if (k >= U.k_hi || j >= M) return;
+
   const int64_t m = P.m;
+  const int R = P.band;
   const int k0 = P.edges[k], hk = P.edges[k + 1] - k0;
-  const int r0 = P.edges[r], hr = P.edges[r + 1] - r0;
   const int c0 = P.edges[j], hj = P.edges[j + 1] - c0;
-  const bool first = (j == r);   // the first update of (k, j): Y is still zero
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  // sources that reach column tile j: s_lo .. s_end (the source row j itself, when in the
+  // band, makes this the first update of (k, j): Y is still zero)
+  const int s_end = min(min(U.s_hi, M - 1), j);
+  const int ns = s_end - U.s_lo + 1;
+  const bool first = (j <= U.s_hi);
+  int cs[kMaxBand + 1];     // cumulative K chunks per source
+  cs[0] = 0;
+#pragma unroll
+  for (int i = 0; i < kMaxBand; ++i) {
+    const int s = U.s_lo + i;
+    const int hs = i < ns ? P.edges[s + 1] - P.edges[s] : 0;
+    cs[i + 1] = cs[i] + 2 * ((hs + 15) & ~15) / kChunk;
+  }
+  const int tid = threadIdx.x;
+  if (tid < kMaxBand) sgany[tid] = 0;
+  __syncthreads();
+  const int wave = tid / 64, lane = tid % 64;
+  const int wr = wave / 2, wc = wave % 2;
   const int li = lane % 16, lk = lane / 16;
 
   // ---- per-column scales (Algorithm 3): common exponent, ProtectUpdate ----
-  const double nu = P.nu[(int64_t)k * P.Mmax + r];
-  int fY[2], fA[2], eN[2];
-  bool colok[2];
-#pragma unroll
-  for (int cb = 0; cb < 2; ++cb) {
-    const int n = 32 * wave + 16 * cb + li;
-    colok[cb] = n < hj;
-    fY[cb] = 0; fA[cb] = 0; eN[cb] = 0;
-    if (colok[cb]) {
+  if (tid < MB) {
+    const int n = tid;
+    int fy = 0, fa = 0, en = 0;
+    int g[kMaxBand] = {};
+    if (n < hj) {
       const int64_t c = c0 + n;
       const int kind = P.blk[c];
       int eY = 0;
@@ -65,108 +110,201 @@ __global__ __launch_bounds__(MB * 2) void update_kernel(PencilDesc P, int r) {
         if (kind == 1) nY += P.norms[(int64_t)k * m + c + 1];
         else if (kind == 2) nY += P.norms[(int64_t)k * m + c - 1];
       }
-      const int eW = P.eW[c];
-      const double nW = P.nW[c];
-      const int ks = eY > eW ? eY : eW;
-      const int q = protect_update(nu, ldexp(nW, eW - ks), ldexp(nY, eY - ks));
-      eN[cb] = ks + q;
-      fY[cb] = eY - eN[cb];
-      fA[cb] = eW - eN[cb];
+      int eWs[kMaxBand];
+      double nWs[kMaxBand], nus[kMaxBand];
+      int ew = INT_MIN;
+#pragma unroll
+      for (int i = 0; i < kMaxBand; ++i) {
+        if (i < ns) {
+          const int s = U.s_lo + i;
+          const int64_t slot = (int64_t)(s % R) * m + c;
+          eWs[i] = P.eW[slot];
+          nWs[i] = P.nW[slot];
+          nus[i] = P.nu[(int64_t)k * P.Mmax + s];
+          ew = max(ew, eWs[i]);
+        }
+      }
+      const int ks = eY > ew ? eY : ew;
+      // |sum_s [S_ks | T_ks] W_s| <= sum_s nu_ks ||W_s|| (each term <= 2^1000, no overflow)
+      double xb = 0.0;
+#pragma unroll
+      for (int i = 0; i < kMaxBand; ++i)
+        if (i < ns) {
+          xb += nus[i] * ldexp(nWs[i], eWs[i] - ks);
+          g[i] = eWs[i] - ew;
+        }
+      const int q = protect_update(1.0, xb, ldexp(nY, eY - ks));
+      en = ks + q;
+      fy = eY - en;
+      fa = ew - en;
+    }
+    sfY[n] = fy;
+    sfA[n] = fa;
+    seN[n] = en;
+#pragma unroll
+    for (int i = 0; i < kMaxBand; ++i) {
+      sg[i][n] = g[i];
+      if (g[i] != 0) atomicOr(&sgany[i], 1);
     }
   }
-  __syncthreads();   // every segment's old scale is read before any is rewritten
-  if (32 * wave >= hj) return;
 
-  // ---- K loop: acc = [S_kr | T_kr] * W ----
+  // ---- K loop ----
   const double psc = P.ctrl->psc;
-  const int KP = (hr + 3) & ~3;
-  const int KH = KP / 4;          // K steps per half
-  const int KS = 2 * KH;
-  const double* __restrict__ Wp = P.W + (int64_t)j * w_tile_doubles(MB) + (int64_t)(2 * wave) * 64 + lane;
-  const double* __restrict__ pS = P.S + (k0 + li) + (int64_t)(r0 + lk) * P.lds;
-  const double* __restrict__ pT = P.T + (k0 + li) + (int64_t)(r0 + lk) * P.ldt;
-  bool rowok[RB];
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb) rowok[rb] = 16 * rb + li < hk;
+  const int nch = cs[ns];
+  const int arow = tid % MB;           // stage-load row of this thread
+  const int akof = tid / MB;           // first k of this thread (stride TPR)
+  const bool arow_ok = arow < hk;
+  const double* __restrict__ Srow = P.S + (k0 + arow);
+  const double* __restrict__ Trow = P.T + (k0 + arow);
 
-  d4 acc[RB][2];
+  // chunk c -> source index i, lower (T) half or not, first K row of the chunk
+  struct ChunkPos { int i, kb, hs; bool lower; int cc; };
+  auto where = [&](int c) {
+    ChunkPos p{0, 0, 0, false, 0};
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
-
-  double a_cur[RB], b_cur[2], a_nxt[RB], b_nxt[2];
-  auto load = [&](int s, double* av, double* bv) {
-    const bool lower = s >= KH;
-    const int kk = 4 * (lower ? s - KH : s);
-    const bool colok_k = kk + lk < hr;
-    const double* base = lower ? pT + (int64_t)kk * P.ldt : pS + (int64_t)kk * P.lds;
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) av[rb] = (rowok[rb] && colok_k) ? base[16 * rb] : 0.0;
-    bv[0] = Wp[(int64_t)(s * CBM) * 64];
-    bv[1] = Wp[(int64_t)(s * CBM + 1) * 64];
+    for (int i = 1; i < kMaxBand; ++i)
+      if (i < ns && c >= cs[i]) p.i = i;
+    const int s = U.s_lo + p.i;
+    const int e_s = P.edges[s];
+    p.hs = P.edges[s + 1] - e_s;
+    p.cc = c - cs[p.i];
+    const int half = (cs[p.i + 1] - cs[p.i]) / 2;
+    p.lower = p.cc >= half;
+    p.kb = e_s + kChunk * (p.lower ? p.cc - half : p.cc);   // absolute column of S or T
+    return p;
   };
-  load(0, a_cur, b_cur);
-  for (int s = 0; s < KS; ++s) {
-    if (s + 1 < KS) load(s + 1, a_nxt, b_nxt);
+
+  double ra[AK], rw[WV];
+  // Every load is unconditional (a masked element reads a valid address), and the
+  // zero mask is applied only when the chunk is written to LDS, so the loads of the
+  // next chunk stay in flight while the matrix cores work on the current one.
+  const double* safe = P.S;
+  auto fetch = [&](int c) {
+    const ChunkPos p = where(c);
+    const int s = U.s_lo + p.i;
+    const int64_t ld = p.lower ? P.ldt : P.lds;
+    const double* pa = (p.lower ? Trow : Srow) + (int64_t)(p.kb + akof) * ld;
+    const int64_t step = (int64_t)TPR * ld;
+    const int krel = p.kb - P.edges[s] + akof;
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      const double av = a_cur[rb] * psc;
-      acc[rb][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b_cur[0], acc[rb][0], 0, 0, 0);
-      acc[rb][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b_cur[1], acc[rb][1], 0, 0, 0);
+    for (int i = 0; i < AK; ++i) {
+      const bool ok = arow_ok && (krel + TPR * i < p.hs);
+      ra[i] = *(ok ? pa + i * step : safe);
     }
+    const double* wsrc = P.W + ((int64_t)(s % R) * P.Mmax + j) * w_tile_doubles(MB) +
+                         (int64_t)p.cc * kChunk * MB + tid;
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) a_cur[rb] = a_nxt[rb];
-    b_cur[0] = b_nxt[0];
-    b_cur[1] = b_nxt[1];
+    for (int i = 0; i < WV; ++i) rw[i] = wsrc[i * kUpdThreads];
+  };
+  auto stash = [&](int b, int c) {
+    const ChunkPos p = where(c);
+    const int krel = p.kb - P.edges[U.s_lo + p.i] + akof;
+#pragma unroll
+    for (int i = 0; i < AK; ++i) {
+      const bool ok = arow_ok && (krel + TPR * i < p.hs);
+      As[b][(akof + TPR * i) * MB + arow] = ok ? psc * ra[i] : 0.0;
+    }
+    if (sgany[p.i]) {
+#pragma unroll
+      for (int i = 0; i < WV; ++i) {
+        const int n = 16 * ((4 * i + tid / 64) % CBM) + tid % 16;
+        Ws[b][i * kUpdThreads + tid] = ldexp(rw[i], sg[p.i][n]);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < WV; ++i) Ws[b][i * kUpdThreads + tid] = rw[i];
+    }
+  };
+
+  d4 acc[RB][CB];
+#pragma unroll
+  for (int a = 0; a < RB; ++a)
+#pragma unroll
+    for (int b = 0; b < CB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+
+  fetch(0);
+  __syncthreads();   // per-column scales published; old scales all read before any rewrite
+  stash(0, 0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int b = c & 1;
+    if (c + 1 < nch) fetch(c + 1);
+#pragma unroll
+    for (int s = 0; s < kChunk / 4; ++s) {
+      double af[RB], bf[CB];
+#pragma unroll
+      for (int a = 0; a < RB; ++a) af[a] = As[b][(4 * s + lk) * MB + WR * wr + 16 * a + li];
+#pragma unroll
+      for (int q = 0; q < CB; ++q) bf[q] = Ws[b][(s * CBM + CB * wc + q) * 64 + lane];
+      // operands swapped: acc holds (A W)^T blocks, so a lane's four accumulator
+      // registers are one C row of four columns and a wave's store covers whole lines
+#pragma unroll
+      for (int a = 0; a < RB; ++a)
+#pragma unroll
+        for (int q = 0; q < CB; ++q)
+          acc[a][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[q], af[a], acc[a][q], 0, 0, 0);
+    }
+    if (c + 1 < nch) stash(b ^ 1, c + 1);
+    __syncthreads();
   }
 
-  // ---- epilogue: Y <- 2^fY Y - 2^fA acc, new segment norms ----
-  // accumulator layout of the 16x16x4 FP64 instruction: lane holds column lane % 16,
-  // rows lane / 16 + 4 * v for v = 0..3
+  // ---- epilogue: Y <- 2^fY Y - 2^fA acc and the new segment norms ----
+  // block (a, q) of the transposed product: lane holds C row 16 a + lane % 16 (within
+  // the wave's rows) for columns 16 q + lane / 16 + 4 v, v = 0..3
 #pragma unroll
-  for (int cb = 0; cb < 2; ++cb) {
-    const int n = 32 * wave + 16 * cb + li;
-    double cmx = 0.0;
-    if (colok[cb]) {
-      double* zc = P.Z + (k0 + lk) + (int64_t)(c0 + n) * P.ldz;
+  for (int q = 0; q < CB; ++q) {
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
+    for (int v = 0; v < 4; ++v) {
+      const int n = WC * wc + 16 * q + lk + 4 * v;
+      double cmx = 0.0;
+      if (n < hj) {
+        const int fy = sfY[n], fa = sfA[n];
+        double* zc = P.Z + (k0 + WR * wr + li) + (int64_t)(c0 + n) * P.ldz;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = 16 * rb + lk + 4 * v;
+        for (int a = 0; a < RB; ++a) {
+          const int i = WR * wr + 16 * a + li;
           if (i < hk) {
-            const double yo = first ? 0.0 : zc[16 * rb + 4 * v];
-            const double yn = ldexp(yo, fY[cb]) - ldexp(acc[rb][cb][v], fA[cb]);
-            zc[16 * rb + 4 * v] = yn;
+            const double yo = first ? 0.0 : zc[16 * a];
+            const double yn = ldexp(yo, fy) - ldexp(acc[a][q][v], fa);
+            zc[16 * a] = yn;
             cmx = fmax(cmx, fabs(yn));
           }
         }
+      }
+      cmx = fmax(cmx, __shfl_xor(cmx, 1));
+      cmx = fmax(cmx, __shfl_xor(cmx, 2));
+      cmx = fmax(cmx, __shfl_xor(cmx, 4));
+      cmx = fmax(cmx, __shfl_xor(cmx, 8));
+      if (li == 0) red[wr][n] = cmx;
     }
-    cmx = fmax(cmx, __shfl_xor(cmx, 16));
-    cmx = fmax(cmx, __shfl_xor(cmx, 32));
-    if (colok[cb] && lk == 0) {
-      const int64_t c = c0 + n;
-      P.exps[(int64_t)k * m + c] = eN[cb];
-      P.norms[(int64_t)k * m + c] = cmx;
-    }
+  }
+  __syncthreads();
+  if (tid < hj) {
+    const int64_t c = c0 + tid;
+    P.exps[(int64_t)k * m + c] = seN[tid];
+    P.norms[(int64_t)k * m + c] = fmax(red[0][tid], red[1][tid]);
   }
 }
 
 template <int MB>
-static void launch_update_t(const PencilDesc& P, int r, hipStream_t s) {
-  const int64_t tiles = (int64_t)r * (P.Mmax - r);
-  const int64_t grid = (tiles + 7) / 8 * 8;
-  update_kernel<MB><<<(unsigned)grid, MB * 2, 0, s>>>(P, r);
+static void launch_update_t(const PencilDesc& P, const UpdRange& U, hipStream_t s) {
+  // upper bound on the 8 x 8 blocked tile range (the true tile count is on the device)
+  const int64_t nbk = (U.k_hi - U.k_lo + 7) / 8, nbj = (P.Mmax - U.j_lo + 7) / 8;
+  const int64_t grid = nbk * nbj * 64;
+  update_kernel<MB><<<(unsigned)grid, kUpdThreads, 0, s>>>(P, U);
 }
 
-void launch_update(const PencilDesc& P, int r, hipStream_t s) {
-  if (r <= 0) return;
+// Apply source rows [s_lo, s_hi] to target rows [k_lo, k_hi) of every tile column
+// j >= j_lo.  Returns false when there is nothing to launch.
+bool launch_update(const PencilDesc& P, int k_lo, int k_hi, int j_lo, int s_lo, int s_hi, hipStream_t s) {
+  if (k_hi <= k_lo || j_lo >= P.Mmax) return false;
+  const UpdRange U{k_lo, k_hi, j_lo, s_lo, s_hi};
   switch (P.mb) {
-    case 32: launch_update_t<32>(P, r, s); break;
-    case 64: launch_update_t<64>(P, r, s); break;
-    default: launch_update_t<128>(P, r, s); break;
+    case 32: launch_update_t<32>(P, U, s); break;
+    case 64: launch_update_t<64>(P, U, s); break;
+    default: launch_update_t<128>(P, U, s); break;
   }
+  return true;
 }
 
 }  // namespace rgev

@@ -83,57 +83,17 @@ def fill_columns(S: np.ndarray, T: np.ndarray, kind_arr: np.ndarray, seed: int,
             T[j + 1, j + 1] = t
             T[j, j + 1] = 0.0
         if b0 > 0:
-            s = rng.standard_normal(b0)
-            t = rng.standard_normal(b0)
+            cs, ct = S[:b0, j], T[:b0, j]
+            if cs.flags.c_contiguous and ct.flags.c_contiguous:
+                rng.standard_normal(out=cs)     # fills in place without holding the GIL
+                rng.standard_normal(out=ct)
+            else:
+                cs[...] = rng.standard_normal(b0)
+                ct[...] = rng.standard_normal(b0)
             if offscale != 1.0:
-                s *= offscale
-                t *= offscale
-            S[:b0, j] = s
-            T[:b0, j] = t
+                cs *= offscale
+                ct *= offscale
     del m
-
-
-def _fill_worker(job):
-    """Child process: attach the shared buffers and fill a set of column ranges."""
-    from multiprocessing import shared_memory
-    name_s, name_t, ld, m, seed, kind, ranges = job
-    hs = shared_memory.SharedMemory(name=name_s)
-    ht = shared_memory.SharedMemory(name=name_t)
-    try:
-        S = np.ndarray((ld, m), dtype=np.float64, buffer=hs.buf, order="F")[:m]
-        T = np.ndarray((ld, m), dtype=np.float64, buffer=ht.buf, order="F")[:m]
-        kind_arr = block_starts(m, seed)
-        for j0, j1 in ranges:
-            fill_columns(S, T, kind_arr, seed, j0, j1, kind)
-        del S, T
-    finally:
-        hs.close()
-        ht.close()
-    return True
-
-
-def _fill_parallel(Sb, Tb, ld, m, seed, kind, procs):
-    """Fill S and T with `procs` spawned child processes writing into shared memory;
-    the result is identical to the single-process fill (columns are independent)."""
-    import multiprocessing as mp
-    from multiprocessing import shared_memory
-    nbytes = ld * m * 8
-    hs = shared_memory.SharedMemory(create=True, size=nbytes)
-    ht = shared_memory.SharedMemory(create=True, size=nbytes)
-    try:
-        chunk = 128
-        ranges = [(j, min(j + chunk, m)) for j in range(0, m, chunk)]
-        jobs = [(hs.name, ht.name, ld, m, seed, kind, ranges[w::procs]) for w in range(procs)]
-        ctx = mp.get_context("spawn")
-        with ctx.Pool(procs) as pool:
-            assert all(pool.map(_fill_worker, jobs))
-        Sb[...] = np.ndarray((ld, m), dtype=np.float64, buffer=hs.buf, order="F")
-        Tb[...] = np.ndarray((ld, m), dtype=np.float64, buffer=ht.buf, order="F")
-    finally:
-        hs.close()
-        hs.unlink()
-        ht.close()
-        ht.unlink()
 
 
 def schur_pencil(m: int, seed: int, kind: str = "normal", ld: int | None = None,
@@ -142,7 +102,8 @@ def schur_pencil(m: int, seed: int, kind: str = "normal", ld: int | None = None,
 
     If ``ld`` > m the arrays are views of column-major (ld, m) buffers, so the
     leading dimension seen through ``S.strides`` is ``ld``.  ``threads`` > 1 fills
-    the columns in that many child processes (same values).
+    the columns from that many threads (same values: every column has its own
+    stream, and the in-place normal fills run without the interpreter lock).
     """
     if kind not in KINDS:
         raise ValueError(f"kind must be one of {KINDS}")
@@ -153,10 +114,14 @@ def schur_pencil(m: int, seed: int, kind: str = "normal", ld: int | None = None,
     Tb = np.zeros((ld, m), dtype=np.float64, order="F")
     S, T = Sb[:m], Tb[:m]
     kind_arr = block_starts(m, seed)
-    if threads <= 1 or m < 4096:
+    if threads <= 1 or m < 2048:
         fill_columns(S, T, kind_arr, seed, 0, m, kind)
     else:
-        _fill_parallel(Sb, Tb, ld, m, seed, kind, int(threads))
+        from concurrent.futures import ThreadPoolExecutor
+        chunk = 256
+        ranges = [(j, min(j + chunk, m)) for j in range(0, m, chunk)]
+        with ThreadPoolExecutor(max_workers=int(threads)) as ex:
+            list(ex.map(lambda r: fill_columns(S, T, kind_arr, seed, r[0], r[1], kind), ranges))
     return S, T, kind_arr
 
 

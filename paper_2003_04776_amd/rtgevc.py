@@ -34,7 +34,8 @@ class RtgevcError(RuntimeError):
 
 
 class Opts(ctypes.Structure):
-    _fields_ = [("mb", ctypes.c_int32), ("normalize", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+    _fields_ = [("mb", ctypes.c_int32), ("normalize", ctypes.c_int32), ("band", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 _lib = None
@@ -72,15 +73,16 @@ EXPORTED = ("rtgevc_workspace_size", "rtgevc", "rtgevc_eigvals", "rtgevc_timed",
 TIMED_NSTATS = 12
 
 
-def make_opts(mb: int = 0, normalize: bool = True) -> Opts:
+def make_opts(mb: int = 0, normalize: bool = True, band: int = 0) -> Opts:
     o = Opts()
     o.mb = int(mb)
     o.normalize = 1 if normalize else 0
+    o.band = int(band)
     return o
 
 
-def workspace_size(m: int, mb: int = 0, normalize: bool = True) -> int:
-    o = make_opts(mb, normalize)
+def workspace_size(m: int, mb: int = 0, normalize: bool = True, band: int = 0) -> int:
+    o = make_opts(mb, normalize, band)
     return int(load().rtgevc_workspace_size(int(m), ctypes.byref(o)))
 
 
@@ -138,10 +140,10 @@ class Solver:
     """Holds a workspace for repeated calls of one order m (the workspace is the only
     allocation, made once by torch; the library itself allocates nothing)."""
 
-    def __init__(self, m: int, mb: int = 0, normalize: bool = True, device="cuda"):
+    def __init__(self, m: int, mb: int = 0, normalize: bool = True, band: int = 0, device="cuda"):
         import torch
         self.m = int(m)
-        self.opts = make_opts(mb, normalize)
+        self.opts = make_opts(mb, normalize, band)
         self.nbytes = int(load().rtgevc_workspace_size(self.m, ctypes.byref(self.opts)))
         self.work = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
         self.device = device
@@ -198,6 +200,7 @@ class Solver:
         return out[0][:m], out[1][:m], out[2][:m], info
 
 
-def tgevc(S, T, select=None, normalize: bool = True, mb: int = 0, stream=None) -> Result:
+def tgevc(S, T, select=None, normalize: bool = True, mb: int = 0, band: int = 0, stream=None) -> Result:
     """All (or the selected) right eigenvectors of the Schur pencil (S, T)."""
-    return Solver(S.shape[0], mb=mb, normalize=normalize, device=S.device).run(S, T, select, stream=stream)
+    return Solver(S.shape[0], mb=mb, normalize=normalize, band=band, device=S.device).run(
+        S, T, select, stream=stream)

@@ -35,13 +35,13 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def run_gpu(S, T, mb=0, select=None, normalize=True, ld=None):
+def run_gpu(S, T, mb=0, select=None, normalize=True, ld=None, band=0):
     torch = _torch()
     from paper_2003_04776_amd import rtgevc as rt
     m = S.shape[0]
     Sd = rt.colmajor_to_device(S, ld=ld)
     Td = rt.colmajor_to_device(T, ld=ld)
-    solver = rt.Solver(m, mb=mb, normalize=normalize)
+    solver = rt.Solver(m, mb=mb, normalize=normalize, band=band)
     res = solver.run(Sd, Td, select=select)
     torch.cuda.synchronize()
     return res.Z.cpu().numpy(), res.scales.cpu().numpy(), int(res.info.item())
@@ -83,6 +83,22 @@ def test_parity_small(m, mb, seed):
     ar, ai, be, _ = oracle.eigvals(S, T)
     eta = residuals(S, T, Zg, ar, ai, be)
     assert max(eta.values()) <= 64 * m * U
+
+
+@pytest.mark.parametrize("m,mb,band,seed", [(300, 32, 1, 30), (301, 32, 2, 31), (333, 32, 3, 32),
+                                             (450, 32, 4, 33), (1000, 64, 3, 34), (1100, 128, 4, 35),
+                                             (700, 64, 1, 36)])
+def test_parity_bands(m, mb, band, seed):
+    """Every band size applies the same updates (grouped differently): same eigenvectors."""
+    _say(f"[band] m={m} mb={mb} band={band} seed={seed}")
+    S, T, blk = pencils.schur_pencil(m, seed)
+    Zg, sc, info = run_gpu(S, T, mb=mb, band=band)
+    assert info == 0
+    worst, errs, nill = compare(S, T, Zg)
+    assert worst <= TOL
+    Zs, scs, _ = run_gpu(pencils.schur_pencil(m, seed + 100, "stress")[0],
+                         pencils.schur_pencil(m, seed + 100, "stress")[1], mb=mb, band=band, normalize=False)
+    assert np.isfinite(Zs).all() and (scs >= 0).all()
 
 
 @pytest.mark.parametrize("m,mb,seed", [(60, 32, 200), (300, 64, 201), (521, 128, 202)])
