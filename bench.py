@@ -141,7 +141,7 @@ def main():
         "config": {
             "workload": f"all right eigenvectors of a real Schur pencil, m={m}, robust FP64 "
                         f"(power-of-two scale exponents), normalised output",
-            "m": m, "mb": int(st0["mb"]), "band": int(solver.opts.band) or 2, "tiles": int(st0["M"]),
+            "m": m, "mb": int(st0["mb"]), "band": int(solver.opts.band) or 4, "tiles": int(st0["M"]),
             "seed": args.seed,
             "generator": args.kind, "flops_per_step": F,
         },

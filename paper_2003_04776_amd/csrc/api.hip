@@ -32,7 +32,7 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-int resolve_band(const rtgevc_opts* o) { return (o && o->band) ? o->band : 2; }
+int resolve_band(const rtgevc_opts* o) { return (o && o->band) ? o->band : 4; }
 
 int resolve_mb(int64_t m, const rtgevc_opts* o) {
   if (o && o->mb) return o->mb;
@@ -78,44 +78,103 @@ size_t carve(PencilDesc& P, char* base, int64_t m, int mb, int band) {
   P.nu = c.take<double>(base, (size_t)Mmax * Mmax);
   P.exps = c.take<int32_t>(base, (size_t)Mmax * m);
   P.norms = c.take<double>(base, (size_t)Mmax * m);
-  P.W = c.take<double>(base, (size_t)band * Mmax * w_tile_doubles(mb));
-  P.eW = c.take<int32_t>(base, (size_t)band * m);
-  P.nW = c.take<double>(base, (size_t)band * m);
+  P.W = c.take<double>(base, (size_t)2 * band * Mmax * w_tile_doubles(mb));
+  P.eW = c.take<int32_t>(base, (size_t)2 * band * m);
+  P.nW = c.take<double>(base, (size_t)2 * band * m);
   P.mb = mb;
   P.Mmax = Mmax;
   P.band = band;
+  P.wslots = 2 * band;
   return c.off;
 }
 
 int hip_code(hipError_t e) { return e == hipSuccess ? 0 : -1000 - (int)e; }
 
-// The blocked back-substitution for tile rows [0, rows), bottom band first.  Bands are
-// the rows [R b, R b + R - 1]; inside a band the rows are solved from the bottom up,
-// each followed by the small update of the band rows above it; then one update applies
-// the whole band to every tile row above the band.  mark(kind) is called before and
-// after each launch (kind 1 = solve, 2 = update); rows at or beyond the device's tile
-// count M are no-ops in the kernels.
+// Per-device side stream and events for the look-ahead schedule, created once (default
+// priority) and kept until the process ends.  The enqueue of one call holds g_aux_mu, so
+// calls from several host threads do not interleave their event records.
+struct Aux {
+  hipStream_t side = nullptr;
+  hipEvent_t evC = nullptr, evJ = nullptr, evU[2] = {nullptr, nullptr};
+  bool ok = false;
+};
+std::mutex g_aux_mu;
+Aux g_aux[64];
+
+hipError_t get_aux(Aux** out) {
+  int dev = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return err;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  Aux& a = g_aux[dev];
+  if (!a.ok) {
+    err = hipStreamCreateWithFlags(&a.side, hipStreamNonBlocking);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&a.evC, hipEventDisableTiming);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&a.evJ, hipEventDisableTiming);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&a.evU[0], hipEventDisableTiming);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&a.evU[1], hipEventDisableTiming);
+    if (err != hipSuccess) return err;
+    a.ok = true;
+  }
+  *out = &a;
+  return hipSuccess;
+}
+
+// The blocked back-substitution for tile rows [0, rows), bottom band first (Algorithm 1
+// with the tasks grouped into bands of R tile rows, the rows [R b, R b + R - 1]):
+//   C(b)   on the caller's stream: the band's rows from the bottom up, each solve
+//          followed by the small update of the band rows above it;
+//   U1(b)  on the caller's stream: the band applied to the next band's rows;
+//   U2(b)  on the side stream: the band applied to every row above the next band.
+// C(b-1) only needs U1(b) and U2(b+1), so it overlaps U2(b) (look-ahead).  C(b) waits
+// for U2(b+2), which last wrote its rows and read the W slots it is about to reuse.
+// mark(kind, before, stream) brackets each launch (kind 1 = solve, 2 = update); rows at
+// or beyond the device's tile count M are no-ops in the kernels.
 template <class Mark>
-void enqueue_rows(const PencilDesc& P, int rows, hipStream_t s, Mark&& mark) {
+hipError_t enqueue_rows(const PencilDesc& P, int rows, hipStream_t sa, Aux& ax, Mark&& mark) {
   const int R = P.band;
-  for (int b = (rows - 1) / R; b >= 0; --b) {
+  hipStream_t sb = ax.side;
+  hipError_t err = hipSuccess;
+  auto chk = [&](hipError_t e) {
+    if (err == hipSuccess) err = e;
+  };
+  // the side stream starts after everything already queued on the caller's stream
+  chk(hipEventRecord(ax.evC, sa));
+  chk(hipStreamWaitEvent(sb, ax.evC, 0));
+  chk(hipEventRecord(ax.evU[0], sb));
+  chk(hipEventRecord(ax.evU[1], sb));
+  for (int b = (rows - 1) / R; b >= 0 && err == hipSuccess; --b) {
     const int r_lo = R * b, r_hi = R * b + R - 1;
+    chk(hipStreamWaitEvent(sa, ax.evU[b & 1], 0));
     for (int i = (r_hi < rows ? r_hi : rows - 1); i >= r_lo; --i) {
-      mark(1, true);
-      launch_solve(P, i, s);
-      mark(1, false);
+      mark(1, true, sa);
+      launch_solve(P, i, sa);
+      mark(1, false, sa);
       if (i > r_lo) {
-        mark(2, true);
-        launch_update(P, r_lo, i, i, i, i, s);
-        mark(2, false);
+        mark(2, true, sa);
+        launch_update(P, r_lo, i, i, i, i, sa);
+        mark(2, false, sa);
       }
     }
     if (r_lo > 0) {
-      mark(2, true);
-      launch_update(P, 0, r_lo, r_lo, r_lo, r_hi, s);
-      mark(2, false);
+      chk(hipEventRecord(ax.evC, sa));
+      const int nlo = r_lo > R ? r_lo - R : 0;
+      mark(2, true, sa);
+      launch_update(P, nlo, r_lo, r_lo, r_lo, r_hi, sa);
+      mark(2, false, sa);
+      if (nlo > 0) {
+        chk(hipStreamWaitEvent(sb, ax.evC, 0));
+        mark(2, true, sb);
+        launch_update(P, 0, nlo, r_lo, r_lo, r_hi, sb);
+        mark(2, false, sb);
+        chk(hipEventRecord(ax.evU[b & 1], sb));
+      }
     }
   }
+  // join the side stream back into the caller's stream
+  chk(hipEventRecord(ax.evJ, sb));
+  chk(hipStreamWaitEvent(sa, ax.evJ, 0));
+  return err;
 }
 
 // Events of the timed entry point, created once per device and reused by later calls
@@ -196,10 +255,15 @@ int rtgevc(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt
   if (m == 0) return 0;
   hipStream_t s = static_cast<hipStream_t>(stream);
   PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts);
+  std::lock_guard<std::mutex> lock(g_aux_mu);
+  Aux* ax = nullptr;
+  hipError_t err = get_aux(&ax);
+  if (err != hipSuccess) return hip_code(err);
   launch_preprocess(P, s);
-  enqueue_rows(P, P.Mmax, s, [](int, bool) {});
+  err = enqueue_rows(P, P.Mmax, s, *ax, [](int, bool, hipStream_t) {});
   launch_consolidate(P, s);
-  return hip_code(hipGetLastError());
+  if (err == hipSuccess) err = hipGetLastError();
+  return hip_code(err);
 }
 
 int rtgevc_eigvals(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt, double* alpha_re,
@@ -230,19 +294,24 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
   if (m == 0) return 0;
   hipStream_t s = static_cast<hipStream_t>(stream);
   PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts);
-  // events bracket every launch on the caller's stream
-  const int nev = 2 * (3 * P.Mmax + 4);
+  // events bracket every launch on the stream it runs on
+  const int nev = 2 * (3 * P.Mmax + 8);
   std::lock_guard<std::mutex> lock(g_event_mu);
+  std::lock_guard<std::mutex> lock2(g_aux_mu);
   hipEvent_t* ev = nullptr;
   int used = 0;
   hipError_t err = get_events(nev, &ev);
   if (err != hipSuccess) return hip_code(err);
-  auto mark = [&]() {
-    const hipError_t e = hipEventRecord(ev[used++], s);
+  Aux* ax = nullptr;
+  err = get_aux(&ax);
+  if (err != hipSuccess) return hip_code(err);
+  auto mark_on = [&](hipStream_t st) {
+    const hipError_t e = hipEventRecord(ev[used++], st);
     if (err == hipSuccess) err = e;
   };
+  auto mark = [&]() { mark_on(s); };
   struct Span { int cls, e0, e1; };
-  Span* spans = new Span[3 * P.Mmax + 4];
+  Span* spans = new Span[3 * P.Mmax + 8];
   int nsp = 0;
   mark();
   launch_preprocess(P, s);
@@ -251,14 +320,16 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
   int32_t M = 0;
   err = hipMemcpyAsync(&M, &P.ctrl->M, sizeof(int32_t), hipMemcpyDeviceToHost, s);
   if (err == hipSuccess) err = hipStreamSynchronize(s);
-  if (err == hipSuccess)
-    enqueue_rows(P, M, s, [&](int kind, bool before) {
-      mark();
+  if (err == hipSuccess) {
+    const hipError_t e = enqueue_rows(P, M, s, *ax, [&](int kind, bool before, hipStream_t st) {
+      mark_on(st);
       if (!before) {
         spans[nsp] = Span{kind, used - 2, used - 1};
         ++nsp;
       }
     });
+    if (err == hipSuccess) err = e;
+  }
   const int c0 = used;
   mark();
   launch_consolidate(P, s);

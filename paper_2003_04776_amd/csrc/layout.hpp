@@ -14,10 +14,11 @@
 //   nu[Mmax*Mmax]      nu[k*Mmax + r] >= max_i sum_l |S_il| + |T_il| over tile pair (k, r)
 //   exps[Mmax*m]       exponent of segment (tile row k, column c): value = 2^e * mantissa
 //   norms[Mmax*m]      infinity norm (upper bound) of that segment's mantissa
-//   W[R * Mmax * WS]   right-updated tiles of the last R solved source rows (Algorithm 2),
-//                      slot (r % R) * Mmax + j, packed in the operand order of the FP64
-//                      matrix instruction
-//   eW, nW [R * m]     exponent and norm bound of W per source-row slot and column
+//   W[2R * Mmax * WS]  right-updated tiles of the last 2R solved source rows (Algorithm 2),
+//                      slot (r % 2R) * Mmax + j (two bands, so a band's solves never
+//                      overwrite what the previous band's update still reads), packed in
+//                      the operand order of the FP64 matrix instruction
+//   eW, nW [2R * m]    exponent and norm bound of W per source-row slot and column
 #pragma once
 #include <stddef.h>
 #include <stdint.h>
@@ -61,6 +62,8 @@ struct PencilDesc {
   int32_t Mmax;
   int32_t normalize;
   int32_t band;       // R: tile rows per update band
+  int32_t wslots;     // 2R source-row slots of W, eW, nW
+  int32_t pad2;
 };
 
 constexpr int kMaxBand = 8;

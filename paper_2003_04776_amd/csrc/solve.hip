@@ -31,6 +31,13 @@ __device__ __forceinline__ Cx cdivx(Cx x, Cx y) {
 }
 __device__ __forceinline__ Cx cscl(Cx x, int q) { return q ? Cx{ldexp(x.r, -q), ldexp(x.i, -q)} : x; }
 
+// When a protection has to scale, the solves scale by 2^128 more than the least
+// exponent: any power of two that meets the bound represents the same vector, and the
+// head room makes the next scaling (and its pass over the solved rows) rare even when
+// the eigenvector keeps growing row after row.
+constexpr int kScaleMargin = 128;
+__device__ __forceinline__ int with_margin(int q) { return q > 0 ? q + kScaleMargin : 0; }
+
 // pivot threshold: u times the size of the terms of beta S_qq - alpha T_qq
 __device__ __forceinline__ double local_smin(double be, double aabs, double smax, double tmax) {
   const double s = kUnitRoundoff * (be * smax + aabs * tmax);
@@ -47,73 +54,79 @@ __device__ __forceinline__ Cx solve1(double a, double b, double be, double s, do
     flags |= kInfoPerturbed;
   }
   // |y/d|_1 <= 2 |y|_1 / |d|_1
-  const int q = protect_division(cn1(y), 0.5 * cn1(d));
+  const int q = with_margin(protect_division(cn1(y), 0.5 * cn1(d)));
   qs += q;
   return cdivx(cscl(y, q), d);
 }
 
 // 2x2 block: Gaussian elimination with complete pivoting on |.|_1, every division
-// and update protected.  y[0], y[1] are the block's rows; the solution replaces them.
-__device__ __forceinline__ void solve2(double a, double b, double be, const double s[2][2],
-                                       const double t[2][2], Cx y[2], int& qs, int& flags) {
-  Cx C[2][2];
-  double smax = 0.0, tmax = 0.0;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const double tv = (i > j) ? 0.0 : t[i][j];
-      C[i][j] = cx(be * s[i][j] - a * tv, -b * tv);
-      smax = fmax(smax, fabs(s[i][j]));
-      tmax = fmax(tmax, fabs(tv));
-    }
+// and update protected.  y0, y1 are the block's rows; the solution replaces them.
+// (Written with selects only, so nothing is indexed dynamically.)
+__device__ __forceinline__ void solve2(double a, double b, double be, double s00, double s01, double s10,
+                                       double s11, double t00, double t01, double t11, Cx& y0, Cx& y1,
+                                       int& qs, int& flags) {
+  const Cx C00 = cx(be * s00 - a * t00, -b * t00);
+  const Cx C01 = cx(be * s01 - a * t01, -b * t01);
+  const Cx C10 = cx(be * s10, 0.0);
+  const Cx C11 = cx(be * s11 - a * t11, -b * t11);
+  const double smax = fmax(fmax(fabs(s00), fabs(s01)), fmax(fabs(s10), fabs(s11)));
+  const double tmax = fmax(fmax(fabs(t00), fabs(t01)), fabs(t11));
   const double smin = local_smin(be, fabs(a) + fabs(b), smax, tmax);
+  const double v00 = cn1(C00), v01 = cn1(C01), v10 = cn1(C10), v11 = cn1(C11);
+  // pivot (ip, jp): the entry of largest |.|_1
   int ip = 0, jp = 0;
-  double best = -1.0;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const double v = cn1(C[i][j]);
-      if (v > best) { best = v; ip = i; jp = j; }
-    }
+  double best = v00;
+  if (v01 > best) { best = v01; ip = 0; jp = 1; }
+  if (v10 > best) { best = v10; ip = 1; jp = 0; }
+  if (v11 > best) { best = v11; ip = 1; jp = 1; }
+  Cx u11, u12, c21, c22;
   if (best < smin) {
-    C[0][0] = cx(smin, 0.0); C[0][1] = cx(0.0, 0.0);
-    C[1][0] = cx(0.0, 0.0); C[1][1] = cx(smin, 0.0);
+    u11 = cx(smin, 0.0); u12 = cx(0.0, 0.0); c21 = cx(0.0, 0.0); c22 = cx(smin, 0.0);
     ip = 0; jp = 0;
     flags |= kInfoPerturbed;
+  } else {
+    // rows/columns permuted so the pivot is (0, 0): u11 = C[ip][jp], u12 = C[ip][1-jp],
+    // c21 = C[1-ip][jp], c22 = C[1-ip][1-jp]
+    const Cx r0a = ip ? C10 : C00, r0b = ip ? C11 : C01;   // pivot row
+    const Cx r1a = ip ? C00 : C10, r1b = ip ? C01 : C11;   // other row
+    u11 = jp ? r0b : r0a;
+    u12 = jp ? r0a : r0b;
+    c21 = jp ? r1b : r1a;
+    c22 = jp ? r1a : r1b;
   }
-  const int io = 1 - ip, jo = 1 - jp;
-  const Cx u11 = C[ip][jp], u12 = C[ip][jo];
-  const Cx l21 = cdivx(C[io][jp], u11);
-  Cx u22 = csub(C[io][jo], cmul(l21, u12));
+  const Cx l21 = cdivx(c21, u11);
+  Cx u22 = csub(c22, cmul(l21, u12));
   if (cn1(u22) < smin) {
     u22 = cx(smin, 0.0);
     flags |= kInfoPerturbed;
   }
-  Cx y1 = y[ip], y2 = y[io];
-  int q = protect_update(cn1(l21), cn1(y1), cn1(y2));
-  y1 = cscl(y1, q); y2 = cscl(y2, q); qs += q;
-  Cx r2 = csub(y2, cmul(l21, y1));
-  q = protect_division(cn1(r2), 0.5 * cn1(u22));
-  r2 = cscl(r2, q); y1 = cscl(y1, q); qs += q;
+  Cx ya = ip ? y1 : y0, yb = ip ? y0 : y1;
+  int q = with_margin(protect_update(cn1(l21), cn1(ya), cn1(yb)));
+  ya = cscl(ya, q); yb = cscl(yb, q); qs += q;
+  Cx r2 = csub(yb, cmul(l21, ya));
+  q = with_margin(protect_division(cn1(r2), 0.5 * cn1(u22)));
+  r2 = cscl(r2, q); ya = cscl(ya, q); qs += q;
   Cx w2 = cdivx(r2, u22);
-  q = protect_update(cn1(u12), cn1(w2), cn1(y1));
-  w2 = cscl(w2, q); y1 = cscl(y1, q); qs += q;
-  Cx n1 = csub(y1, cmul(u12, w2));
-  q = protect_division(cn1(n1), 0.5 * cn1(u11));
+  q = with_margin(protect_update(cn1(u12), cn1(w2), cn1(ya)));
+  w2 = cscl(w2, q); ya = cscl(ya, q); qs += q;
+  Cx n1 = csub(ya, cmul(u12, w2));
+  q = with_margin(protect_division(cn1(n1), 0.5 * cn1(u11)));
   n1 = cscl(n1, q); w2 = cscl(w2, q); qs += q;
   const Cx w1 = cdivx(n1, u11);
-  y[jp] = w1;
-  y[jo] = w2;
+  // unknown jp gets w1, the other gets w2
+  y0 = jp ? w2 : w1;
+  y1 = jp ? w1 : w2;
 }
 
 template <int MB>
 __global__ __launch_bounds__(MB) void solve_kernel(PencilDesc P, int r) {
   constexpr int LDY = MB + 1;   // odd stride: row and column sweeps are both conflict-free
+  constexpr int PW = 4;         // columns per staged panel of S_rr and T_rr
   __shared__ double Y[MB * LDY];
-  __shared__ double stS[2][2][MB];   // [buffer][slot: 0 = column q, 1 = column q-1][row]
-  __shared__ double stT[2][2][MB];
+  __shared__ double stS[2][PW][MB];   // [panel slot][column in panel][row]
+  __shared__ double stT[2][PW][MB];
+  __shared__ double tcnS[MB], tcnT[MB];
+  __shared__ int8_t tblk[MB];
   __shared__ double cmax[MB];
   __shared__ double colA[MB], colB[MB], colBe[MB];
   __shared__ int colG[MB];
@@ -151,48 +164,69 @@ __global__ __launch_bounds__(MB) void solve_kernel(PencilDesc P, int r) {
   double ybound = 0.0;
   int flags = 0;
 
-  // ---- right-hand side Y_rj (zero for the tip tile) ----
+  // ---- structure and column norms of the diagonal tile, right-hand side Y_rj ----
+  if (lc < hr) {
+    tblk[lc] = P.blk[r0 + lc];
+    tcnS[lc] = P.cnS[r0 + lc];
+    tcnT[lc] = P.cnT[r0 + lc];
+  }
   for (int idx = lc; idx < MB * LDY; idx += MB) Y[idx] = 0.0;
   __syncthreads();
   if (!tip) {
-    for (int idx = lc; idx < hr * hj; idx += MB) {
-      const int i = idx % hr, col = idx / hr;
-      Y[i * LDY + col] = P.Z[(r0 + i) + (c0 + col) * ldz];
+    // thread lc reads row lc of every column (coalesced down the columns), 16 loads in flight
+    if (lc < hr) {
+      const double* zrow = P.Z + (r0 + lc) + (int64_t)c0 * ldz;
+      for (int col0 = 0; col0 < hj; col0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) v[t] = (col0 + t < hj) ? zrow[(int64_t)(col0 + t) * ldz] : 0.0;
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+          if (col0 + t < hj) Y[lc * LDY + col0 + t] = v[t];
+      }
     }
     if (inrange) {
       e = P.exps[(int64_t)r * m + c];
       ybound = P.norms[(int64_t)r * m + c] + (kind != 0 ? P.norms[(int64_t)r * m + c0 + partner] : 0.0);
     }
   }
-  // ---- stage the first block's two columns ----
-  {
-    const int qa = hr - 1, qb = hr - 2;
-    if (lc < hr) {
-      stS[0][0][lc] = psc * S[(r0 + lc) + (r0 + qa) * lds];
-      stT[0][0][lc] = psc * T[(r0 + lc) + (r0 + qa) * ldt];
-      stS[0][1][lc] = qb >= 0 ? psc * S[(r0 + lc) + (r0 + qb) * lds] : 0.0;
-      stT[0][1][lc] = qb >= 0 ? psc * T[(r0 + lc) + (r0 + qb) * ldt] : 0.0;
+
+  // ---- panels of S_rr, T_rr: panel p = columns [PW p, PW p + PW), slot p % 2 ----
+  double pfS[PW], pfT[PW];
+  auto panel_fetch = [&](int p) {
+#pragma unroll
+    for (int t = 0; t < PW; ++t) {
+      const int col = PW * p + t;
+      const bool ok = p >= 0 && col < hr && lc < hr;
+      pfS[t] = ok ? S[(r0 + lc) + (r0 + col) * lds] : 0.0;
+      pfT[t] = ok ? T[(r0 + lc) + (r0 + col) * ldt] : 0.0;
     }
+  };
+  auto panel_publish = [&](int p) {
+#pragma unroll
+    for (int t = 0; t < PW; ++t) {
+      stS[p & 1][t][lc] = psc * pfS[t];
+      stT[p & 1][t][lc] = psc * pfT[t];
+    }
+  };
+  auto SC = [&](int col) -> const double* { return stS[(col / PW) & 1][col % PW]; };
+  auto TC = [&](int col) -> const double* { return stT[(col / PW) & 1][col % PW]; };
+
+  int plow = (hr - 1) / PW;   // lowest-numbered panel resident in LDS
+  panel_fetch(plow);
+  panel_publish(plow);
+  panel_fetch(plow - 1);
+  if ((tblk[hr - 1] == 2 ? hr - 2 : hr - 1) < PW * plow) {   // the first block reaches below
+    --plow;
+    panel_publish(plow);
+    panel_fetch(plow - 1);
   }
   __syncthreads();
 
-  int buf = 0;
   int q = hr - 1;
   while (q >= 0) {
-    const int q0 = (P.blk[r0 + q] == 2) ? q - 1 : q;
+    const int q0 = (tblk[q] == 2) ? q - 1 : q;
     const int nb = q - q0 + 1;
-    const int s0 = nb - 1;   // stage slot of column q0
-    // prefetch the next block's two columns
-    const int qn = q0 - 1;
-    double pS0 = 0.0, pT0 = 0.0, pS1 = 0.0, pT1 = 0.0;
-    if (qn >= 0 && lc < hr) {
-      pS0 = S[(r0 + lc) + (r0 + qn) * lds];
-      pT0 = T[(r0 + lc) + (r0 + qn) * ldt];
-      if (qn >= 1) {
-        pS1 = S[(r0 + lc) + (r0 + qn - 1) * lds];
-        pT1 = T[(r0 + lc) + (r0 + qn - 1) * ldt];
-      }
-    }
     // ---- phase A: small solve of the block (rows q0..q) ----
     const bool work = selected && !(tip && q0 > pc);
     Cx z0 = cx(0.0, 0.0), z1 = cx(0.0, 0.0);
@@ -209,33 +243,31 @@ __global__ __launch_bounds__(MB) void solve_kernel(PencilDesc P, int r) {
           z0 = cx(1.0, 0.0);
         } else {
           // second row of the singular block beta S_b - alpha T_b gives z_p for z_{p+1} = 1
-          const double s21 = stS[buf][1][q], s22 = stS[buf][0][q], t22 = stT[buf][0][q];
+          const double s21 = SC(q0)[q], s22 = SC(q)[q], t22 = TC(q)[q];
           double m21 = be * s21;
           const Cx nn = cx(-(be * s22 - a * t22), b * t22);
           const double smin = local_smin(be, aabs, fmax(fabs(s21), fabs(s22)), fabs(t22));
           if (fabs(m21) < smin) { m21 = smin; flags |= kInfoPerturbed; }
-          const int qd = protect_division(cn1(nn), fabs(m21));
+          const int qd = with_margin(protect_division(cn1(nn), fabs(m21)));
           const Cx ns = cscl(nn, qd);
           z0 = cx(ns.r / m21, ns.i / m21);
           z1 = cx(ldexp(1.0, -qd), 0.0);
           qs += qd;
         }
       } else if (nb == 1) {
-        z0 = solve1(a, b, be, stS[buf][0][q], stT[buf][0][q], yv(q), qs, flags);
+        z0 = solve1(a, b, be, SC(q)[q], TC(q)[q], yv(q), qs, flags);
       } else {
-        const double s2[2][2] = {{stS[buf][1][q0], stS[buf][0][q0]}, {stS[buf][1][q], stS[buf][0][q]}};
-        const double t2[2][2] = {{stT[buf][1][q0], stT[buf][0][q0]}, {0.0, stT[buf][0][q]}};
-        Cx yy[2] = {yv(q0), yv(q)};
-        solve2(a, b, be, s2, t2, yy, qs, flags);
-        z0 = yy[0];
-        z1 = yy[1];
+        z0 = yv(q0);
+        z1 = yv(q);
+        solve2(a, b, be, SC(q0)[q0], SC(q)[q0], SC(q0)[q], SC(q)[q], TC(q0)[q0], TC(q)[q0], TC(q)[q],
+               z0, z1, qs, flags);
       }
       if (q0 > 0) {
         // ProtectUpdate for y[0:q0] -= (beta S - alpha T)[0:q0, q0..q] z
-        cn = be * P.cnS[r0 + q0] + aabs * P.cnT[r0 + q0];
-        if (nb == 2) cn += be * P.cnS[r0 + q] + aabs * P.cnT[r0 + q];
+        cn = be * tcnS[q0] + aabs * tcnT[q0];
+        if (nb == 2) cn += be * tcnS[q] + aabs * tcnT[q];
         const double zn = fmax(cn1(z0), cn1(z1));
-        const int qu = protect_update(cn, zn, ldexp(ybound, -qs));
+        const int qu = with_margin(protect_update(cn, zn, ldexp(ybound, -qs)));
         z0 = cscl(z0, qu);
         z1 = cscl(z1, qu);
         qs += qu;
@@ -243,8 +275,16 @@ __global__ __launch_bounds__(MB) void solve_kernel(PencilDesc P, int r) {
     }
     __syncthreads();   // every thread has read rows q0..q before any is overwritten
     if (work) {
+      // the scale applies to the whole segment: the solved rows below now, the rows
+      // above inside the update loop (f is an exact power of two)
+      double f = 1.0;
       if (qs > 0) {
-        for (int i = 0; i < hr; ++i) Y[i * LDY + lc] = ldexp(Y[i * LDY + lc], -qs);
+        for (int i = q + 1; i < hr; ++i) Y[i * LDY + lc] = ldexp(Y[i * LDY + lc], -qs);
+        if (qs <= 1000) {
+          f = ldexp(1.0, -qs);
+        } else {
+          for (int i = 0; i < q0; ++i) Y[i * LDY + lc] = ldexp(Y[i * LDY + lc], -qs);
+        }
         e += qs;
         ybound = ldexp(ybound, -qs);
       }
@@ -255,39 +295,39 @@ __global__ __launch_bounds__(MB) void solve_kernel(PencilDesc P, int r) {
         // u = beta z, v = alpha z (own real or imaginary part)
         const double u0 = be * (im ? z0.i : z0.r);
         const double v0 = im ? (b * z0.r + a * z0.i) : (a * z0.r - b * z0.i);
-        const double* sc0 = stS[buf][s0];
-        const double* tc0 = stT[buf][s0];
+        const double* sc0 = SC(q0);
+        const double* tc0 = TC(q0);
         if (nb == 1) {
 #pragma unroll 4
           for (int i = 0; i < q0; ++i) {
-            double y = Y[i * LDY + lc];
-            y -= sc0[i] * u0 - tc0[i] * v0;
-            Y[i * LDY + lc] = y;
+            const double y = Y[i * LDY + lc];
+            Y[i * LDY + lc] = y * f - (sc0[i] * u0 - tc0[i] * v0);
           }
         } else {
           const double u1 = be * (im ? z1.i : z1.r);
           const double v1 = im ? (b * z1.r + a * z1.i) : (a * z1.r - b * z1.i);
-          const double* sc1 = stS[buf][0];
-          const double* tc1 = stT[buf][0];
+          const double* sc1 = SC(q);
+          const double* tc1 = TC(q);
 #pragma unroll 4
           for (int i = 0; i < q0; ++i) {
-            double y = Y[i * LDY + lc];
-            y -= (sc0[i] * u0 - tc0[i] * v0) + (sc1[i] * u1 - tc1[i] * v1);
-            Y[i * LDY + lc] = y;
+            const double y = Y[i * LDY + lc];
+            Y[i * LDY + lc] = y * f - ((sc0[i] * u0 - tc0[i] * v0) + (sc1[i] * u1 - tc1[i] * v1));
           }
         }
         ybound += cn * fmax(cn1(z0), cn1(z1));
       }
     }
-    // publish the prefetched columns for the next block
-    if (qn >= 0 && lc < hr) {
-      stS[buf ^ 1][0][lc] = psc * pS0;
-      stT[buf ^ 1][0][lc] = psc * pT0;
-      stS[buf ^ 1][1][lc] = psc * pS1;
-      stT[buf ^ 1][1][lc] = psc * pT1;
+    // the next block ends at q0 - 1; publish the panel below when it reaches into it
+    const int qn = q0 - 1;
+    if (qn >= 0) {
+      const int qn0 = (tblk[qn] == 2) ? qn - 1 : qn;
+      if (qn0 < PW * plow) {
+        --plow;
+        panel_publish(plow);
+        panel_fetch(plow - 1);
+      }
     }
     __syncthreads();
-    buf ^= 1;
     q = q0 - 1;
   }
 
@@ -312,15 +352,15 @@ __global__ __launch_bounds__(MB) void solve_kernel(PencilDesc P, int r) {
     if (nxb > 1.0) frexp(nxb, &g);
     colG[lc] = g;
     if (inrange) {
-      const int64_t slot = (int64_t)(r % P.band) * m;
+      const int64_t slot = (int64_t)(r % P.wslots) * m;
       P.eW[slot + c] = e + g;
       P.nW[slot + c] = ldexp(nxb, -g);
     }
   }
-  // ---- write the solved tile to Z (coalesced down each column) ----
-  for (int idx = lc; idx < hr * hj; idx += MB) {
-    const int i = idx % hr, col = idx / hr;
-    P.Z[(r0 + i) + (c0 + col) * ldz] = Y[i * LDY + col];
+  // ---- write the solved tile to Z (thread lc writes row lc: coalesced down each column) ----
+  if (lc < hr) {
+    double* zrow = P.Z + (r0 + lc) + (int64_t)c0 * ldz;
+    for (int col = 0; col < hj; ++col) zrow[(int64_t)col * ldz] = Y[lc * LDY + col];
   }
   __syncthreads();
   // ---- W = 2^-g [X D ; -X B] in operand order: [kstep][col block][lane] ----
@@ -329,7 +369,7 @@ __global__ __launch_bounds__(MB) void solve_kernel(PencilDesc P, int r) {
     const int KP = (hr + 15) & ~15;        // rows of each half, padded to the update's K chunk
     const int KS = 2 * KP / 4;
     const int total = KS * CBM * 64;
-    double* Wj = P.W + ((int64_t)(r % P.band) * P.Mmax + j) * w_tile_doubles(MB);
+    double* Wj = P.W + ((int64_t)(r % P.wslots) * P.Mmax + j) * w_tile_doubles(MB);
     for (int idx = lc; idx < total; idx += MB) {
       const int s = idx / (CBM * 64);
       const int rem = idx % (CBM * 64);

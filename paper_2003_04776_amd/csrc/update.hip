@@ -13,11 +13,12 @@
 // own exponent, the per-column factors that bring the band to one exponent are exact
 // powers of two applied while W is staged, and one ProtectUpdate bounds the sum.
 //
-// One workgroup (4 waves) per target tile (k, j).  The K dimension (2 h_s per source, each half
-// padded to 16) is streamed in chunks of 16: the next chunk of [S_kr | T_kr] and of
-// the packed W tile is fetched into registers while the matrix cores work on the
-// current chunk in LDS (one barrier per chunk).  The waves split the tile 2 x 2; each
-// keeps a (MB/2) x (MB/2) block of 16x16x4 FP64 accumulators.  Tiles are visited in
+// One workgroup per target tile (k, j).  The K dimension (2 h_s per source, each half
+// padded to 16) is streamed in chunks of 16 through two LDS stages; the loads of the
+// chunk after next are issued before the matrix cores start on the current chunk, so
+// every global load has two chunks of compute to arrive (one barrier per chunk).  The
+// waves split the tile into a WGR x WGC grid (2 x 4 for MB = 128: 64 x 32 per wave,
+// so four waves share each SIMD when two workgroups share a CU).  Tiles are visited in
 // 8 x 8 blocks, each XCD taking a contiguous range of blocks, so the S/T and W tiles
 // that neighbouring workgroups share stay in that XCD's L2.
 #include <hip/hip_runtime.h>
@@ -31,8 +32,12 @@ namespace rgev {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kUpdThreads = 256;
 constexpr int kChunk = 16;   // K rows per LDS stage
+
+template <int MB> struct UpdShape;   // wave grid per tile size
+template <> struct UpdShape<128> { static constexpr int R = 2, C = 4; };
+template <> struct UpdShape<64> { static constexpr int R = 2, C = 4; };
+template <> struct UpdShape<32> { static constexpr int R = 2, C = 2; };
 
 struct UpdRange {
   int k_lo, k_hi;   // target tile rows [k_lo, k_hi)
@@ -40,10 +45,14 @@ struct UpdRange {
   int s_lo, s_hi;   // source tile rows (all below every target row)
 };
 
+// two workgroups per CU: 2 R C / 4 waves per SIMD
 template <int MB>
-__global__ __launch_bounds__(kUpdThreads, 2) void update_kernel(PencilDesc P, UpdRange U) {
-  constexpr int WR = MB / 2;            // rows per wave
-  constexpr int WC = MB / 2;            // columns per wave
+__global__ __launch_bounds__(64 * UpdShape<MB>::R * UpdShape<MB>::C, UpdShape<MB>::R * UpdShape<MB>::C / 2)
+void update_kernel(PencilDesc P, UpdRange U) {
+  constexpr int WGR = UpdShape<MB>::R, WGC = UpdShape<MB>::C;
+  constexpr int kUpdThreads = 64 * WGR * WGC;
+  constexpr int WR = MB / WGR;          // rows per wave
+  constexpr int WC = MB / WGC;          // columns per wave
   constexpr int RB = WR / 16;           // row blocks per wave
   constexpr int CB = WC / 16;           // column blocks per wave
   constexpr int CBM = MB / 16;          // column blocks of a W tile
@@ -55,7 +64,7 @@ __global__ __launch_bounds__(kUpdThreads, 2) void update_kernel(PencilDesc P, Up
   __shared__ int sfY[MB], sfA[MB], seN[MB];
   __shared__ int sg[kMaxBand][MB];   // exponent of each source's W relative to the band's
   __shared__ int sgany[kMaxBand];
-  __shared__ double red[2][MB];
+  __shared__ double red[WGR][MB];
 
   const int M = P.ctrl->M;
   if (U.j_lo >= M || U.k_hi <= U.k_lo || U.s_lo >= M) return;
@@ -71,7 +80,7 @@ __global__ __launch_bounds__(kUpdThreads, 2) void update_kernel(PencilDesc P, Up
   if (k >= U.k_hi || j >= M) return;
 
   const int64_t m = P.m;
-  const int R = P.band;
+  const int WSL = P.wslots;
   const int k0 = P.edges[k], hk = P.edges[k + 1] - k0;
   const int c0 = P.edges[j], hj = P.edges[j + 1] - c0;
   // sources that reach column tile j: s_lo .. s_end (the source row j itself, when in the
@@ -91,7 +100,7 @@ __global__ __launch_bounds__(kUpdThreads, 2) void update_kernel(PencilDesc P, Up
   if (tid < kMaxBand) sgany[tid] = 0;
   __syncthreads();
   const int wave = tid / 64, lane = tid % 64;
-  const int wr = wave / 2, wc = wave % 2;
+  const int wr = wave / WGC, wc = wave % WGC;
   const int li = lane % 16, lk = lane / 16;
 
   // ---- per-column scales (Algorithm 3): common exponent, ProtectUpdate ----
@@ -117,7 +126,7 @@ __global__ __launch_bounds__(kUpdThreads, 2) void update_kernel(PencilDesc P, Up
       for (int i = 0; i < kMaxBand; ++i) {
         if (i < ns) {
           const int s = U.s_lo + i;
-          const int64_t slot = (int64_t)(s % R) * m + c;
+          const int64_t slot = (int64_t)(s % WSL) * m + c;
           eWs[i] = P.eW[slot];
           nWs[i] = P.nW[slot];
           nus[i] = P.nu[(int64_t)k * P.Mmax + s];
@@ -174,12 +183,11 @@ __global__ __launch_bounds__(kUpdThreads, 2) void update_kernel(PencilDesc P, Up
     return p;
   };
 
-  double ra[AK], rw[WV];
   // Every load is unconditional (a masked element reads a valid address), and the
-  // zero mask is applied only when the chunk is written to LDS, so the loads of the
-  // next chunk stay in flight while the matrix cores work on the current one.
+  // zero mask is applied only when the chunk is written to LDS, so the loads stay in
+  // flight while the matrix cores work.
   const double* safe = P.S;
-  auto fetch = [&](int c) {
+  auto fetch = [&](int c, double (&ra)[AK], double (&rw)[WV]) {
     const ChunkPos p = where(c);
     const int s = U.s_lo + p.i;
     const int64_t ld = p.lower ? P.ldt : P.lds;
@@ -191,12 +199,12 @@ __global__ __launch_bounds__(kUpdThreads, 2) void update_kernel(PencilDesc P, Up
       const bool ok = arow_ok && (krel + TPR * i < p.hs);
       ra[i] = *(ok ? pa + i * step : safe);
     }
-    const double* wsrc = P.W + ((int64_t)(s % R) * P.Mmax + j) * w_tile_doubles(MB) +
+    const double* wsrc = P.W + ((int64_t)(s % WSL) * P.Mmax + j) * w_tile_doubles(MB) +
                          (int64_t)p.cc * kChunk * MB + tid;
 #pragma unroll
     for (int i = 0; i < WV; ++i) rw[i] = wsrc[i * kUpdThreads];
   };
-  auto stash = [&](int b, int c) {
+  auto stash = [&](int b, int c, const double (&ra)[AK], const double (&rw)[WV]) {
     const ChunkPos p = where(c);
     const int krel = p.kb - P.edges[U.s_lo + p.i] + akof;
 #pragma unroll
@@ -207,7 +215,7 @@ __global__ __launch_bounds__(kUpdThreads, 2) void update_kernel(PencilDesc P, Up
     if (sgany[p.i]) {
 #pragma unroll
       for (int i = 0; i < WV; ++i) {
-        const int n = 16 * ((4 * i + tid / 64) % CBM) + tid % 16;
+        const int n = 16 * (((i * kUpdThreads + tid) / 64) % CBM) + tid % 16;
         Ws[b][i * kUpdThreads + tid] = ldexp(rw[i], sg[p.i][n]);
       }
     } else {
@@ -222,13 +230,15 @@ __global__ __launch_bounds__(kUpdThreads, 2) void update_kernel(PencilDesc P, Up
 #pragma unroll
     for (int b = 0; b < CB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-  fetch(0);
+  double ra0[AK], rw0[WV], ra1[AK], rw1[WV], ra2[AK], rw2[WV];
+  fetch(0, ra0, rw0);
+  if (1 < nch) fetch(1, ra1, rw1);
   __syncthreads();   // per-column scales published; old scales all read before any rewrite
-  stash(0, 0);
+  stash(0, 0, ra0, rw0);
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
     const int b = c & 1;
-    if (c + 1 < nch) fetch(c + 1);
+    if (c + 2 < nch) fetch(c + 2, ra2, rw2);
 #pragma unroll
     for (int s = 0; s < kChunk / 4; ++s) {
       double af[RB], bf[CB];
@@ -244,8 +254,12 @@ __global__ __launch_bounds__(kUpdThreads, 2) void update_kernel(PencilDesc P, Up
         for (int q = 0; q < CB; ++q)
           acc[a][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[q], af[a], acc[a][q], 0, 0, 0);
     }
-    if (c + 1 < nch) stash(b ^ 1, c + 1);
+    if (c + 1 < nch) stash(b ^ 1, c + 1, ra1, rw1);
     __syncthreads();
+#pragma unroll
+    for (int i = 0; i < AK; ++i) ra1[i] = ra2[i];
+#pragma unroll
+    for (int i = 0; i < WV; ++i) rw1[i] = rw2[i];
   }
 
   // ---- epilogue: Y <- 2^fY Y - 2^fA acc and the new segment norms ----
@@ -281,8 +295,11 @@ __global__ __launch_bounds__(kUpdThreads, 2) void update_kernel(PencilDesc P, Up
   __syncthreads();
   if (tid < hj) {
     const int64_t c = c0 + tid;
+    double nx = red[0][tid];
+#pragma unroll
+    for (int w = 1; w < WGR; ++w) nx = fmax(nx, red[w][tid]);
     P.exps[(int64_t)k * m + c] = seN[tid];
-    P.norms[(int64_t)k * m + c] = fmax(red[0][tid], red[1][tid]);
+    P.norms[(int64_t)k * m + c] = nx;
   }
 }
 
@@ -291,7 +308,7 @@ static void launch_update_t(const PencilDesc& P, const UpdRange& U, hipStream_t 
   // upper bound on the 8 x 8 blocked tile range (the true tile count is on the device)
   const int64_t nbk = (U.k_hi - U.k_lo + 7) / 8, nbj = (P.Mmax - U.j_lo + 7) / 8;
   const int64_t grid = nbk * nbj * 64;
-  update_kernel<MB><<<(unsigned)grid, kUpdThreads, 0, s>>>(P, U);
+  update_kernel<MB><<<(unsigned)grid, 64 * UpdShape<MB>::R * UpdShape<MB>::C, 0, s>>>(P, U);
 }
 
 // Apply source rows [s_lo, s_hi] to target rows [k_lo, k_hi) of every tile column
