@@ -12,6 +12,8 @@
 // threads that both evaluate the complex pivot arithmetic and keep their own part.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "layout.hpp"
 #include "robust.hpp"
 
@@ -118,19 +120,30 @@ __device__ __forceinline__ void solve2(double a, double b, double be, double s00
   y1 = jp ? w1 : w2;
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int solve_threads(int mb) { return mb < 64 ? 64 : mb; }
+// the whole workgroup: the column threads plus as many again for the matrix-core and
+// copy phases (one wave per SIMD)
+constexpr int solve_total(int mb) { return mb < 64 ? 64 : 2 * mb; }
+
 template <int MB>
-__global__ __launch_bounds__(MB) void solve_kernel(PencilDesc P, int r) {
+__global__ __launch_bounds__(solve_total(MB)) void solve_kernel(PencilDesc P, int r) {
+  constexpr int NT = solve_threads(MB);   // one thread per column, at least one full wave
+  constexpr int NTOT = solve_total(MB);
   constexpr int LDY = MB + 1;   // odd stride: row and column sweeps are both conflict-free
-  constexpr int PW = 4;         // columns per staged panel of S_rr and T_rr
+  constexpr int G = 8;          // rows per group (recursive blocking inside the tile)
   __shared__ double Y[MB * LDY];
-  __shared__ double stS[2][PW][MB];   // [panel slot][column in panel][row]
-  __shared__ double stT[2][PW][MB];
+  __shared__ double Bop[2 * G][NT];   // [-beta z ; alpha z] of the group, own parts
+  __shared__ double Sg[G][G], Tg[G][G];   // diagonal block of the group: [row][column]
   __shared__ double tcnS[MB], tcnT[MB];
+  __shared__ int fcol[NT];
+  __shared__ int ecol[NT];            // scale exponent still owed by the rows above the group
   __shared__ int8_t tblk[MB];
-  __shared__ double cmax[MB];
-  __shared__ double colA[MB], colB[MB], colBe[MB];
-  __shared__ int colG[MB];
-  __shared__ int8_t colKind[MB];
+  __shared__ double cmax[NT];
+  __shared__ double colA[NT], colB[NT], colBe[NT];
+  __shared__ int colG[NT];
+  __shared__ int8_t colKind[NT];
 
   const int M = P.ctrl->M;
   const int j = r + (int)blockIdx.x;
@@ -145,7 +158,9 @@ __global__ __launch_bounds__(MB) void solve_kernel(PencilDesc P, int r) {
   const int64_t lds = P.lds, ldt = P.ldt, ldz = P.ldz;
 
   const int lc = threadIdx.x;
+  const int wave = lc / 64, lane = lc % 64;
   const bool inrange = lc < hj;
+  const bool colthr = lc < NT;
   const int64_t c = c0 + lc;
   int kind = 0;
   bool selected = false;
@@ -158,6 +173,8 @@ __global__ __launch_bounds__(MB) void solve_kernel(PencilDesc P, int r) {
     be = P.be[c];
   }
   const int partner = kind == 1 ? lc + 1 : (kind == 2 ? lc - 1 : lc);
+  const bool pair = kind == 1;                 // this thread carries the pair (lc, lc + 1)
+  const bool owner = selected && kind != 2;
   const int pc = (kind == 2 ? lc - 1 : lc) + (c0 - r0);   // local row of own block (tip tile)
   const double aabs = fabs(a) + fabs(b);
   int e = 0;
@@ -170,7 +187,7 @@ __global__ __launch_bounds__(MB) void solve_kernel(PencilDesc P, int r) {
     tcnS[lc] = P.cnS[r0 + lc];
     tcnT[lc] = P.cnT[r0 + lc];
   }
-  for (int idx = lc; idx < MB * LDY; idx += MB) Y[idx] = 0.0;
+  for (int idx = lc; idx < MB * LDY; idx += NTOT) Y[idx] = 0.0;
   __syncthreads();
   if (!tip) {
     // thread lc reads row lc of every column (coalesced down the columns), 16 loads in flight
@@ -191,154 +208,261 @@ __global__ __launch_bounds__(MB) void solve_kernel(PencilDesc P, int r) {
     }
   }
 
-  // ---- panels of S_rr, T_rr: panel p = columns [PW p, PW p + PW), slot p % 2 ----
-  double pfS[PW], pfT[PW];
-  auto panel_fetch = [&](int p) {
-#pragma unroll
-    for (int t = 0; t < PW; ++t) {
-      const int col = PW * p + t;
-      const bool ok = p >= 0 && col < hr && lc < hr;
-      pfS[t] = ok ? S[(r0 + lc) + (r0 + col) * lds] : 0.0;
-      pfT[t] = ok ? T[(r0 + lc) + (r0 + col) * ldt] : 0.0;
+  // groups of at most G rows from the bottom, never splitting a 2x2 block
+  auto group_lo = [&](int g1) {
+    int g0 = g1 - G + 1;
+    if (g0 < 0) g0 = 0;
+    if (g0 > 0 && tblk[g0] == 2) ++g0;
+    return g0;
+  };
+  // the group's diagonal block of S and T (lanes 0..63 of wave 0 hold one entry each)
+  // (loads are unconditional, from a valid address when masked, and the mask is applied
+  // at publication, so they stay in flight while the group is solved)
+  double pS = 0.0, pT = 0.0;
+  bool pOk = false;
+  auto panel_fetch = [&](int g0) {
+    const int u = lane / G, t = lane % G;
+    pOk = wave == 0 && g0 >= 0 && g0 + u < hr && g0 + t < hr;
+    const int64_t ro = pOk ? (r0 + g0 + u) : 0, co = pOk ? (r0 + g0 + t) : 0;
+    pS = S[ro + co * lds];
+    pT = T[ro + co * ldt];
+  };
+  auto panel_publish = [&]() {
+    if (wave == 0) {
+      Sg[lane / G][lane % G] = pOk ? psc * pS : 0.0;
+      Tg[lane / G][lane % G] = pOk ? psc * pT : 0.0;
     }
   };
-  auto panel_publish = [&](int p) {
-#pragma unroll
-    for (int t = 0; t < PW; ++t) {
-      stS[p & 1][t][lc] = psc * pfS[t];
-      stT[p & 1][t][lc] = psc * pfT[t];
-    }
-  };
-  auto SC = [&](int col) -> const double* { return stS[(col / PW) & 1][col % PW]; };
-  auto TC = [&](int col) -> const double* { return stT[(col / PW) & 1][col % PW]; };
-
-  int plow = (hr - 1) / PW;   // lowest-numbered panel resident in LDS
-  panel_fetch(plow);
-  panel_publish(plow);
-  panel_fetch(plow - 1);
-  if ((tblk[hr - 1] == 2 ? hr - 2 : hr - 1) < PW * plow) {   // the first block reaches below
-    --plow;
-    panel_publish(plow);
-    panel_fetch(plow - 1);
-  }
+  __syncthreads();   // tblk visible
+  int g1 = hr - 1;
+  int g0 = group_lo(g1);
+  panel_fetch(g0);
+  panel_publish();
   __syncthreads();
 
-  int q = hr - 1;
-  while (q >= 0) {
-    const int q0 = (tblk[q] == 2) ? q - 1 : q;
-    const int nb = q - q0 + 1;
-    // ---- phase A: small solve of the block (rows q0..q) ----
-    const bool work = selected && !(tip && q0 > pc);
-    Cx z0 = cx(0.0, 0.0), z1 = cx(0.0, 0.0);
-    int qs = 0;
-    double cn = 0.0;
-    if (work) {
-      auto yv = [&](int row) -> Cx {
-        if (kind == 0) return cx(Y[row * LDY + lc], 0.0);
-        const double own = Y[row * LDY + lc], oth = Y[row * LDY + partner];
-        return kind == 1 ? cx(own, oth) : cx(oth, own);
+  while (g1 >= 0) {
+    const int gn1 = g0 - 1;                       // next group
+    const int gn0 = gn1 >= 0 ? group_lo(gn1) : -1;
+    panel_fetch(gn0);                             // lands during this group's work
+    // operands of the rank-2G update of the rows above (A = [S | T] rows 0..g0-1 of the
+    // group's columns), 16 x 4 blocks in the layout of the FP64 matrix instruction
+    double af[MB / 16][4];   // raw entries; masked and scaled where they are used
+#pragma unroll
+    for (int rb = 0; rb < MB / 16; ++rb)
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int row = 16 * rb + lane % 16;
+        const int kk = 4 * st + lane / 16;        // 0..15: S columns 0..7, T columns 8..15
+        const int col = g0 + (kk & (G - 1));
+        const bool ok = row < g0 && col <= g1;
+        const int64_t ro = ok ? r0 + row : 0, co = ok ? r0 + col : 0;
+        af[rb][st] = kk < G ? S[ro + co * lds] : T[ro + co * ldt];
+      }
+    double yb_above = ybound;   // bound on the rows above the group
+    int qsg = 0;                // scaling raised inside the group
+
+    // ---- blocks of the group, bottom up; updates stay inside the group ----
+    // Each column's substitution is private to the thread that owns it (a complex pair
+    // belongs to the thread of its first column), so the blocks need no barrier.
+    int q = g1;
+    while (q >= g0) {
+      const int q0 = (tblk[q] == 2) ? q - 1 : q;
+      const int nb = q - q0 + 1;
+      const int lq0 = q0 - g0, lq = q - g0;      // positions in the group panel
+      if (owner && !(tip && q0 > pc)) {
+        auto yv = [&](int row) -> Cx { return cx(Y[row * LDY + lc], pair ? Y[row * LDY + lc + 1] : 0.0); };
+        Cx z0 = cx(0.0, 0.0), z1 = cx(0.0, 0.0);
+        int qs = 0;
+        if (tip && q0 == pc) {
+          if (nb == 1) {
+            z0 = cx(1.0, 0.0);
+          } else {
+            // second row of the singular block beta S_b - alpha T_b gives z_p for z_{p+1} = 1
+            const double s21 = Sg[lq][lq0], s22 = Sg[lq][lq], t22 = Tg[lq][lq];
+            double m21 = be * s21;
+            const Cx nn = cx(-(be * s22 - a * t22), b * t22);
+            const double smin = local_smin(be, aabs, fmax(fabs(s21), fabs(s22)), fabs(t22));
+            if (fabs(m21) < smin) { m21 = smin; flags |= kInfoPerturbed; }
+            const int qd = with_margin(protect_division(cn1(nn), fabs(m21)));
+            const Cx ns = cscl(nn, qd);
+            z0 = cx(ns.r / m21, ns.i / m21);
+            z1 = cx(ldexp(1.0, -qd), 0.0);
+            qs += qd;
+          }
+        } else if (nb == 1) {
+          z0 = solve1(a, b, be, Sg[lq][lq], Tg[lq][lq], yv(q), qs, flags);
+        } else {
+          z0 = yv(q0);
+          z1 = yv(q);
+          solve2(a, b, be, Sg[lq0][lq0], Sg[lq0][lq], Sg[lq][lq0], Sg[lq][lq], Tg[lq0][lq0], Tg[lq0][lq],
+                 Tg[lq][lq], z0, z1, qs, flags);
+        }
+        double cn = 0.0;
+        if (q0 > 0) {
+          // ProtectUpdate for y[0:q0] -= (beta S - alpha T)[0:q0, q0..q] z (inside the group
+          // now, above it at the end of the group; the column norms bound both)
+          cn = be * tcnS[q0] + aabs * tcnT[q0];
+          if (nb == 2) cn += be * tcnS[q] + aabs * tcnT[q];
+          const double zn = fmax(cn1(z0), cn1(z1));
+          const int qu = with_margin(protect_update(cn, zn, ldexp(ybound, -qs)));
+          z0 = cscl(z0, qu);
+          z1 = cscl(z1, qu);
+          qs += qu;
+        }
+        if (qs > 0) {
+          // the group's other rows now; the rows above and below at the end of the group
+          for (int i = g0; i <= g1; ++i) {
+            Y[i * LDY + lc] = ldexp(Y[i * LDY + lc], -qs);
+            if (pair) Y[i * LDY + lc + 1] = ldexp(Y[i * LDY + lc + 1], -qs);
+          }
+          qsg += qs;
+          e += qs;
+          ybound = ldexp(ybound, -qs);
+          yb_above = ldexp(yb_above, -qs);
+        }
+        Y[q0 * LDY + lc] = z0.r;
+        if (pair) Y[q0 * LDY + lc + 1] = z0.i;
+        if (nb == 2) {
+          Y[q * LDY + lc] = z1.r;
+          if (pair) Y[q * LDY + lc + 1] = z1.i;
+        }
+        if (q0 > g0) {
+          // y -= S (beta z) - T (alpha z), real and imaginary parts
+          const Cx u0 = cx(be * z0.r, be * z0.i), u1 = cx(be * z1.r, be * z1.i);
+          const Cx v0 = cx(a * z0.r - b * z0.i, a * z0.i + b * z0.r);
+          const Cx v1 = cx(a * z1.r - b * z1.i, a * z1.i + b * z1.r);
+          for (int i = g0; i < q0; ++i) {
+            const int li = i - g0;
+            const double s0 = Sg[li][lq0], t0 = Tg[li][lq0];
+            double dr = s0 * u0.r - t0 * v0.r, di = s0 * u0.i - t0 * v0.i;
+            if (nb == 2) {
+              const double s1 = Sg[li][lq], t1 = Tg[li][lq];
+              dr += s1 * u1.r - t1 * v1.r;
+              di += s1 * u1.i - t1 * v1.i;
+            }
+            Y[i * LDY + lc] -= dr;
+            if (pair) Y[i * LDY + lc + 1] -= di;
+          }
+        }
+        if (q0 > 0) ybound += cn * fmax(cn1(z0), cn1(z1));
+      }
+      q = q0 - 1;
+    }
+
+    // ---- end of group: bound the rank-2G update of the rows above, settle scales ----
+    if (owner && g0 > 0) {
+      double cng = 0.0, zng = 0.0;
+      for (int i = g0; i <= g1; ++i) {
+        cng += be * tcnS[i] + aabs * tcnT[i];
+        zng = fmax(zng, fabs(Y[i * LDY + lc]) + (pair ? fabs(Y[i * LDY + lc + 1]) : 0.0));
+      }
+      const int qg = with_margin(protect_update(cng, zng, yb_above));
+      if (qg > 0) {
+        for (int i = g0; i <= g1; ++i) {
+          Y[i * LDY + lc] = ldexp(Y[i * LDY + lc], -qg);
+          if (pair) Y[i * LDY + lc + 1] = ldexp(Y[i * LDY + lc + 1], -qg);
+        }
+        qsg += qg;
+        e += qg;
+        yb_above = ldexp(yb_above, -qg);
+        zng = ldexp(zng, -qg);
+      }
+      ybound = yb_above + cng * zng;
+    }
+    if (owner && qsg > 0)   // the solved rows below the group (rare: scaling has head room)
+      for (int i = g1 + 1; i < hr; ++i) {
+        Y[i * LDY + lc] = ldexp(Y[i * LDY + lc], -qsg);
+        if (pair) Y[i * LDY + lc + 1] = ldexp(Y[i * LDY + lc + 1], -qsg);
+      }
+    if (colthr && kind != 2) {
+      fcol[lc] = qsg;
+      if (pair) fcol[lc + 1] = qsg;
+    }
+    __syncthreads();   // the group's solved values and scales are final
+    // B operand: [-beta z ; alpha z] own parts, zero for rows outside the group
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+      const int i = g0 + t;
+      double bu = 0.0, bv = 0.0;
+      if (i <= g1 && selected) {
+        const double own = Y[i * LDY + lc];
+        const double oth = Y[i * LDY + partner];
+        const double zr = kind == 2 ? oth : own, zi = kind == 0 ? 0.0 : (kind == 1 ? oth : own);
+        bu = -be * own;
+        bv = kind == 2 ? (b * zr + a * zi) : (a * zr - b * zi);
+      }
+      if (colthr) {
+        Bop[t][lc] = bu;
+        Bop[G + t][lc] = bv;
+      }
+    }
+    panel_publish();   // the next group's diagonal block (its loads had the whole group)
+    __syncthreads();
+
+    // ---- rank-2G update of the rows above the group on the FP64 matrix cores ----
+    // Y[0:g0, :] <- 2^-fcol Y[0:g0, :] + [S | T][0:g0, group] * [-beta z ; alpha z]
+    if (g0 > 0) {
+      const int nrb = (g0 + 15) / 16, ncb = (hj + 15) / 16;
+      constexpr int nw = NTOT / 64;
+      // A wave owns whole column blocks; its row blocks are independent chains, issued
+      // interleaved.  NR (a compile-time bound on the row blocks) keeps every operand in
+      // registers and every instruction unconditional: rows at or below the group and
+      // columns past the tile are computed and dropped, and operand columns past the
+      // group meet zero rows of B.
+      auto rank_update = [&](auto nr_c) {
+        constexpr int NR = decltype(nr_c)::value;
+        for (int cb = wave; cb < ncb; cb += nw) {
+          const int col = 16 * cb + lane % 16;
+          const int fs = fcol[col];
+          d4 acc[NR];
+#pragma unroll
+          for (int rb = 0; rb < NR; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              acc[rb][v] = ldexp(Y[(16 * rb + lane / 16 + 4 * v) * LDY + col], -fs);
+#pragma unroll
+          for (int st = 0; st < 4; ++st) {
+            const double bf = Bop[4 * st + lane / 16][col];
+#pragma unroll
+            for (int rb = 0; rb < NR; ++rb)
+              acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(psc * af[rb][st], bf, acc[rb], 0, 0, 0);
+          }
+          const bool cok = col < hj;
+#pragma unroll
+          for (int rb = 0; rb < NR; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = 16 * rb + lane / 16 + 4 * v;
+              if (row < g0 && cok) Y[row * LDY + col] = acc[rb][v];
+            }
+        }
       };
-      if (tip && q0 == pc) {
-        if (nb == 1) {
-          z0 = cx(1.0, 0.0);
-        } else {
-          // second row of the singular block beta S_b - alpha T_b gives z_p for z_{p+1} = 1
-          const double s21 = SC(q0)[q], s22 = SC(q)[q], t22 = TC(q)[q];
-          double m21 = be * s21;
-          const Cx nn = cx(-(be * s22 - a * t22), b * t22);
-          const double smin = local_smin(be, aabs, fmax(fabs(s21), fabs(s22)), fabs(t22));
-          if (fabs(m21) < smin) { m21 = smin; flags |= kInfoPerturbed; }
-          const int qd = with_margin(protect_division(cn1(nn), fabs(m21)));
-          const Cx ns = cscl(nn, qd);
-          z0 = cx(ns.r / m21, ns.i / m21);
-          z1 = cx(ldexp(1.0, -qd), 0.0);
-          qs += qd;
-        }
-      } else if (nb == 1) {
-        z0 = solve1(a, b, be, SC(q)[q], TC(q)[q], yv(q), qs, flags);
-      } else {
-        z0 = yv(q0);
-        z1 = yv(q);
-        solve2(a, b, be, SC(q0)[q0], SC(q)[q0], SC(q0)[q], SC(q)[q], TC(q0)[q0], TC(q)[q0], TC(q)[q],
-               z0, z1, qs, flags);
-      }
-      if (q0 > 0) {
-        // ProtectUpdate for y[0:q0] -= (beta S - alpha T)[0:q0, q0..q] z
-        cn = be * tcnS[q0] + aabs * tcnT[q0];
-        if (nb == 2) cn += be * tcnS[q] + aabs * tcnT[q];
-        const double zn = fmax(cn1(z0), cn1(z1));
-        const int qu = with_margin(protect_update(cn, zn, ldexp(ybound, -qs)));
-        z0 = cscl(z0, qu);
-        z1 = cscl(z1, qu);
-        qs += qu;
-      }
-    }
-    __syncthreads();   // every thread has read rows q0..q before any is overwritten
-    if (work) {
-      // the scale applies to the whole segment: the solved rows below now, the rows
-      // above inside the update loop (f is an exact power of two)
-      double f = 1.0;
-      if (qs > 0) {
-        for (int i = q + 1; i < hr; ++i) Y[i * LDY + lc] = ldexp(Y[i * LDY + lc], -qs);
-        if (qs <= 1000) {
-          f = ldexp(1.0, -qs);
-        } else {
-          for (int i = 0; i < q0; ++i) Y[i * LDY + lc] = ldexp(Y[i * LDY + lc], -qs);
-        }
-        e += qs;
-        ybound = ldexp(ybound, -qs);
-      }
-      const bool im = (kind == 2);
-      Y[q0 * LDY + lc] = im ? z0.i : z0.r;
-      if (nb == 2) Y[q * LDY + lc] = im ? z1.i : z1.r;
-      if (q0 > 0) {
-        // u = beta z, v = alpha z (own real or imaginary part)
-        const double u0 = be * (im ? z0.i : z0.r);
-        const double v0 = im ? (b * z0.r + a * z0.i) : (a * z0.r - b * z0.i);
-        const double* sc0 = SC(q0);
-        const double* tc0 = TC(q0);
-        if (nb == 1) {
-#pragma unroll 4
-          for (int i = 0; i < q0; ++i) {
-            const double y = Y[i * LDY + lc];
-            Y[i * LDY + lc] = y * f - (sc0[i] * u0 - tc0[i] * v0);
-          }
-        } else {
-          const double u1 = be * (im ? z1.i : z1.r);
-          const double v1 = im ? (b * z1.r + a * z1.i) : (a * z1.r - b * z1.i);
-          const double* sc1 = SC(q);
-          const double* tc1 = TC(q);
-#pragma unroll 4
-          for (int i = 0; i < q0; ++i) {
-            const double y = Y[i * LDY + lc];
-            Y[i * LDY + lc] = y * f - ((sc0[i] * u0 - tc0[i] * v0) + (sc1[i] * u1 - tc1[i] * v1));
-          }
-        }
-        ybound += cn * fmax(cn1(z0), cn1(z1));
-      }
-    }
-    // the next block ends at q0 - 1; publish the panel below when it reaches into it
-    const int qn = q0 - 1;
-    if (qn >= 0) {
-      const int qn0 = (tblk[qn] == 2) ? qn - 1 : qn;
-      if (qn0 < PW * plow) {
-        --plow;
-        panel_publish(plow);
-        panel_fetch(plow - 1);
-      }
+      constexpr int NR0 = MB / 16;
+      if (nrb > NR0 / 2) rank_update(std::integral_constant<int, NR0>{});
+      else if (nrb > NR0 / 4 || NR0 < 4) rank_update(std::integral_constant<int, (NR0 / 2 > 0 ? NR0 / 2 : 1)>{});
+      else rank_update(std::integral_constant<int, (NR0 / 4 > 0 ? NR0 / 4 : 1)>{});
     }
     __syncthreads();
-    q = q0 - 1;
+    g1 = gn1;
+    g0 = gn0;
   }
+
+  // the second column of a pair takes the exponent its owner carried
+  if (colthr && pair) ecol[lc + 1] = e;
+  __syncthreads();
+  if (kind == 2) e = ecol[lc];
 
   // ---- segment norm and exponent ----
   double nx = 0.0;
-  for (int i = 0; i < hr; ++i) nx = fmax(nx, fabs(Y[i * LDY + lc]));
-  cmax[lc] = nx;
-  colA[lc] = a;
-  colB[lc] = b;
-  colBe[lc] = be;
-  colKind[lc] = (int8_t)kind;
+  if (inrange)
+    for (int i = 0; i < hr; ++i) nx = fmax(nx, fabs(Y[i * LDY + lc]));
+  if (colthr) {
+    cmax[lc] = nx;
+    colA[lc] = a;
+    colB[lc] = b;
+    colBe[lc] = be;
+    colKind[lc] = (int8_t)kind;
+  }
   if (inrange) {
     P.exps[(int64_t)r * m + c] = e;
     P.norms[(int64_t)r * m + c] = nx;
@@ -347,10 +471,10 @@ __global__ __launch_bounds__(MB) void solve_kernel(PencilDesc P, int r) {
   __syncthreads();
   // Algorithm 2 with a scale that bounds the pair norm of W by one
   {
-    const double nxb = cmax[lc] + (kind != 0 ? cmax[partner] : 0.0);
+    const double nxb = colthr ? cmax[lc] + (kind != 0 ? cmax[partner] : 0.0) : 0.0;
     int g = 0;
     if (nxb > 1.0) frexp(nxb, &g);
-    colG[lc] = g;
+    if (colthr) colG[lc] = g;
     if (inrange) {
       const int64_t slot = (int64_t)(r % P.wslots) * m;
       P.eW[slot + c] = e + g;
@@ -368,42 +492,38 @@ __global__ __launch_bounds__(MB) void solve_kernel(PencilDesc P, int r) {
     constexpr int CBM = MB / 16;
     const int KP = (hr + 15) & ~15;        // rows of each half, padded to the update's K chunk
     const int KS = 2 * KP / 4;
-    const int total = KS * CBM * 64;
     double* Wj = P.W + ((int64_t)(r % P.wslots) * P.Mmax + j) * w_tile_doubles(MB);
-    for (int idx = lc; idx < total; idx += MB) {
-      const int s = idx / (CBM * 64);
-      const int rem = idx % (CBM * 64);
-      const int cb = rem / 64, l = rem % 64;
-      const int kr = 4 * s + l / 16;
-      const int n = 16 * cb + l % 16;
-      double w = 0.0;
-      if (n < hj) {
+    // a thread keeps one (column block, lane) position and walks the K steps
+    for (int cbl = lc; cbl < CBM * 64; cbl += NTOT) {
+      const int n = 16 * (cbl / 64) + cbl % 16;
+      const int l16 = (cbl % 64) / 16;
+      const bool nok = n < hj;
+      const int g = nok ? colG[n] : 0;
+      const int kd = nok ? colKind[n] : 0;
+      const double an = nok ? colA[n] : 0.0, bn = nok ? colB[n] : 0.0, ben = nok ? colBe[n] : 0.0;
+      const int np = kd == 1 ? n + 1 : (kd == 2 ? n - 1 : n);
+      for (int s = 0; s < KS; ++s) {
+        const int kr = 4 * s + l16;
         const bool lower = kr >= KP;
         const int i = lower ? kr - KP : kr;
-        if (i < hr) {
-          const int g = colG[n];
-          const int kd = colKind[n];
-          const double x = Y[i * LDY + n];
-          if (!lower) {
-            w = colBe[n] * x;
-          } else {
-            const double an = colA[n], bn = colB[n];
-            if (kd == 0) w = an * x;
-            else if (kd == 1) w = an * x - bn * Y[i * LDY + n + 1];
-            else w = bn * Y[i * LDY + n - 1] + an * x;
-            w = -w;
-          }
+        double w = 0.0;
+        if (nok && i < hr) {
+          const double x = Y[i * LDY + n], xp = Y[i * LDY + np];
+          if (!lower) w = ben * x;
+          else if (kd == 0) w = -(an * x);
+          else if (kd == 1) w = -(an * x - bn * xp);
+          else w = -(bn * xp + an * x);
           w = ldexp(w, -g);
         }
+        Wj[(int64_t)s * (CBM * 64) + cbl] = w;
       }
-      Wj[idx] = w;
     }
   }
 }
 
 template <int MB>
 static void launch_solve_t(const PencilDesc& P, int r, hipStream_t s) {
-  solve_kernel<MB><<<P.Mmax - r, MB, 0, s>>>(P, r);
+  solve_kernel<MB><<<P.Mmax - r, solve_total(MB), 0, s>>>(P, r);
 }
 
 void launch_solve(const PencilDesc& P, int r, hipStream_t s) {
