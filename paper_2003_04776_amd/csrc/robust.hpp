@@ -52,28 +52,31 @@ __device__ __forceinline__ int protect_update(double t, double x, double y) {
 }
 
 // Complex quotient (a + ib) / (c + id) by Smith's method, with the refinements of
-// Baudin & Smith (2012) for intermediate products that underflow.
+// Baudin & Smith (2012) for intermediate products that underflow.  Requires |d| <= |c|.
 __device__ __forceinline__ void smith_core(double a, double b, double c, double d, double& e, double& f) {
   const double r = d / c;
   const double t = 1.0 / (c + d * r);
-  if (r != 0.0) {
+  if (r != 0.0 || d == 0.0) {
+    // (d == 0 lands here too: r = 0 and the products with r vanish)
     const double br = b * r;
     e = (br != 0.0) ? (a + br) * t : a * t + (b * t) * r;
     const double ar = a * r;
     f = (ar != 0.0) ? (b - ar) * t : b * t - (a * t) * r;
   } else {
+    // d / c underflowed
     e = (a + d * (b / c)) * t;
     f = (b - d * (a / c)) * t;
   }
 }
 
+// The larger of |c|, |d| goes to the divisor's real slot; the swap is done with
+// selects so lanes with different orderings share one instruction stream.
 __device__ __forceinline__ void complex_div(double a, double b, double c, double d, double& e, double& f) {
-  if (fabs(d) <= fabs(c)) {
-    smith_core(a, b, c, d, e, f);
-  } else {
-    smith_core(b, a, d, c, e, f);
-    f = -f;
-  }
+  const bool sw = fabs(d) > fabs(c);
+  double e1, f1;
+  smith_core(sw ? b : a, sw ? a : b, sw ? d : c, sw ? c : d, e1, f1);
+  e = e1;
+  f = sw ? -f1 : f1;
 }
 
 __device__ __forceinline__ double abs1(double x, double y) { return fabs(x) + fabs(y); }

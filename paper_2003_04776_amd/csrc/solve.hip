@@ -263,15 +263,36 @@ __global__ __launch_bounds__(solve_total(MB)) void solve_kernel(PencilDesc P, in
 
     // ---- blocks of the group, bottom up; updates stay inside the group ----
     // Each column's substitution is private to the thread that owns it (a complex pair
-    // belongs to the thread of its first column), so the blocks need no barrier.
+    // belongs to the thread of its first column), so the blocks need no barrier.  The
+    // unsolved rows live in registers as a stack, stk[k] = row (top) - k: a block takes
+    // its rows from the top, the rows above it are updated in place, and the stack
+    // shifts by the block size, so every register index is a constant.
+    Cx stk[G];
+    const int yc0 = lc < MB ? lc : 0, yc1 = pair ? lc + 1 : yc0;   // (threads past the tile read column 0)
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int row = g1 - k >= 0 ? g1 - k : 0;   // (rows above the group: never stored)
+      stk[k] = cx(Y[row * LDY + yc0], pair ? Y[row * LDY + yc1] : 0.0);
+    }
     int q = g1;
     while (q >= g0) {
       const int q0 = (tblk[q] == 2) ? q - 1 : q;
       const int nb = q - q0 + 1;
       const int lq0 = q0 - g0, lq = q - g0;      // positions in the group panel
-      if (owner && !(tip && q0 > pc)) {
-        auto yv = [&](int row) -> Cx { return cx(Y[row * LDY + lc], pair ? Y[row * LDY + lc + 1] : 0.0); };
-        Cx z0 = cx(0.0, 0.0), z1 = cx(0.0, 0.0);
+      // the block's columns of the panel for the rows above it: entry k is row q0 - 1 - k
+      double sc0[G - 1], tc0[G - 1], sc1[G - 1], tc1[G - 1];
+#pragma unroll
+      for (int k = 0; k < G - 1; ++k) {
+        const int li = lq0 - 1 - k >= 0 ? lq0 - 1 - k : 0;
+        sc0[k] = Sg[li][lq0];
+        tc0[k] = Tg[li][lq0];
+        sc1[k] = Sg[li][lq];
+        tc1[k] = Tg[li][lq];
+      }
+      const bool work = owner && !(tip && q0 > pc);
+      Cx z0 = cx(0.0, 0.0), z1 = cx(0.0, 0.0);
+      double cn = 0.0;
+      if (work) {
         int qs = 0;
         if (tip && q0 == pc) {
           if (nb == 1) {
@@ -290,14 +311,13 @@ __global__ __launch_bounds__(solve_total(MB)) void solve_kernel(PencilDesc P, in
             qs += qd;
           }
         } else if (nb == 1) {
-          z0 = solve1(a, b, be, Sg[lq][lq], Tg[lq][lq], yv(q), qs, flags);
+          z0 = solve1(a, b, be, Sg[lq][lq], Tg[lq][lq], stk[0], qs, flags);
         } else {
-          z0 = yv(q0);
-          z1 = yv(q);
+          z0 = stk[1];
+          z1 = stk[0];
           solve2(a, b, be, Sg[lq0][lq0], Sg[lq0][lq], Sg[lq][lq0], Sg[lq][lq], Tg[lq0][lq0], Tg[lq0][lq],
                  Tg[lq][lq], z0, z1, qs, flags);
         }
-        double cn = 0.0;
         if (q0 > 0) {
           // ProtectUpdate for y[0:q0] -= (beta S - alpha T)[0:q0, q0..q] z (inside the group
           // now, above it at the end of the group; the column norms bound both)
@@ -310,8 +330,11 @@ __global__ __launch_bounds__(solve_total(MB)) void solve_kernel(PencilDesc P, in
           qs += qu;
         }
         if (qs > 0) {
-          // the group's other rows now; the rows above and below at the end of the group
-          for (int i = g0; i <= g1; ++i) {
+          // the unsolved rows now, the group's solved rows in LDS; the rows above and below
+          // the group at its end
+#pragma unroll
+          for (int k = 0; k < G; ++k) stk[k] = cscl(stk[k], qs);
+          for (int i = q + 1; i <= g1; ++i) {
             Y[i * LDY + lc] = ldexp(Y[i * LDY + lc], -qs);
             if (pair) Y[i * LDY + lc + 1] = ldexp(Y[i * LDY + lc + 1], -qs);
           }
@@ -326,25 +349,29 @@ __global__ __launch_bounds__(solve_total(MB)) void solve_kernel(PencilDesc P, in
           Y[q * LDY + lc] = z1.r;
           if (pair) Y[q * LDY + lc + 1] = z1.i;
         }
-        if (q0 > g0) {
-          // y -= S (beta z) - T (alpha z), real and imaginary parts
-          const Cx u0 = cx(be * z0.r, be * z0.i), u1 = cx(be * z1.r, be * z1.i);
-          const Cx v0 = cx(a * z0.r - b * z0.i, a * z0.i + b * z0.r);
-          const Cx v1 = cx(a * z1.r - b * z1.i, a * z1.i + b * z1.r);
-          for (int i = g0; i < q0; ++i) {
-            const int li = i - g0;
-            const double s0 = Sg[li][lq0], t0 = Tg[li][lq0];
-            double dr = s0 * u0.r - t0 * v0.r, di = s0 * u0.i - t0 * v0.i;
-            if (nb == 2) {
-              const double s1 = Sg[li][lq], t1 = Tg[li][lq];
-              dr += s1 * u1.r - t1 * v1.r;
-              di += s1 * u1.i - t1 * v1.i;
-            }
-            Y[i * LDY + lc] -= dr;
-            if (pair) Y[i * LDY + lc + 1] -= di;
-          }
-        }
         if (q0 > 0) ybound += cn * fmax(cn1(z0), cn1(z1));
+      }
+      // pop the block; stk[k] is now row q0 - 1 - k
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        const Cx s1 = k + 1 < G ? stk[k + 1] : cx(0.0, 0.0);
+        const Cx s2 = k + 2 < G ? stk[k + 2] : cx(0.0, 0.0);
+        stk[k] = nb == 1 ? s1 : s2;
+      }
+      if (work) {
+        // y -= S (beta z) - T (alpha z) on the rows above the block (real and imaginary
+        // parts); entries above the group are scratch
+        const Cx u0 = cx(be * z0.r, be * z0.i), u1 = cx(be * z1.r, be * z1.i);
+        const Cx v0 = cx(a * z0.r - b * z0.i, a * z0.i + b * z0.r);
+        const Cx v1 = cx(a * z1.r - b * z1.i, a * z1.i + b * z1.r);
+#pragma unroll
+        for (int k = 0; k < G - 1; ++k) {
+          double dr = sc0[k] * u0.r - tc0[k] * v0.r, di = sc0[k] * u0.i - tc0[k] * v0.i;
+          dr += sc1[k] * u1.r - tc1[k] * v1.r;   // (z1 = 0 for a 1x1 block)
+          di += sc1[k] * u1.i - tc1[k] * v1.i;
+          stk[k].r -= dr;
+          stk[k].i -= di;
+        }
       }
       q = q0 - 1;
     }
