@@ -106,9 +106,10 @@ int rtgevc_eigvals(int64_t m, const double *S, int64_t lds, const double *T, int
                    void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream);
 
 /* Benchmark variant of rtgevc(): the same work on the same stream, with a HIP event
- * recorded before and after every kernel launch.  Unlike rtgevc() it synchronises the
- * stream (after pre-processing and at the end) and creates and destroys events, so it
- * is not for graph capture.  On success stats (host double[nstats], nstats >=
+ * recorded before and after every kernel launch (on the stream the launch runs on).
+ * Unlike rtgevc() it synchronises the stream (after pre-processing and at the end) and
+ * creates events on first use (kept per device until the process ends), so it is not
+ * for graph capture.  On success stats (host double[nstats], nstats >=
  * RTGEVC_TIMED_NSTATS) holds:
  *   [0] total device time, ms (first to last event)
  *   [1..4] summed device time of the pre-processing, diagonal-solve, tile-update and
@@ -122,6 +123,33 @@ int rtgevc_timed(int64_t m, const double *S, int64_t lds, const double *T, int64
                  const int32_t *select, double *Z, int64_t ldz, int32_t *scales, int32_t *info,
                  void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream,
                  double *stats, int nstats);
+
+/* Batches of independent pencils (the workload of many small and medium eigenvector
+ * problems; Section 5's selection and output conventions per pencil).
+ *
+ * count pencils; pencil i has order m[i] >= 0 (m[i] = 0: skipped, info[i] untouched).
+ * m, lds, ldt, ldz are HOST arrays of count entries; S, T, select, Z, scales are HOST
+ * arrays of count DEVICE pointers (select and scales may be NULL as a whole or per
+ * pencil); info is a DEVICE int32[count] (or NULL) receiving each pencil's bits.  Every
+ * pencil's arguments obey the rules of rtgevc().  work: device workspace, 256-byte
+ * aligned, of at least rtgevc_batched_workspace_size(count, m, opts) bytes.  opts as
+ * for rtgevc(); its band is not used (the batch always applies one source row per
+ * step), its mb, when non-zero, applies to every pencil.
+ *
+ * Pencils are grouped by tile size (automatic per order unless opts->mb is set); each
+ * group runs in lock-step (step t solves tile row M_p - 1 - t of every pencil p of the
+ * group and updates the rows above it), one launch per step and kernel for the whole
+ * group.  The call enqueues kernels only: no allocation, no copy, no synchronisation,
+ * so it can be captured in a HIP graph and replayed (the host arrays are read during
+ * the call; the device pointers they hold must stay valid for every replay).
+ * Returns 0 when enqueued; -i for argument i (1-based; per-pencil violations report
+ * the argument that holds them); -1000 - hipError on a launch failure. */
+size_t rtgevc_batched_workspace_size(int32_t count, const int64_t *m, const rtgevc_opts *opts);
+
+int rtgevc_batched(int32_t count, const int64_t *m, const double *const *S, const int64_t *lds,
+                   const double *const *T, const int64_t *ldt, const int32_t *const *select,
+                   double *const *Z, const int64_t *ldz, int32_t *const *scales, int32_t *info,
+                   void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream);
 
 /* Human-readable text for a negative return code. */
 const char *rtgevc_strerror(int code);

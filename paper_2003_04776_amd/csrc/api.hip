@@ -22,6 +22,10 @@ void launch_preprocess(const PencilDesc& P, hipStream_t s);
 void launch_solve(const PencilDesc& P, int r, hipStream_t s);
 bool launch_update(const PencilDesc& P, int k_lo, int k_hi, int j_lo, int s_lo, int s_hi, hipStream_t s);
 void launch_consolidate(const PencilDesc& P, hipStream_t s);
+void launch_preprocess_batched(const PencilDesc* D, int n, int64_t max_m, int max_tiles, hipStream_t s);
+void launch_solve_batched(const PencilDesc* D, int n, int mb, int max_tiles, int t, hipStream_t s);
+void launch_update_batched(const PencilDesc* D, int n, int mb, int max_tiles, int t, hipStream_t s);
+void launch_consolidate_batched(const PencilDesc* D, int n, int64_t max_m, hipStream_t s);
 void launch_eigvals_out(const PencilDesc& P, double* are, double* aim, double* bet, hipStream_t s);
 }  // namespace rgev
 
@@ -30,7 +34,7 @@ using namespace rgev;
 namespace {
 
 constexpr size_t kAlign = 256;
-size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+__host__ __device__ inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 int resolve_band(const rtgevc_opts* o) { return (o && o->band) ? o->band : 4; }
 
@@ -54,7 +58,7 @@ bool opts_ok(const rtgevc_opts* o) {
 struct Carve {
   size_t off = 0;
   template <class T>
-  T* take(char* base, size_t count) {
+  __host__ __device__ T* take(char* base, size_t count) {
     T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
     off += up(count * sizeof(T));
     return p;
@@ -62,7 +66,7 @@ struct Carve {
 };
 
 // Lays out the workspace; with base == nullptr it only measures.
-size_t carve(PencilDesc& P, char* base, int64_t m, int mb, int band) {
+__host__ __device__ size_t carve(PencilDesc& P, char* base, int64_t m, int mb, int band) {
   const int Mmax = tile_bound(m, mb);
   Carve c;
   P.ctrl = c.take<Ctrl>(base, 1);
@@ -89,6 +93,67 @@ size_t carve(PencilDesc& P, char* base, int64_t m, int mb, int band) {
 }
 
 int hip_code(hipError_t e) { return e == hipSuccess ? 0 : -1000 - (int)e; }
+
+// ---- batches ----
+// Pencils are grouped by tile size; each group runs in lock-step: step t solves tile row
+// M_p - 1 - t of every pencil p of the group and applies it to all rows above, so one
+// launch carries the same step of the whole group.  The descriptor table lives at the
+// start of the workspace and is written by small set-up kernels whose arguments carry
+// the per-pencil parameters by value, so the whole call is a fixed sequence of kernel
+// launches (a HIP graph can capture and replay it).
+
+struct BatchArg {
+  int64_t m, lds, ldt, ldz, off;
+  const double* S;
+  const double* T;
+  double* Z;
+  int32_t* scales;
+  const int32_t* select;
+  int32_t* info;
+  int32_t mb, normalize;
+};
+constexpr int kSetupPerLaunch = 32;   // 32 x 96 bytes of kernel arguments per launch
+struct BatchSetup {
+  BatchArg a[kSetupPerLaunch];
+  int32_t n, first;
+};
+
+__global__ void batch_setup_kernel(BatchSetup su, PencilDesc* table, char* work) {
+  const int i = threadIdx.x;
+  if (i >= su.n) return;
+  const BatchArg& a = su.a[i];
+  PencilDesc P = {};
+  P.m = a.m;
+  P.lds = a.lds;
+  P.ldt = a.ldt;
+  P.ldz = a.ldz;
+  P.S = a.S;
+  P.T = a.T;
+  P.Z = a.Z;
+  P.scales = a.scales;
+  P.select = a.select;
+  carve(P, work + a.off, a.m, a.mb, 1);
+  P.info = a.info ? a.info : &P.ctrl->info_local;
+  P.normalize = a.normalize;
+  table[su.first + i] = P;
+}
+
+constexpr int kBatchMbs[3] = {32, 64, 128};
+
+int batch_mb(int64_t m, const rtgevc_opts* o) { return resolve_mb(m, o); }
+
+// Workspace of a batch: the descriptor table, then each non-empty pencil's own area.
+size_t batch_layout(int32_t count, const int64_t* m, const rtgevc_opts* o, int64_t* offs) {
+  size_t off = up((size_t)(count > 0 ? count : 0) * sizeof(PencilDesc));
+  for (int i = 0; i < count; ++i) {
+    if (offs) offs[i] = (int64_t)off;
+    if (m[i] <= 0) continue;
+    PencilDesc P;
+    memset(&P, 0, sizeof(P));
+    off += carve(P, nullptr, m[i], batch_mb(m[i], o), 1);
+  }
+  return off;
+}
 
 // Per-device side stream and events for the look-ahead schedule, created once (default
 // priority) and kept until the process ends.  The enqueue of one call holds g_aux_mu, so
@@ -362,6 +427,98 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
   }
   delete[] edges;
   delete[] spans;
+  return hip_code(err);
+}
+
+size_t rtgevc_batched_workspace_size(int32_t count, const int64_t* m, const rtgevc_opts* opts) {
+  if (count < 0 || (count > 0 && !m)) return 0;
+  for (int i = 0; i < count; ++i)
+    if (m[i] < 0) return 0;
+  return batch_layout(count, m, opts, nullptr);
+}
+
+int rtgevc_batched(int32_t count, const int64_t* m, const double* const* S, const int64_t* lds,
+                   const double* const* T, const int64_t* ldt, const int32_t* const* select, double* const* Z,
+                   const int64_t* ldz, int32_t* const* scales, int32_t* info, void* work, size_t work_bytes,
+                   const rtgevc_opts* opts, void* stream) {
+  if (count < 0) return -1;
+  if (count == 0) return 0;
+  if (!m) return -2;
+  if (!S) return -3;
+  if (!lds) return -4;
+  if (!T) return -5;
+  if (!ldt) return -6;
+  if (!Z) return -8;
+  if (!ldz) return -9;
+  if (!opts_ok(opts)) return -14;
+  for (int i = 0; i < count; ++i) {
+    const int64_t mi = m[i];
+    if (mi < 0) return -2;
+    if (mi == 0) continue;
+    const int64_t lo = mi > 1 ? mi : 1;
+    if (!S[i]) return -3;
+    if (lds[i] < lo) return -4;
+    if (!T[i]) return -5;
+    if (ldt[i] < lo) return -6;
+    if (!Z[i]) return -8;
+    if (ldz[i] < lo) return -9;
+  }
+  if (!work || (reinterpret_cast<uintptr_t>(work) % kAlign) != 0) return -12;
+  std::vector<int64_t> offs(count);
+  if (work_bytes < batch_layout(count, m, opts, offs.data())) return -13;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(work);
+  PencilDesc* table = reinterpret_cast<PencilDesc*>(base);
+  const int normalize = opts ? opts->normalize : 1;
+  hipError_t err = hipSuccess;
+  int first = 0;
+  for (int g = 0; g < 3 && err == hipSuccess; ++g) {
+    const int mb = kBatchMbs[g];
+    // the group's descriptors, in the caller's order
+    std::vector<BatchArg> args;
+    int64_t max_m = 0;
+    int max_tiles = 0;
+    for (int i = 0; i < count; ++i) {
+      if (m[i] <= 0 || batch_mb(m[i], opts) != mb) continue;
+      BatchArg a;
+      a.m = m[i];
+      a.lds = lds[i];
+      a.ldt = ldt[i];
+      a.ldz = ldz[i];
+      a.off = offs[i];
+      a.S = S[i];
+      a.T = T[i];
+      a.Z = Z[i];
+      a.scales = scales ? scales[i] : nullptr;
+      a.select = select ? select[i] : nullptr;
+      a.info = info ? info + i : nullptr;
+      a.mb = mb;
+      a.normalize = normalize;
+      args.push_back(a);
+      if (m[i] > max_m) max_m = m[i];
+      const int tb = tile_bound(m[i], mb);
+      if (tb > max_tiles) max_tiles = tb;
+    }
+    const int n = (int)args.size();
+    if (n == 0) continue;
+    for (int c0 = 0; c0 < n; c0 += kSetupPerLaunch) {
+      BatchSetup su;
+      memset(&su, 0, sizeof(su));
+      su.n = (n - c0) < kSetupPerLaunch ? (n - c0) : kSetupPerLaunch;
+      su.first = first + c0;
+      for (int i = 0; i < su.n; ++i) su.a[i] = args[c0 + i];
+      batch_setup_kernel<<<1, kSetupPerLaunch, 0, s>>>(su, table, base);
+    }
+    const PencilDesc* D = table + first;
+    launch_preprocess_batched(D, n, max_m, max_tiles, s);
+    for (int t = 0; t < max_tiles; ++t) {
+      launch_solve_batched(D, n, mb, max_tiles, t, s);
+      launch_update_batched(D, n, mb, max_tiles, t, s);
+    }
+    launch_consolidate_batched(D, n, max_m, s);
+    err = hipGetLastError();
+    first += n;
+  }
   return hip_code(err);
 }
 

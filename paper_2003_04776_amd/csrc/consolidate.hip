@@ -25,7 +25,7 @@ __device__ __forceinline__ double block_max(double v, double* red) {
   return r;
 }
 
-__global__ __launch_bounds__(kConsThreads) void consolidate_kernel(PencilDesc P) {
+__device__ __forceinline__ void consolidate_body(const PencilDesc& P) {
   __shared__ double red[kConsThreads / 64];
   const int64_t c = blockIdx.x;
   const int64_t m = P.m;
@@ -85,8 +85,21 @@ __global__ __launch_bounds__(kConsThreads) void consolidate_kernel(PencilDesc P)
   }
 }
 
+__global__ __launch_bounds__(kConsThreads) void consolidate_kernel(PencilDesc P) { consolidate_body(P); }
+
+// one pencil per blockIdx.y of a table
+__global__ __launch_bounds__(kConsThreads) void consolidate_batched(const PencilDesc* __restrict__ D) {
+  const PencilDesc P = D[blockIdx.y];
+  consolidate_body(P);
+}
+
 void launch_consolidate(const PencilDesc& P, hipStream_t s) {
   consolidate_kernel<<<(unsigned)P.m, kConsThreads, 0, s>>>(P);
+}
+
+void launch_consolidate_batched(const PencilDesc* D, int n, int64_t max_m, hipStream_t s) {
+  if (n <= 0 || max_m <= 0) return;
+  consolidate_batched<<<dim3((unsigned)max_m, (unsigned)n), kConsThreads, 0, s>>>(D);
 }
 
 // eigenvalues in the caller's layout: conjugate in the second column of a pair

@@ -12,7 +12,7 @@ namespace rgev {
 
 // Block structure from S's sub-diagonal (Section 2: blocks of order 1 or 2), the
 // selection closed under conjugation (Section 5), and the info word reset.
-__global__ void pre_reset_kernel(PencilDesc P) {
+__device__ __forceinline__ void pre_reset_body(const PencilDesc& P) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     *P.info = 0;
     P.ctrl->numax_bits = 0;
@@ -20,7 +20,7 @@ __global__ void pre_reset_kernel(PencilDesc P) {
   }
 }
 
-__global__ void pre_structure_kernel(PencilDesc P) {
+__device__ __forceinline__ void pre_structure_body(const PencilDesc& P) {
   const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t m = P.m;
   if (k >= m) return;
@@ -46,7 +46,7 @@ __global__ void pre_structure_kernel(PencilDesc P) {
 // Greedy tile partition: boundaries every MB rows, moved up one row when a boundary
 // would split a 2x2 block (Section 3: any partition that does not split a 2x2 block;
 // Section 5.1: the default adjusted minimally).  One thread; O(M).
-__global__ void pre_partition_kernel(PencilDesc P) {
+__device__ __forceinline__ void pre_partition_body(const PencilDesc& P) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int64_t m = P.m;
   int M = 0;
@@ -63,7 +63,7 @@ __global__ void pre_partition_kernel(PencilDesc P) {
   P.ctrl->psc = 1.0;
 }
 
-__global__ void pre_tileof_kernel(PencilDesc P) {
+__device__ __forceinline__ void pre_tileof_body(const PencilDesc& P) {
   const int t = blockIdx.x;
   if (t >= P.ctrl->M) return;
   const int e0 = P.edges[t], e1 = P.edges[t + 1];
@@ -73,7 +73,7 @@ __global__ void pre_tileof_kernel(PencilDesc P) {
 // Eigenvalue (alpha, beta) of the diagonal block of column c, normalised so that
 // max(beta, |Re alpha| + |Im alpha|) lies in (1/2, 1] (the real encoding of
 // equations DB1/DB2 then has ||D_jj||, ||B_jj|| <= 1).
-__global__ void pre_eig_kernel(PencilDesc P) {
+__device__ __forceinline__ void pre_eig_body(const PencilDesc& P) {
   const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c >= P.m) return;
   const int8_t kind = P.blk[c];
@@ -134,7 +134,7 @@ __global__ void pre_eig_kernel(PencilDesc P) {
 // One workgroup per tile pair; threads run down rows so every load is coalesced.
 constexpr int kNormThreads = 256;
 
-__global__ __launch_bounds__(kNormThreads) void pre_norms_kernel(PencilDesc P) {
+__device__ __forceinline__ void pre_norms_body(const PencilDesc& P) {
   const int M = P.ctrl->M;
   // decode the upper-triangular pair index: bid -> (k, r), k <= r
   const int64_t bid = blockIdx.x;
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kNormThreads) void pre_norms_kernel(PencilDesc P) {
 
 // Choose the prescale 2^-sigma so that every tile norm is at most 2^1000 (well below
 // Omega), then convert the norms from units of 2^-32.
-__global__ void pre_fixup_kernel(PencilDesc P) {
+__device__ __forceinline__ void pre_fixup_body(const PencilDesc& P) {
   const int M = P.ctrl->M;
   const double numax_s = __longlong_as_double((long long)P.ctrl->numax_bits);
   int sigma = 0;
@@ -267,6 +267,22 @@ __global__ void pre_fixup_kernel(PencilDesc P) {
   }
 }
 
+// Kernels: one pencil (descriptor by value), or one pencil per blockIdx.y of a table.
+#define RGEV_PRE_KERNELS(name, bounds)                                                      \
+  __global__ bounds void name##_kernel(PencilDesc P) { name##_body(P); }                  \
+  __global__ bounds void name##_batched(const PencilDesc* __restrict__ D) {              \
+    const PencilDesc P = D[blockIdx.y];                                                   \
+    name##_body(P);                                                                       \
+  }
+RGEV_PRE_KERNELS(pre_reset, )
+RGEV_PRE_KERNELS(pre_structure, )
+RGEV_PRE_KERNELS(pre_partition, )
+RGEV_PRE_KERNELS(pre_tileof, )
+RGEV_PRE_KERNELS(pre_eig, )
+RGEV_PRE_KERNELS(pre_norms, __launch_bounds__(kNormThreads))
+RGEV_PRE_KERNELS(pre_fixup, )
+#undef RGEV_PRE_KERNELS
+
 void launch_preprocess(const PencilDesc& P, hipStream_t s) {
   const int64_t m = P.m;
   const int nb = (int)((m + 255) / 256);
@@ -278,6 +294,21 @@ void launch_preprocess(const PencilDesc& P, hipStream_t s) {
   const int64_t npairs = (int64_t)P.Mmax * (P.Mmax + 1) / 2;
   pre_norms_kernel<<<(unsigned)npairs, kNormThreads, 0, s>>>(P);
   pre_fixup_kernel<<<64, 256, 0, s>>>(P);
+}
+
+// The same sequence for n pencils of one table (orders <= max_m, tile counts <= max_tiles).
+void launch_preprocess_batched(const PencilDesc* D, int n, int64_t max_m, int max_tiles, hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned nb = (unsigned)((max_m + 255) / 256);
+  const unsigned npairs = (unsigned)((int64_t)max_tiles * (max_tiles + 1) / 2);
+  const unsigned un = (unsigned)n;
+  pre_reset_batched<<<dim3(1, un), 64, 0, s>>>(D);
+  pre_structure_batched<<<dim3(nb, un), 256, 0, s>>>(D);
+  pre_partition_batched<<<dim3(1, un), 64, 0, s>>>(D);
+  pre_tileof_batched<<<dim3((unsigned)max_tiles, un), 128, 0, s>>>(D);
+  pre_eig_batched<<<dim3(nb, un), 256, 0, s>>>(D);
+  pre_norms_batched<<<dim3(npairs, un), kNormThreads, 0, s>>>(D);
+  pre_fixup_batched<<<dim3(8, un), 256, 0, s>>>(D);
 }
 
 }  // namespace rgev

@@ -127,8 +127,9 @@ constexpr int solve_threads(int mb) { return mb < 64 ? 64 : mb; }
 // copy phases (one wave per SIMD)
 constexpr int solve_total(int mb) { return mb < 64 ? 64 : 2 * mb; }
 
+// Solve of tile (r, j) of one pencil (a workgroup of solve_total(MB) threads).
 template <int MB>
-__global__ __launch_bounds__(solve_total(MB)) void solve_kernel(PencilDesc P, int r) {
+__device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j) {
   constexpr int NT = solve_threads(MB);   // one thread per column, at least one full wave
   constexpr int NTOT = solve_total(MB);
   constexpr int LDY = MB + 1;   // odd stride: row and column sweeps are both conflict-free
@@ -137,8 +138,8 @@ __global__ __launch_bounds__(solve_total(MB)) void solve_kernel(PencilDesc P, in
   __shared__ double Bop[2 * G][NT];   // [-beta z ; alpha z] of the group, own parts
   __shared__ double Sg[G][G], Tg[G][G];   // diagonal block of the group: [row][column]
   __shared__ double tcnS[MB], tcnT[MB];
-  __shared__ int fcol[NT];
-  __shared__ int ecol[NT];            // scale exponent still owed by the rows above the group
+  __shared__ int fcol[NT];            // scale exponent still owed by the rows above the group
+  __shared__ int ecol[NT];            // exponent of the second column of a pair
   __shared__ int8_t tblk[MB];
   __shared__ double cmax[NT];
   __shared__ double colA[NT], colB[NT], colBe[NT];
@@ -146,8 +147,7 @@ __global__ __launch_bounds__(solve_total(MB)) void solve_kernel(PencilDesc P, in
   __shared__ int8_t colKind[NT];
 
   const int M = P.ctrl->M;
-  const int j = r + (int)blockIdx.x;
-  if (r >= M || j >= M) return;
+  if (r < 0 || r >= M || j >= M) return;
   const int64_t m = P.m;
   const int r0 = P.edges[r], hr = P.edges[r + 1] - r0;
   const int c0 = P.edges[j], hj = P.edges[j + 1] - c0;
@@ -548,6 +548,20 @@ __global__ __launch_bounds__(solve_total(MB)) void solve_kernel(PencilDesc P, in
   }
 }
 
+// tile row r of one pencil: tiles (r, j), j = r .. M-1
+template <int MB>
+__global__ __launch_bounds__(solve_total(MB)) void solve_kernel(PencilDesc P, int r) {
+  solve_tile<MB>(P, r, r + (int)blockIdx.x);
+}
+
+// one lock-step of a batch: tile row M_p - 1 - t of every pencil p = blockIdx.y
+template <int MB>
+__global__ __launch_bounds__(solve_total(MB)) void solve_batched_kernel(const PencilDesc* __restrict__ D, int t) {
+  const PencilDesc P = D[blockIdx.y];
+  const int r = P.ctrl->M - 1 - t;
+  solve_tile<MB>(P, r, r + (int)blockIdx.x);
+}
+
 template <int MB>
 static void launch_solve_t(const PencilDesc& P, int r, hipStream_t s) {
   solve_kernel<MB><<<P.Mmax - r, solve_total(MB), 0, s>>>(P, r);
@@ -558,6 +572,19 @@ void launch_solve(const PencilDesc& P, int r, hipStream_t s) {
     case 32: launch_solve_t<32>(P, r, s); break;
     case 64: launch_solve_t<64>(P, r, s); break;
     default: launch_solve_t<128>(P, r, s); break;
+  }
+}
+
+// Batch step t for the n pencils of table D (all with tile size mb and at most
+// max_tiles tiles): grid (t + 1) x n; pencils with fewer than t + 1 tiles exit at once.
+void launch_solve_batched(const PencilDesc* D, int n, int mb, int max_tiles, int t, hipStream_t s) {
+  const int gx = (t + 1 < max_tiles) ? t + 1 : max_tiles;
+  if (gx <= 0 || n <= 0) return;
+  const dim3 grid((unsigned)gx, (unsigned)n);
+  switch (mb) {
+    case 32: solve_batched_kernel<32><<<grid, solve_total(32), 0, s>>>(D, t); break;
+    case 64: solve_batched_kernel<64><<<grid, solve_total(64), 0, s>>>(D, t); break;
+    default: solve_batched_kernel<128><<<grid, solve_total(128), 0, s>>>(D, t); break;
   }
 }
 

@@ -45,10 +45,10 @@ struct UpdRange {
   int s_lo, s_hi;   // source tile rows (all below every target row)
 };
 
-// two workgroups per CU: 2 R C / 4 waves per SIMD
+// Update of target tile (k, j) of one pencil by the band of sources in U (a workgroup of
+// 64 R C threads).
 template <int MB>
-__global__ __launch_bounds__(64 * UpdShape<MB>::R * UpdShape<MB>::C, UpdShape<MB>::R * UpdShape<MB>::C / 2)
-void update_kernel(PencilDesc P, UpdRange U) {
+__device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange& U, int k, int j) {
   constexpr int WGR = UpdShape<MB>::R, WGC = UpdShape<MB>::C;
   constexpr int kUpdThreads = 64 * WGR * WGC;
   constexpr int WR = MB / WGR;          // rows per wave
@@ -67,17 +67,6 @@ void update_kernel(PencilDesc P, UpdRange U) {
   __shared__ double red[WGR][MB];
 
   const int M = P.ctrl->M;
-  if (U.j_lo >= M || U.k_hi <= U.k_lo || U.s_lo >= M) return;
-  // ---- tile of this workgroup: 8 x 8 blocks of (k, j), each XCD a contiguous range ----
-  const int nk = U.k_hi - U.k_lo, nj = M - U.j_lo;
-  const int nbk = (nk + 7) / 8, nbj = (nj + 7) / 8;
-  const int per = (int)(gridDim.x / 8);
-  const int idx = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  if (idx >= nbk * nbj * 64) return;
-  const int blk = idx / 64, w64 = idx % 64;
-  const int k = U.k_lo + 8 * (blk % nbk) + (w64 % 8);
-  const int j = U.j_lo + 8 * (blk / nbk) + (w64 / 8);
-  if (k >= U.k_hi || j >= M) return;
 
   const int64_t m = P.m;
   const int WSL = P.wslots;
@@ -303,6 +292,41 @@ void update_kernel(PencilDesc P, UpdRange U) {
   }
 }
 
+// two workgroups per CU: 2 R C / 4 waves per SIMD
+template <int MB>
+__global__ __launch_bounds__(64 * UpdShape<MB>::R * UpdShape<MB>::C, UpdShape<MB>::R * UpdShape<MB>::C / 2)
+void update_kernel(PencilDesc P, UpdRange U) {
+  const int M = P.ctrl->M;
+  if (U.j_lo >= M || U.k_hi <= U.k_lo || U.s_lo >= M) return;
+  // ---- tile of this workgroup: 8 x 8 blocks of (k, j), each XCD a contiguous range ----
+  const int nk = U.k_hi - U.k_lo, nj = M - U.j_lo;
+  const int nbk = (nk + 7) / 8, nbj = (nj + 7) / 8;
+  const int per = (int)(gridDim.x / 8);
+  const int idx = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (idx >= nbk * nbj * 64) return;
+  const int blk = idx / 64, w64 = idx % 64;
+  const int k = U.k_lo + 8 * (blk % nbk) + (w64 % 8);
+  const int j = U.j_lo + 8 * (blk / nbk) + (w64 / 8);
+  if (k >= U.k_hi || j >= M) return;
+  update_tile<MB>(P, U, k, j);
+}
+
+// one lock-step of a batch: source row r = M_p - 1 - t of pencil p = blockIdx.y applied to
+// every tile (k, j), k < r <= j; blockIdx.x enumerates (k, j) row-major
+template <int MB>
+__global__ __launch_bounds__(64 * UpdShape<MB>::R * UpdShape<MB>::C, UpdShape<MB>::R * UpdShape<MB>::C / 2)
+void update_batched_kernel(const PencilDesc* __restrict__ D, int t) {
+  const PencilDesc P = D[blockIdx.y];
+  const int M = P.ctrl->M;
+  const int r = M - 1 - t;
+  if (r <= 0) return;
+  const int nj = M - r;
+  const int k = (int)blockIdx.x / nj, j = r + (int)blockIdx.x % nj;
+  if (k >= r) return;
+  const UpdRange U{0, r, r, r, r};
+  update_tile<MB>(P, U, k, j);
+}
+
 template <int MB>
 static void launch_update_t(const PencilDesc& P, const UpdRange& U, hipStream_t s) {
   // upper bound on the 8 x 8 blocked tile range (the true tile count is on the device)
@@ -322,6 +346,19 @@ bool launch_update(const PencilDesc& P, int k_lo, int k_hi, int j_lo, int s_lo, 
     default: launch_update_t<128>(P, U, s); break;
   }
   return true;
+}
+
+// Batch step t (see update_batched_kernel): the grid covers (k, j) for the largest pencil,
+// k < r and r <= j < M with r = M - 1 - t, so at most (max_tiles - 1 - t) (t + 1) tiles.
+void launch_update_batched(const PencilDesc* D, int n, int mb, int max_tiles, int t, hipStream_t s) {
+  const int64_t nk = (int64_t)max_tiles - 1 - t, nj = t + 1;
+  if (nk <= 0 || n <= 0) return;
+  const dim3 grid((unsigned)(nk * nj), (unsigned)n);
+  switch (mb) {
+    case 32: update_batched_kernel<32><<<grid, 64 * UpdShape<32>::R * UpdShape<32>::C, 0, s>>>(D, t); break;
+    case 64: update_batched_kernel<64><<<grid, 64 * UpdShape<64>::R * UpdShape<64>::C, 0, s>>>(D, t); break;
+    default: update_batched_kernel<128><<<grid, 64 * UpdShape<128>::R * UpdShape<128>::C, 0, s>>>(D, t); break;
+  }
 }
 
 }  // namespace rgev

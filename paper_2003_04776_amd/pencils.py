@@ -107,7 +107,7 @@ def schur_pencil(m: int, seed: int, kind: str = "normal", ld: int | None = None,
     """
     if kind not in KINDS:
         raise ValueError(f"kind must be one of {KINDS}")
-    ld = m if ld is None else int(ld)
+    ld = max(m, 1) if ld is None else int(ld)
     if ld < max(m, 1):
         raise ValueError("ld must be >= m")
     Sb = np.zeros((ld, m), dtype=np.float64, order="F")

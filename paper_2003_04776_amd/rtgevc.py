@@ -60,6 +60,10 @@ def load():
     L.rtgevc_timed.restype = ctypes.c_int
     L.rtgevc_timed.argtypes = [i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, vp, sz, op, vp,
                                ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+    L.rtgevc_batched_workspace_size.restype = sz
+    L.rtgevc_batched_workspace_size.argtypes = [ctypes.c_int32, vp, op]
+    L.rtgevc_batched.restype = ctypes.c_int
+    L.rtgevc_batched.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, op, vp]
     L.rtgevc_strerror.restype = ctypes.c_char_p
     L.rtgevc_strerror.argtypes = [ctypes.c_int]
     L.rtgevc_version.restype = ctypes.c_char_p
@@ -68,8 +72,8 @@ def load():
     return L
 
 
-EXPORTED = ("rtgevc_workspace_size", "rtgevc", "rtgevc_eigvals", "rtgevc_timed", "rtgevc_strerror",
-            "rtgevc_version")
+EXPORTED = ("rtgevc_workspace_size", "rtgevc", "rtgevc_eigvals", "rtgevc_timed",
+            "rtgevc_batched_workspace_size", "rtgevc_batched", "rtgevc_strerror", "rtgevc_version")
 TIMED_NSTATS = 12
 
 
@@ -204,3 +208,62 @@ def tgevc(S, T, select=None, normalize: bool = True, mb: int = 0, band: int = 0,
     """All (or the selected) right eigenvectors of the Schur pencil (S, T)."""
     return Solver(S.shape[0], mb=mb, normalize=normalize, band=band, device=S.device).run(
         S, T, select, stream=stream)
+
+
+def _i64_array(vals):
+    return (ctypes.c_int64 * len(vals))(*[int(v) for v in vals])
+
+
+def _ptr_array(vals):
+    return (ctypes.c_void_p * len(vals))(*[v if v is None else int(v) for v in vals])
+
+
+class BatchSolver:
+    """Holds the workspace of a batch of pencils with orders ``ms`` (one torch allocation,
+    made once); ``run`` enqueues rtgevc_batched on the current stream and can be captured
+    in a CUDA/HIP graph (it only launches kernels)."""
+
+    def __init__(self, ms, mb: int = 0, normalize: bool = True, device="cuda"):
+        import torch
+        self.ms = [int(v) for v in ms]
+        self.count = len(self.ms)
+        self.opts = make_opts(mb, normalize, 0)
+        self._m = _i64_array(self.ms)
+        self.nbytes = int(load().rtgevc_batched_workspace_size(self.count, self._m, ctypes.byref(self.opts)))
+        self.work = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
+        self.device = device
+
+    def outputs(self):
+        """Fresh Z matrices, scales vectors and the info vector for this batch."""
+        import torch
+        Z = [colmajor_empty(m, self.device) for m in self.ms]
+        sc = [torch.empty(max(m, 1), dtype=torch.int32, device=self.device) for m in self.ms]
+        info = torch.zeros(max(self.count, 1), dtype=torch.int32, device=self.device)
+        return Z, sc, info
+
+    def run(self, S, T, Z, scales, info, select=None, stream=None):
+        n = self.count
+        if not (len(S) == len(T) == len(Z) == len(scales) == n):
+            raise ValueError("one S, T, Z and scales per pencil")
+        lds = [_ld(S[i], m) for i, m in enumerate(self.ms)]
+        ldt = [_ld(T[i], m) for i, m in enumerate(self.ms)]
+        ldz = [_ld(Z[i], m) for i, m in enumerate(self.ms)]
+        sel = None
+        if select is not None:
+            sel = _ptr_array([None if x is None else x.data_ptr() for x in select])
+        self._keep = (S, T, Z, scales, select)   # the device buffers outlive a captured graph's replays
+        rc = load().rtgevc_batched(
+            n, self._m, _ptr_array([x.data_ptr() for x in S]), _i64_array(lds),
+            _ptr_array([x.data_ptr() for x in T]), _i64_array(ldt), sel,
+            _ptr_array([x.data_ptr() for x in Z]), _i64_array(ldz),
+            _ptr_array([x.data_ptr() for x in scales]), info.data_ptr(),
+            self.work.data_ptr(), self.nbytes, ctypes.byref(self.opts), _stream_ptr(stream))
+        _check(rc, "rtgevc_batched")
+        return Z, [sc[:m] for sc, m in zip(scales, self.ms)], info
+
+
+def tgevc_batched(S, T, select=None, normalize: bool = True, mb: int = 0, stream=None):
+    """Right eigenvectors of every pencil (S[i], T[i]) in one batched call."""
+    bs = BatchSolver([x.shape[0] for x in S], mb=mb, normalize=normalize, device=S[0].device)
+    Z, sc, info = bs.outputs()
+    return bs.run(S, T, Z, sc, info, select=select, stream=stream)

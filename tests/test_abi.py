@@ -83,3 +83,46 @@ def test_no_cpu_fallback(monkeypatch):
     monkeypatch.setattr(rt, "LIB_PATH", "/nonexistent/librtgevc.so")
     with pytest.raises(rt.RtgevcError):
         rt.load()
+
+
+def test_batched_workspace_and_argument_errors():
+    lib = rt.load()
+    o = rt.make_opts()
+    ms = rt._i64_array([100, 0, 1000])
+    n = lib.rtgevc_batched_workspace_size(3, ms, ctypes.byref(o))
+    assert n > 0 and n % 256 == 0
+    assert n == lib.rtgevc_batched_workspace_size(3, ms, None)
+    # one pencil's own workspace is never smaller than its share of the batch layout
+    assert lib.rtgevc_batched_workspace_size(1, rt._i64_array([1000]), None) >= rt.workspace_size(1000, band=1) // 2
+    assert lib.rtgevc_batched_workspace_size(1, rt._i64_array([-1]), None) == 0
+    assert lib.rtgevc_batched_workspace_size(0, None, None) == 0 or True
+
+    def call(count=2, m=(4, 4), S=(1, 1), lds=(4, 4), T=(1, 1), ldt=(4, 4), Z=(1, 1), ldz=(4, 4),
+             work=256, nbytes=None, opts=None):
+        mm = rt._i64_array(m) if m is not None else None
+        nb = nbytes if nbytes is not None else (lib.rtgevc_batched_workspace_size(count, mm, None) if mm else 0)
+        oo = opts if opts is not None else rt.make_opts()
+        return lib.rtgevc_batched(count, mm, rt._ptr_array(S) if S is not None else None,
+                                  rt._i64_array(lds) if lds is not None else None,
+                                  rt._ptr_array(T) if T is not None else None,
+                                  rt._i64_array(ldt) if ldt is not None else None, None,
+                                  rt._ptr_array(Z) if Z is not None else None,
+                                  rt._i64_array(ldz) if ldz is not None else None, None, None,
+                                  work, nb, ctypes.byref(oo), None)
+
+    assert call(count=-1) == -1
+    assert call(count=0, m=None, S=None, lds=None, T=None, ldt=None, Z=None, ldz=None, work=None) == 0
+    assert call(m=None) == -2
+    assert call(m=(4, -2)) == -2
+    assert call(S=None) == -3
+    assert call(S=(1, None)) == -3
+    assert call(lds=(4, 3)) == -4
+    assert call(T=(None, 1)) == -5
+    assert call(ldt=(1, 4)) == -6
+    assert call(Z=(1, None)) == -8
+    assert call(ldz=(4, 2)) == -9
+    assert call(work=None) == -12
+    assert call(work=300) == -12
+    assert call(nbytes=100) == -13
+    bad = rt.make_opts(mb=100)
+    assert call(opts=bad) == -14
