@@ -151,6 +151,14 @@ int rtgevc_batched(int32_t count, const int64_t *m, const double *const *S, cons
                    double *const *Z, const int64_t *ldz, int32_t *const *scales, int32_t *info,
                    void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream);
 
+/* The tile size and band a call with these options would use for order m (batched != 0:
+ * as a pencil of rtgevc_batched, whose band is always 1).  The automatic choices come
+ * from a table compiled into the library, written by an autotuning sweep on the GPU
+ * (performance parameters only: every choice computes the same eigenvectors).
+ * out receives mb, band and normalize (reserved fields zero).  Returns 0, -1 (m < 0),
+ * -3 (invalid opts) or -4 (out is NULL).  Host only; touches no GPU. */
+int rtgevc_resolve_opts(int64_t m, int32_t batched, const rtgevc_opts *opts, rtgevc_opts *out);
+
 /* Human-readable text for a negative return code. */
 const char *rtgevc_strerror(int code);
 

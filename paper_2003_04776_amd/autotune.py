@@ -1,0 +1,176 @@
+"""Autotuner: sweeps the performance parameters of the solver on the GPU and writes the
+table the library compiles in.
+
+Parameters are performance choices only — tile size mb and update band R for single
+pencils, tile size per order bucket for batches — never bounds: every choice computes
+the same eigenvectors, so a table from another machine is safe, merely slower.
+
+    python -m paper_2003_04776_amd.autotune [--out-dir DIR] [--quick]
+
+writes DIR/tuning.json (every timing of the sweep) and DIR/tuning_table.inc (the chosen
+entries, in the form csrc/tuning_table.inc expects); copy both into the package (the
+.inc into csrc/) and rebuild.  Inputs are the seeded synthetic pencils of
+``pencils.schur_pencil``.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+SINGLE_SIZES = (256, 1024, 4096, 8192, 32768)
+BATCH_BUCKETS = ((64, 128), (128, 256), (256, 512), (512, 1024), (1024, 2048))
+MBS = (32, 64, 128)
+BANDS = (1, 2, 4, 8)
+
+
+def single_candidates(m):
+    for mb in MBS:
+        if m >= 8192 and mb == 32:
+            continue       # thousands of tile rows: never competitive, and slow to sweep
+        if mb > 2 * m:
+            continue
+        for band in BANDS:
+            yield mb, band
+
+
+def time_single(m, mb, band, Sd, Td, Z, sc, info, reps):
+    from paper_2003_04776_amd import rtgevc as rt
+    solver = rt.Solver(m, mb=mb, band=band)
+    solver.run_timed(Sd, Td, Z, sc, info)          # warm-up (first launch of each kernel)
+    best = math.inf
+    for _ in range(reps):
+        best = min(best, solver.run_timed(Sd, Td, Z, sc, info)["total_ms"])
+    return best
+
+
+def time_batch(ms, mb, Sd, Td, reps):
+    import torch
+    from paper_2003_04776_amd import rtgevc as rt
+    bs = rt.BatchSolver(ms, mb=mb)
+    Z, sc, info = bs.outputs()
+    bs.run(Sd, Td, Z, sc, info)
+    torch.cuda.synchronize()
+    best = math.inf
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        bs.run(Sd, Td, Z, sc, info)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def choose_single(results):
+    """results: {m: {(mb, band): ms}} -> table entries (m_max, mb, band), sizes ascending;
+    each measured size's best choice covers up to the geometric midpoint to the next."""
+    sizes = sorted(results)
+    out = []
+    for i, m in enumerate(sizes):
+        (mb, band), _ = min(results[m].items(), key=lambda kv: kv[1])
+        m_max = int(math.sqrt(m * sizes[i + 1])) if i + 1 < len(sizes) else None
+        out.append((m_max, mb, band))
+    return out
+
+
+def choose_batch(results):
+    """results: {(lo, hi): {mb: ms}} -> entries (m_max, mb), buckets ascending."""
+    buckets = sorted(results)
+    out = []
+    for i, (lo, hi) in enumerate(buckets):
+        mb, _ = min(results[(lo, hi)].items(), key=lambda kv: kv[1])
+        out.append((hi if i + 1 < len(buckets) else None, mb))
+    return out
+
+
+def render_inc(single, batch, source):
+    lines = [
+        "// Performance parameters chosen per problem size (never bounds: every choice computes",
+        "// the same eigenvectors).  Written by paper_2003_04776_amd/autotune.py from a sweep on",
+        f"// the GPU ({source}).",
+        "// Single pencils: the first entry with m <= m_max applies.",
+        "static const TuneSingle kTuneSingle[] = {",
+    ]
+    for m_max, mb, band in single:
+        lines.append(f"    {{{m_max if m_max is not None else 'INT64_MAX'}, {mb}, {band}}},")
+    lines += ["};", "// Pencils of a batch (tile size per order bucket).", "static const TuneBatch kTuneBatch[] = {"]
+    for m_max, mb in batch:
+        lines.append(f"    {{{m_max if m_max is not None else 'INT64_MAX'}, {mb}}},")
+    lines.append("};")
+    return "\n".join(lines) + "\n"
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--out-dir", default=HERE)
+    ap.add_argument("--quick", action="store_true", help="smaller sweep (sizes up to 8192)")
+    ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--batch-count", type=int, default=64)
+    args = ap.parse_args()
+
+    import numpy as np
+    import torch
+
+    from paper_2003_04776_amd import pencils
+    from paper_2003_04776_amd import rtgevc as rt
+
+    dev = torch.cuda.get_device_properties(0)
+    record = {"device": dev.name, "gcn_arch": getattr(dev, "gcnArchName", ""), "single": {}, "batch": {}}
+    single = {}
+    sizes = [m for m in SINGLE_SIZES if not (args.quick and m > 8192)]
+    for m in sizes:
+        S, T, _ = pencils.schur_pencil(m, 500 + m, threads=16)
+        Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
+        del S, T
+        Z = rt.colmajor_empty(m)
+        sc = torch.empty(m, dtype=torch.int32, device="cuda")
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        single[m] = {}
+        for mb, band in single_candidates(m):
+            t = time_single(m, mb, band, Sd, Td, Z, sc, info, args.reps)
+            single[m][(mb, band)] = t
+            record["single"].setdefault(str(m), {})[f"mb={mb},band={band}"] = round(t, 4)
+            print(f"[tune] single m={m} mb={mb} band={band}: {t:.3f} ms", flush=True)
+        del Sd, Td, Z
+        torch.cuda.empty_cache()
+    batch = {}
+    for bi, (lo, hi) in enumerate(BATCH_BUCKETS):
+        rng = np.random.default_rng(7000 + bi)
+        ms = [int(v) for v in rng.integers(lo, hi, size=args.batch_count)]
+        Sd, Td = [], []
+        for i, m in enumerate(ms):
+            S, T, _ = pencils.schur_pencil(m, 7100 + 100 * bi + i)
+            Sd.append(rt.colmajor_to_device(S))
+            Td.append(rt.colmajor_to_device(T))
+        batch[(lo, hi)] = {}
+        for mb in MBS:
+            if mb > 2 * hi:
+                continue
+            t = time_batch(ms, mb, Sd, Td, args.reps)
+            batch[(lo, hi)][mb] = t
+            record["batch"].setdefault(f"{lo}-{hi}", {})[f"mb={mb}"] = round(t, 4)
+            print(f"[tune] batch [{lo},{hi}) x{len(ms)} mb={mb}: {t:.3f} ms", flush=True)
+        del Sd, Td
+        torch.cuda.empty_cache()
+    ch_single, ch_batch = choose_single(single), choose_batch(batch)
+    record["chosen_single"] = [{"m_max": a, "mb": b, "band": c} for a, b, c in ch_single]
+    record["chosen_batch"] = [{"m_max": a, "mb": b} for a, b in ch_batch]
+    os.makedirs(args.out_dir, exist_ok=True)
+    with open(os.path.join(args.out_dir, "tuning.json"), "w") as f:
+        json.dump(record, f, indent=1)
+    with open(os.path.join(args.out_dir, "tuning_table.inc"), "w") as f:
+        f.write(render_inc(ch_single, ch_batch, f"{dev.name}, {time.strftime('%Y-%m-%d')}"))
+    print(json.dumps({"chosen_single": record["chosen_single"], "chosen_batch": record["chosen_batch"]}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

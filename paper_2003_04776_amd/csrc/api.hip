@@ -36,14 +36,26 @@ namespace {
 constexpr size_t kAlign = 256;
 __host__ __device__ inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-int resolve_band(const rtgevc_opts* o) { return (o && o->band) ? o->band : 4; }
+struct TuneSingle {
+  int64_t m_max;
+  int32_t mb, band;
+};
+struct TuneBatch {
+  int64_t m_max;
+  int32_t mb;
+};
+#include "tuning_table.inc"
 
-int resolve_mb(int64_t m, const rtgevc_opts* o) {
-  if (o && o->mb) return o->mb;
-  if (m <= 96) return 32;
-  if (m <= 384) return 64;
-  return 128;
+const TuneSingle& tune_single(int64_t m) {
+  const int n = (int)(sizeof(kTuneSingle) / sizeof(kTuneSingle[0]));
+  for (int i = 0; i < n - 1; ++i)
+    if (m <= kTuneSingle[i].m_max) return kTuneSingle[i];
+  return kTuneSingle[n - 1];
 }
+
+int resolve_band(int64_t m, const rtgevc_opts* o) { return (o && o->band) ? o->band : tune_single(m).band; }
+
+int resolve_mb(int64_t m, const rtgevc_opts* o) { return (o && o->mb) ? o->mb : tune_single(m).mb; }
 
 bool opts_ok(const rtgevc_opts* o) {
   if (!o) return true;
@@ -140,7 +152,13 @@ __global__ void batch_setup_kernel(BatchSetup su, PencilDesc* table, char* work)
 
 constexpr int kBatchMbs[3] = {32, 64, 128};
 
-int batch_mb(int64_t m, const rtgevc_opts* o) { return resolve_mb(m, o); }
+int batch_mb(int64_t m, const rtgevc_opts* o) {
+  if (o && o->mb) return o->mb;
+  const int n = (int)(sizeof(kTuneBatch) / sizeof(kTuneBatch[0]));
+  for (int i = 0; i < n - 1; ++i)
+    if (m <= kTuneBatch[i].m_max) return kTuneBatch[i].mb;
+  return kTuneBatch[n - 1].mb;
+}
 
 // Workspace of a batch: the descriptor table, then each non-empty pencil's own area.
 size_t batch_layout(int32_t count, const int64_t* m, const rtgevc_opts* o, int64_t* offs) {
@@ -292,7 +310,7 @@ PencilDesc make_desc(int64_t m, const double* S, int64_t lds, const double* T, i
   P.Z = Z;
   P.scales = scales;
   P.select = select;
-  carve(P, static_cast<char*>(work), m, resolve_mb(m, opts), resolve_band(opts));
+  carve(P, static_cast<char*>(work), m, resolve_mb(m, opts), resolve_band(m, opts));
   P.info = info ? info : &P.ctrl->info_local;
   P.normalize = opts ? opts->normalize : 1;
   return P;
@@ -307,7 +325,7 @@ size_t rtgevc_workspace_size(int64_t m, const rtgevc_opts* opts) {
   if (m == 0) return kAlign;
   PencilDesc P;
   memset(&P, 0, sizeof(P));
-  return carve(P, nullptr, m, resolve_mb(m, opts), resolve_band(opts));
+  return carve(P, nullptr, m, resolve_mb(m, opts), resolve_band(m, opts));
 }
 
 int rtgevc(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt, const int32_t* select,
@@ -520,6 +538,22 @@ int rtgevc_batched(int32_t count, const int64_t* m, const double* const* S, cons
     first += n;
   }
   return hip_code(err);
+}
+
+int rtgevc_resolve_opts(int64_t m, int32_t batched, const rtgevc_opts* opts, rtgevc_opts* out) {
+  if (m < 0) return -1;
+  if (!opts_ok(opts)) return -3;
+  if (!out) return -4;
+  memset(out, 0, sizeof(*out));
+  out->normalize = opts ? opts->normalize : 1;
+  if (batched) {
+    out->mb = batch_mb(m, opts);
+    out->band = 1;
+  } else {
+    out->mb = resolve_mb(m, opts);
+    out->band = resolve_band(m, opts);
+  }
+  return 0;
 }
 
 const char* rtgevc_strerror(int code) {

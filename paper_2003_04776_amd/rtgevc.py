@@ -64,6 +64,8 @@ def load():
     L.rtgevc_batched_workspace_size.argtypes = [ctypes.c_int32, vp, op]
     L.rtgevc_batched.restype = ctypes.c_int
     L.rtgevc_batched.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, op, vp]
+    L.rtgevc_resolve_opts.restype = ctypes.c_int
+    L.rtgevc_resolve_opts.argtypes = [i64, ctypes.c_int32, op, op]
     L.rtgevc_strerror.restype = ctypes.c_char_p
     L.rtgevc_strerror.argtypes = [ctypes.c_int]
     L.rtgevc_version.restype = ctypes.c_char_p
@@ -73,7 +75,8 @@ def load():
 
 
 EXPORTED = ("rtgevc_workspace_size", "rtgevc", "rtgevc_eigvals", "rtgevc_timed",
-            "rtgevc_batched_workspace_size", "rtgevc_batched", "rtgevc_strerror", "rtgevc_version")
+            "rtgevc_batched_workspace_size", "rtgevc_batched", "rtgevc_resolve_opts", "rtgevc_strerror",
+            "rtgevc_version")
 TIMED_NSTATS = 12
 
 
@@ -88,6 +91,14 @@ def make_opts(mb: int = 0, normalize: bool = True, band: int = 0) -> Opts:
 def workspace_size(m: int, mb: int = 0, normalize: bool = True, band: int = 0) -> int:
     o = make_opts(mb, normalize, band)
     return int(load().rtgevc_workspace_size(int(m), ctypes.byref(o)))
+
+
+def resolve_opts(m: int, batched: bool = False, mb: int = 0, band: int = 0, normalize: bool = True):
+    """(mb, band) the library would use for order m with these options."""
+    o, out = make_opts(mb, normalize, band), Opts()
+    _check(load().rtgevc_resolve_opts(int(m), 1 if batched else 0, ctypes.byref(o), ctypes.byref(out)),
+           "rtgevc_resolve_opts")
+    return int(out.mb), int(out.band)
 
 
 def strerror(code: int) -> str:

@@ -56,15 +56,17 @@ def _check_pencil(S, T, Zg, select=None, tol=TOL):
     return worst, io
 
 
-def test_batched_parity_mixed_sizes():
-    """Orders spanning the three tile sizes, ragged tails, m = 1 and an empty pencil."""
+@pytest.mark.parametrize("mb", [0, 32, 128])
+def test_batched_parity_mixed_sizes(mb):
+    """Orders from 1 to 1030 (several tiles and ragged tails at every tile size), m = 1 and
+    an empty pencil; automatic (table) and explicit tile sizes."""
     torch = _torch()
     from paper_2003_04776_amd import rtgevc as rt
     ms = [1, 7, 33, 64, 97, 150, 0, 385, 700, 1030, 2, 400]
-    _say(f"[batched] sizes {ms}")
+    _say(f"[batched] mb={mb} sizes {ms}")
     batch = _batch(ms, 3000)
     Sd, Td = _upload(batch)
-    Z, sc, info = rt.tgevc_batched(Sd, Td)
+    Z, sc, info = rt.tgevc_batched(Sd, Td, mb=mb)
     torch.cuda.synchronize()
     info = info.cpu().numpy()
     for i, (S, T, blk) in enumerate(batch):
