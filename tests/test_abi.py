@@ -34,11 +34,13 @@ def test_version_and_strerror():
 
 def test_workspace_size_monotone():
     assert rt.workspace_size(-1) == 0
-    prev = 0
-    for m in (1, 10, 100, 1000, 5000):
-        w = rt.workspace_size(m)
-        assert w >= prev and w % 256 == 0
-        prev = w
+    for mb, band in ((32, 1), (64, 4), (128, 8)):
+        prev = 0
+        for m in (1, 10, 100, 1000, 5000):
+            w = rt.workspace_size(m, mb=mb, band=band)
+            assert w >= prev and w % 256 == 0
+            prev = w
+    assert rt.workspace_size(5000, mb=128, band=4) > rt.workspace_size(5000, mb=128, band=1)
     assert rt.workspace_size(1000, mb=64) != rt.workspace_size(1000, mb=128)
 
 
