@@ -1,565 +1,25 @@
-// Diagonal-tile solves of Algorithm 1 (Section 3): kernel 1 computes the tips Y_jj,
-// the eigenvectors of the small pencil (S_jj, T_jj); kernel 3 solves
-// S_ii Z D_jj - T_ii Z B_jj = Y_ij.  Both are robust back-substitution over the
-// 1x1/2x2 blocks of the diagonal tile (Section 4: every division protected by
-// ProtectDivision, every column update by ProtectUpdate, scale factors as integer
-// exponents).  After the solve, the tile is turned into the right-updated operand of
-// Algorithm 2, W = 2^-g [X D ; -X B], packed for the FP64 matrix instruction.
-//
-// One workgroup per tile (i, j); one thread per eigenvector column of tile j.  The
-// tile Y_ij lives in LDS for the whole solve; the columns of S_ii and T_ii that a step
-// needs are staged into LDS one block ahead.  A complex pair occupies two adjacent
-// threads that both evaluate the complex pivot arithmetic and keep their own part.
+// Kernels of the diagonal solves (the tile body is in solve_tile.hpp): one tile row of
+// one pencil per launch, or one lock-step of a batch.
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
-
-#include "layout.hpp"
-#include "robust.hpp"
+#include "solve_tile.hpp"
 
 namespace rgev {
-
-struct Cx {
-  double r, i;
-};
-__device__ __forceinline__ Cx cx(double r, double i) { return Cx{r, i}; }
-__device__ __forceinline__ Cx cmul(Cx x, Cx y) { return Cx{x.r * y.r - x.i * y.i, x.r * y.i + x.i * y.r}; }
-__device__ __forceinline__ Cx csub(Cx x, Cx y) { return Cx{x.r - y.r, x.i - y.i}; }
-__device__ __forceinline__ double cn1(Cx x) { return fabs(x.r) + fabs(x.i); }
-__device__ __forceinline__ Cx cdivx(Cx x, Cx y) {
-  Cx z;
-  complex_div(x.r, x.i, y.r, y.i, z.r, z.i);
-  return z;
-}
-__device__ __forceinline__ Cx cscl(Cx x, int q) { return q ? Cx{ldexp(x.r, -q), ldexp(x.i, -q)} : x; }
-
-// When a protection has to scale, the solves scale by 2^128 more than the least
-// exponent: any power of two that meets the bound represents the same vector, and the
-// head room makes the next scaling (and its pass over the solved rows) rare even when
-// the eigenvector keeps growing row after row.
-constexpr int kScaleMargin = 128;
-__device__ __forceinline__ int with_margin(int q) { return q > 0 ? q + kScaleMargin : 0; }
-
-// pivot threshold: u times the size of the terms of beta S_qq - alpha T_qq
-__device__ __forceinline__ double local_smin(double be, double aabs, double smax, double tmax) {
-  const double s = kUnitRoundoff * (be * smax + aabs * tmax);
-  return s < kTiny ? kTiny : s;
-}
-
-// (beta s - alpha t) w = y for one row; alpha = a + i b (b = 0 for a real column).
-__device__ __forceinline__ Cx solve1(double a, double b, double be, double s, double t, Cx y, int& qs,
-                                     int& flags) {
-  Cx d = cx(be * s - a * t, -b * t);
-  const double smin = local_smin(be, fabs(a) + fabs(b), fabs(s), fabs(t));
-  if (cn1(d) < smin) {
-    d = cx(smin, 0.0);
-    flags |= kInfoPerturbed;
-  }
-  // |y/d|_1 <= 2 |y|_1 / |d|_1
-  const int q = with_margin(protect_division(cn1(y), 0.5 * cn1(d)));
-  qs += q;
-  return cdivx(cscl(y, q), d);
-}
-
-// 2x2 block: Gaussian elimination with complete pivoting on |.|_1, every division
-// and update protected.  y0, y1 are the block's rows; the solution replaces them.
-// (Written with selects only, so nothing is indexed dynamically.)
-__device__ __forceinline__ void solve2(double a, double b, double be, double s00, double s01, double s10,
-                                       double s11, double t00, double t01, double t11, Cx& y0, Cx& y1,
-                                       int& qs, int& flags) {
-  const Cx C00 = cx(be * s00 - a * t00, -b * t00);
-  const Cx C01 = cx(be * s01 - a * t01, -b * t01);
-  const Cx C10 = cx(be * s10, 0.0);
-  const Cx C11 = cx(be * s11 - a * t11, -b * t11);
-  const double smax = fmax(fmax(fabs(s00), fabs(s01)), fmax(fabs(s10), fabs(s11)));
-  const double tmax = fmax(fmax(fabs(t00), fabs(t01)), fabs(t11));
-  const double smin = local_smin(be, fabs(a) + fabs(b), smax, tmax);
-  const double v00 = cn1(C00), v01 = cn1(C01), v10 = cn1(C10), v11 = cn1(C11);
-  // pivot (ip, jp): the entry of largest |.|_1
-  int ip = 0, jp = 0;
-  double best = v00;
-  if (v01 > best) { best = v01; ip = 0; jp = 1; }
-  if (v10 > best) { best = v10; ip = 1; jp = 0; }
-  if (v11 > best) { best = v11; ip = 1; jp = 1; }
-  Cx u11, u12, c21, c22;
-  if (best < smin) {
-    u11 = cx(smin, 0.0); u12 = cx(0.0, 0.0); c21 = cx(0.0, 0.0); c22 = cx(smin, 0.0);
-    ip = 0; jp = 0;
-    flags |= kInfoPerturbed;
-  } else {
-    // rows/columns permuted so the pivot is (0, 0): u11 = C[ip][jp], u12 = C[ip][1-jp],
-    // c21 = C[1-ip][jp], c22 = C[1-ip][1-jp]
-    const Cx r0a = ip ? C10 : C00, r0b = ip ? C11 : C01;   // pivot row
-    const Cx r1a = ip ? C00 : C10, r1b = ip ? C01 : C11;   // other row
-    u11 = jp ? r0b : r0a;
-    u12 = jp ? r0a : r0b;
-    c21 = jp ? r1b : r1a;
-    c22 = jp ? r1a : r1b;
-  }
-  const Cx l21 = cdivx(c21, u11);
-  Cx u22 = csub(c22, cmul(l21, u12));
-  if (cn1(u22) < smin) {
-    u22 = cx(smin, 0.0);
-    flags |= kInfoPerturbed;
-  }
-  Cx ya = ip ? y1 : y0, yb = ip ? y0 : y1;
-  int q = with_margin(protect_update(cn1(l21), cn1(ya), cn1(yb)));
-  ya = cscl(ya, q); yb = cscl(yb, q); qs += q;
-  Cx r2 = csub(yb, cmul(l21, ya));
-  q = with_margin(protect_division(cn1(r2), 0.5 * cn1(u22)));
-  r2 = cscl(r2, q); ya = cscl(ya, q); qs += q;
-  Cx w2 = cdivx(r2, u22);
-  q = with_margin(protect_update(cn1(u12), cn1(w2), cn1(ya)));
-  w2 = cscl(w2, q); ya = cscl(ya, q); qs += q;
-  Cx n1 = csub(ya, cmul(u12, w2));
-  q = with_margin(protect_division(cn1(n1), 0.5 * cn1(u11)));
-  n1 = cscl(n1, q); w2 = cscl(w2, q); qs += q;
-  const Cx w1 = cdivx(n1, u11);
-  // unknown jp gets w1, the other gets w2
-  y0 = jp ? w2 : w1;
-  y1 = jp ? w1 : w2;
-}
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-constexpr int solve_threads(int mb) { return mb < 64 ? 64 : mb; }
-// the whole workgroup: the column threads plus as many again for the matrix-core and
-// copy phases (one wave per SIMD)
-constexpr int solve_total(int mb) { return mb < 64 ? 64 : 2 * mb; }
-
-// Solve of tile (r, j) of one pencil (a workgroup of solve_total(MB) threads).
-template <int MB>
-__device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j) {
-  constexpr int NT = solve_threads(MB);   // one thread per column, at least one full wave
-  constexpr int NTOT = solve_total(MB);
-  constexpr int LDY = MB + 1;   // odd stride: row and column sweeps are both conflict-free
-  constexpr int G = 8;          // rows per group (recursive blocking inside the tile)
-  __shared__ double Y[MB * LDY];
-  __shared__ double Bop[2 * G][NT];   // [-beta z ; alpha z] of the group, own parts
-  __shared__ double Sg[G][G], Tg[G][G];   // diagonal block of the group: [row][column]
-  __shared__ double tcnS[MB], tcnT[MB];
-  __shared__ int fcol[NT];            // scale exponent still owed by the rows above the group
-  __shared__ int ecol[NT];            // exponent of the second column of a pair
-  __shared__ int8_t tblk[MB];
-  __shared__ double cmax[NT];
-  __shared__ double colA[NT], colB[NT], colBe[NT];
-  __shared__ int colG[NT];
-  __shared__ int8_t colKind[NT];
-
-  const int M = P.ctrl->M;
-  if (r < 0 || r >= M || j >= M) return;
-  const int64_t m = P.m;
-  const int r0 = P.edges[r], hr = P.edges[r + 1] - r0;
-  const int c0 = P.edges[j], hj = P.edges[j + 1] - c0;
-  const bool tip = (r == j);
-  const double psc = P.ctrl->psc;
-  const double* S = P.S;
-  const double* T = P.T;
-  const int64_t lds = P.lds, ldt = P.ldt, ldz = P.ldz;
-
-  const int lc = threadIdx.x;
-  const int wave = lc / 64, lane = lc % 64;
-  const bool inrange = lc < hj;
-  const bool colthr = lc < NT;
-  const int64_t c = c0 + lc;
-  int kind = 0;
-  bool selected = false;
-  double a = 0.0, b = 0.0, be = 0.0;
-  if (inrange) {
-    kind = P.blk[c];
-    selected = P.sel[c] != 0;
-    a = P.ar[c];
-    b = (kind != 0) ? P.ai[c] : 0.0;
-    be = P.be[c];
-  }
-  const int partner = kind == 1 ? lc + 1 : (kind == 2 ? lc - 1 : lc);
-  const bool pair = kind == 1;                 // this thread carries the pair (lc, lc + 1)
-  const bool owner = selected && kind != 2;
-  const int pc = (kind == 2 ? lc - 1 : lc) + (c0 - r0);   // local row of own block (tip tile)
-  const double aabs = fabs(a) + fabs(b);
-  int e = 0;
-  double ybound = 0.0;
-  int flags = 0;
-
-  // ---- structure and column norms of the diagonal tile, right-hand side Y_rj ----
-  if (lc < hr) {
-    tblk[lc] = P.blk[r0 + lc];
-    tcnS[lc] = P.cnS[r0 + lc];
-    tcnT[lc] = P.cnT[r0 + lc];
-  }
-  for (int idx = lc; idx < MB * LDY; idx += NTOT) Y[idx] = 0.0;
-  __syncthreads();
-  if (!tip) {
-    // thread lc reads row lc of every column (coalesced down the columns), 16 loads in flight
-    if (lc < hr) {
-      const double* zrow = P.Z + (r0 + lc) + (int64_t)c0 * ldz;
-      for (int col0 = 0; col0 < hj; col0 += 16) {
-        double v[16];
-#pragma unroll
-        for (int t = 0; t < 16; ++t) v[t] = (col0 + t < hj) ? zrow[(int64_t)(col0 + t) * ldz] : 0.0;
-#pragma unroll
-        for (int t = 0; t < 16; ++t)
-          if (col0 + t < hj) Y[lc * LDY + col0 + t] = v[t];
-      }
-    }
-    if (inrange) {
-      e = P.exps[(int64_t)r * m + c];
-      ybound = P.norms[(int64_t)r * m + c] + (kind != 0 ? P.norms[(int64_t)r * m + c0 + partner] : 0.0);
-    }
-  }
-
-  // groups of at most G rows from the bottom, never splitting a 2x2 block
-  auto group_lo = [&](int g1) {
-    int g0 = g1 - G + 1;
-    if (g0 < 0) g0 = 0;
-    if (g0 > 0 && tblk[g0] == 2) ++g0;
-    return g0;
-  };
-  // the group's diagonal block of S and T (lanes 0..63 of wave 0 hold one entry each)
-  // (loads are unconditional, from a valid address when masked, and the mask is applied
-  // at publication, so they stay in flight while the group is solved)
-  double pS = 0.0, pT = 0.0;
-  bool pOk = false;
-  auto panel_fetch = [&](int g0) {
-    const int u = lane / G, t = lane % G;
-    pOk = wave == 0 && g0 >= 0 && g0 + u < hr && g0 + t < hr;
-    const int64_t ro = pOk ? (r0 + g0 + u) : 0, co = pOk ? (r0 + g0 + t) : 0;
-    pS = S[ro + co * lds];
-    pT = T[ro + co * ldt];
-  };
-  auto panel_publish = [&]() {
-    if (wave == 0) {
-      Sg[lane / G][lane % G] = pOk ? psc * pS : 0.0;
-      Tg[lane / G][lane % G] = pOk ? psc * pT : 0.0;
-    }
-  };
-  __syncthreads();   // tblk visible
-  int g1 = hr - 1;
-  int g0 = group_lo(g1);
-  panel_fetch(g0);
-  panel_publish();
-  __syncthreads();
-
-  while (g1 >= 0) {
-    const int gn1 = g0 - 1;                       // next group
-    const int gn0 = gn1 >= 0 ? group_lo(gn1) : -1;
-    panel_fetch(gn0);                             // lands during this group's work
-    // operands of the rank-2G update of the rows above (A = [S | T] rows 0..g0-1 of the
-    // group's columns), 16 x 4 blocks in the layout of the FP64 matrix instruction
-    double af[MB / 16][4];   // raw entries; masked and scaled where they are used
-#pragma unroll
-    for (int rb = 0; rb < MB / 16; ++rb)
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const int row = 16 * rb + lane % 16;
-        const int kk = 4 * st + lane / 16;        // 0..15: S columns 0..7, T columns 8..15
-        const int col = g0 + (kk & (G - 1));
-        const bool ok = row < g0 && col <= g1;
-        const int64_t ro = ok ? r0 + row : 0, co = ok ? r0 + col : 0;
-        af[rb][st] = kk < G ? S[ro + co * lds] : T[ro + co * ldt];
-      }
-    double yb_above = ybound;   // bound on the rows above the group
-    int qsg = 0;                // scaling raised inside the group
-
-    // ---- blocks of the group, bottom up; updates stay inside the group ----
-    // Each column's substitution is private to the thread that owns it (a complex pair
-    // belongs to the thread of its first column), so the blocks need no barrier.  The
-    // unsolved rows live in registers as a stack, stk[k] = row (top) - k: a block takes
-    // its rows from the top, the rows above it are updated in place, and the stack
-    // shifts by the block size, so every register index is a constant.
-    Cx stk[G];
-    const int yc0 = lc < MB ? lc : 0, yc1 = pair ? lc + 1 : yc0;   // (threads past the tile read column 0)
-#pragma unroll
-    for (int k = 0; k < G; ++k) {
-      const int row = g1 - k >= 0 ? g1 - k : 0;   // (rows above the group: never stored)
-      stk[k] = cx(Y[row * LDY + yc0], pair ? Y[row * LDY + yc1] : 0.0);
-    }
-    int q = g1;
-    while (q >= g0) {
-      const int q0 = (tblk[q] == 2) ? q - 1 : q;
-      const int nb = q - q0 + 1;
-      const int lq0 = q0 - g0, lq = q - g0;      // positions in the group panel
-      // the block's columns of the panel for the rows above it: entry k is row q0 - 1 - k
-      double sc0[G - 1], tc0[G - 1], sc1[G - 1], tc1[G - 1];
-#pragma unroll
-      for (int k = 0; k < G - 1; ++k) {
-        const int li = lq0 - 1 - k >= 0 ? lq0 - 1 - k : 0;
-        sc0[k] = Sg[li][lq0];
-        tc0[k] = Tg[li][lq0];
-        sc1[k] = Sg[li][lq];
-        tc1[k] = Tg[li][lq];
-      }
-      const bool work = owner && !(tip && q0 > pc);
-      Cx z0 = cx(0.0, 0.0), z1 = cx(0.0, 0.0);
-      double cn = 0.0;
-      if (work) {
-        int qs = 0;
-        if (tip && q0 == pc) {
-          if (nb == 1) {
-            z0 = cx(1.0, 0.0);
-          } else {
-            // second row of the singular block beta S_b - alpha T_b gives z_p for z_{p+1} = 1
-            const double s21 = Sg[lq][lq0], s22 = Sg[lq][lq], t22 = Tg[lq][lq];
-            double m21 = be * s21;
-            const Cx nn = cx(-(be * s22 - a * t22), b * t22);
-            const double smin = local_smin(be, aabs, fmax(fabs(s21), fabs(s22)), fabs(t22));
-            if (fabs(m21) < smin) { m21 = smin; flags |= kInfoPerturbed; }
-            const int qd = with_margin(protect_division(cn1(nn), fabs(m21)));
-            const Cx ns = cscl(nn, qd);
-            z0 = cx(ns.r / m21, ns.i / m21);
-            z1 = cx(ldexp(1.0, -qd), 0.0);
-            qs += qd;
-          }
-        } else if (nb == 1) {
-          z0 = solve1(a, b, be, Sg[lq][lq], Tg[lq][lq], stk[0], qs, flags);
-        } else {
-          z0 = stk[1];
-          z1 = stk[0];
-          solve2(a, b, be, Sg[lq0][lq0], Sg[lq0][lq], Sg[lq][lq0], Sg[lq][lq], Tg[lq0][lq0], Tg[lq0][lq],
-                 Tg[lq][lq], z0, z1, qs, flags);
-        }
-        if (q0 > 0) {
-          // ProtectUpdate for y[0:q0] -= (beta S - alpha T)[0:q0, q0..q] z (inside the group
-          // now, above it at the end of the group; the column norms bound both)
-          cn = be * tcnS[q0] + aabs * tcnT[q0];
-          if (nb == 2) cn += be * tcnS[q] + aabs * tcnT[q];
-          const double zn = fmax(cn1(z0), cn1(z1));
-          const int qu = with_margin(protect_update(cn, zn, ldexp(ybound, -qs)));
-          z0 = cscl(z0, qu);
-          z1 = cscl(z1, qu);
-          qs += qu;
-        }
-        if (qs > 0) {
-          // the unsolved rows now, the group's solved rows in LDS; the rows above and below
-          // the group at its end
-#pragma unroll
-          for (int k = 0; k < G; ++k) stk[k] = cscl(stk[k], qs);
-          for (int i = q + 1; i <= g1; ++i) {
-            Y[i * LDY + lc] = ldexp(Y[i * LDY + lc], -qs);
-            if (pair) Y[i * LDY + lc + 1] = ldexp(Y[i * LDY + lc + 1], -qs);
-          }
-          qsg += qs;
-          e += qs;
-          ybound = ldexp(ybound, -qs);
-          yb_above = ldexp(yb_above, -qs);
-        }
-        Y[q0 * LDY + lc] = z0.r;
-        if (pair) Y[q0 * LDY + lc + 1] = z0.i;
-        if (nb == 2) {
-          Y[q * LDY + lc] = z1.r;
-          if (pair) Y[q * LDY + lc + 1] = z1.i;
-        }
-        if (q0 > 0) ybound += cn * fmax(cn1(z0), cn1(z1));
-      }
-      // pop the block; stk[k] is now row q0 - 1 - k
-#pragma unroll
-      for (int k = 0; k < G; ++k) {
-        const Cx s1 = k + 1 < G ? stk[k + 1] : cx(0.0, 0.0);
-        const Cx s2 = k + 2 < G ? stk[k + 2] : cx(0.0, 0.0);
-        stk[k] = nb == 1 ? s1 : s2;
-      }
-      if (work) {
-        // y -= S (beta z) - T (alpha z) on the rows above the block (real and imaginary
-        // parts); entries above the group are scratch
-        const Cx u0 = cx(be * z0.r, be * z0.i), u1 = cx(be * z1.r, be * z1.i);
-        const Cx v0 = cx(a * z0.r - b * z0.i, a * z0.i + b * z0.r);
-        const Cx v1 = cx(a * z1.r - b * z1.i, a * z1.i + b * z1.r);
-#pragma unroll
-        for (int k = 0; k < G - 1; ++k) {
-          double dr = sc0[k] * u0.r - tc0[k] * v0.r, di = sc0[k] * u0.i - tc0[k] * v0.i;
-          dr += sc1[k] * u1.r - tc1[k] * v1.r;   // (z1 = 0 for a 1x1 block)
-          di += sc1[k] * u1.i - tc1[k] * v1.i;
-          stk[k].r -= dr;
-          stk[k].i -= di;
-        }
-      }
-      q = q0 - 1;
-    }
-
-    // ---- end of group: bound the rank-2G update of the rows above, settle scales ----
-    if (owner && g0 > 0) {
-      double cng = 0.0, zng = 0.0;
-      for (int i = g0; i <= g1; ++i) {
-        cng += be * tcnS[i] + aabs * tcnT[i];
-        zng = fmax(zng, fabs(Y[i * LDY + lc]) + (pair ? fabs(Y[i * LDY + lc + 1]) : 0.0));
-      }
-      const int qg = with_margin(protect_update(cng, zng, yb_above));
-      if (qg > 0) {
-        for (int i = g0; i <= g1; ++i) {
-          Y[i * LDY + lc] = ldexp(Y[i * LDY + lc], -qg);
-          if (pair) Y[i * LDY + lc + 1] = ldexp(Y[i * LDY + lc + 1], -qg);
-        }
-        qsg += qg;
-        e += qg;
-        yb_above = ldexp(yb_above, -qg);
-        zng = ldexp(zng, -qg);
-      }
-      ybound = yb_above + cng * zng;
-    }
-    if (owner && qsg > 0)   // the solved rows below the group (rare: scaling has head room)
-      for (int i = g1 + 1; i < hr; ++i) {
-        Y[i * LDY + lc] = ldexp(Y[i * LDY + lc], -qsg);
-        if (pair) Y[i * LDY + lc + 1] = ldexp(Y[i * LDY + lc + 1], -qsg);
-      }
-    if (colthr && kind != 2) {
-      fcol[lc] = qsg;
-      if (pair) fcol[lc + 1] = qsg;
-    }
-    __syncthreads();   // the group's solved values and scales are final
-    // B operand: [-beta z ; alpha z] own parts, zero for rows outside the group
-#pragma unroll
-    for (int t = 0; t < G; ++t) {
-      const int i = g0 + t;
-      double bu = 0.0, bv = 0.0;
-      if (i <= g1 && selected) {
-        const double own = Y[i * LDY + lc];
-        const double oth = Y[i * LDY + partner];
-        const double zr = kind == 2 ? oth : own, zi = kind == 0 ? 0.0 : (kind == 1 ? oth : own);
-        bu = -be * own;
-        bv = kind == 2 ? (b * zr + a * zi) : (a * zr - b * zi);
-      }
-      if (colthr) {
-        Bop[t][lc] = bu;
-        Bop[G + t][lc] = bv;
-      }
-    }
-    panel_publish();   // the next group's diagonal block (its loads had the whole group)
-    __syncthreads();
-
-    // ---- rank-2G update of the rows above the group on the FP64 matrix cores ----
-    // Y[0:g0, :] <- 2^-fcol Y[0:g0, :] + [S | T][0:g0, group] * [-beta z ; alpha z]
-    if (g0 > 0) {
-      const int nrb = (g0 + 15) / 16, ncb = (hj + 15) / 16;
-      constexpr int nw = NTOT / 64;
-      // A wave owns whole column blocks; its row blocks are independent chains, issued
-      // interleaved.  NR (a compile-time bound on the row blocks) keeps every operand in
-      // registers and every instruction unconditional: rows at or below the group and
-      // columns past the tile are computed and dropped, and operand columns past the
-      // group meet zero rows of B.
-      auto rank_update = [&](auto nr_c) {
-        constexpr int NR = decltype(nr_c)::value;
-        for (int cb = wave; cb < ncb; cb += nw) {
-          const int col = 16 * cb + lane % 16;
-          const int fs = fcol[col];
-          d4 acc[NR];
-#pragma unroll
-          for (int rb = 0; rb < NR; ++rb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-              acc[rb][v] = ldexp(Y[(16 * rb + lane / 16 + 4 * v) * LDY + col], -fs);
-#pragma unroll
-          for (int st = 0; st < 4; ++st) {
-            const double bf = Bop[4 * st + lane / 16][col];
-#pragma unroll
-            for (int rb = 0; rb < NR; ++rb)
-              acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(psc * af[rb][st], bf, acc[rb], 0, 0, 0);
-          }
-          const bool cok = col < hj;
-#pragma unroll
-          for (int rb = 0; rb < NR; ++rb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int row = 16 * rb + lane / 16 + 4 * v;
-              if (row < g0 && cok) Y[row * LDY + col] = acc[rb][v];
-            }
-        }
-      };
-      constexpr int NR0 = MB / 16;
-      if (nrb > NR0 / 2) rank_update(std::integral_constant<int, NR0>{});
-      else if (nrb > NR0 / 4 || NR0 < 4) rank_update(std::integral_constant<int, (NR0 / 2 > 0 ? NR0 / 2 : 1)>{});
-      else rank_update(std::integral_constant<int, (NR0 / 4 > 0 ? NR0 / 4 : 1)>{});
-    }
-    __syncthreads();
-    g1 = gn1;
-    g0 = gn0;
-  }
-
-  // the second column of a pair takes the exponent its owner carried
-  if (colthr && pair) ecol[lc + 1] = e;
-  __syncthreads();
-  if (kind == 2) e = ecol[lc];
-
-  // ---- segment norm and exponent ----
-  double nx = 0.0;
-  if (inrange)
-    for (int i = 0; i < hr; ++i) nx = fmax(nx, fabs(Y[i * LDY + lc]));
-  if (colthr) {
-    cmax[lc] = nx;
-    colA[lc] = a;
-    colB[lc] = b;
-    colBe[lc] = be;
-    colKind[lc] = (int8_t)kind;
-  }
-  if (inrange) {
-    P.exps[(int64_t)r * m + c] = e;
-    P.norms[(int64_t)r * m + c] = nx;
-  }
-  if (flags) atomicOr(P.info, flags);
-  __syncthreads();
-  // Algorithm 2 with a scale that bounds the pair norm of W by one
-  {
-    const double nxb = colthr ? cmax[lc] + (kind != 0 ? cmax[partner] : 0.0) : 0.0;
-    int g = 0;
-    if (nxb > 1.0) frexp(nxb, &g);
-    if (colthr) colG[lc] = g;
-    if (inrange) {
-      const int64_t slot = (int64_t)(r % P.wslots) * m;
-      P.eW[slot + c] = e + g;
-      P.nW[slot + c] = ldexp(nxb, -g);
-    }
-  }
-  // ---- write the solved tile to Z (thread lc writes row lc: coalesced down each column) ----
-  if (lc < hr) {
-    double* zrow = P.Z + (r0 + lc) + (int64_t)c0 * ldz;
-    for (int col = 0; col < hj; ++col) zrow[(int64_t)col * ldz] = Y[lc * LDY + col];
-  }
-  __syncthreads();
-  // ---- W = 2^-g [X D ; -X B] in operand order: [kstep][col block][lane] ----
-  {
-    constexpr int CBM = MB / 16;
-    const int KP = (hr + 15) & ~15;        // rows of each half, padded to the update's K chunk
-    const int KS = 2 * KP / 4;
-    double* Wj = P.W + ((int64_t)(r % P.wslots) * P.Mmax + j) * w_tile_doubles(MB);
-    // a thread keeps one (column block, lane) position and walks the K steps
-    for (int cbl = lc; cbl < CBM * 64; cbl += NTOT) {
-      const int n = 16 * (cbl / 64) + cbl % 16;
-      const int l16 = (cbl % 64) / 16;
-      const bool nok = n < hj;
-      const int g = nok ? colG[n] : 0;
-      const int kd = nok ? colKind[n] : 0;
-      const double an = nok ? colA[n] : 0.0, bn = nok ? colB[n] : 0.0, ben = nok ? colBe[n] : 0.0;
-      const int np = kd == 1 ? n + 1 : (kd == 2 ? n - 1 : n);
-      for (int s = 0; s < KS; ++s) {
-        const int kr = 4 * s + l16;
-        const bool lower = kr >= KP;
-        const int i = lower ? kr - KP : kr;
-        double w = 0.0;
-        if (nok && i < hr) {
-          const double x = Y[i * LDY + n], xp = Y[i * LDY + np];
-          if (!lower) w = ben * x;
-          else if (kd == 0) w = -(an * x);
-          else if (kd == 1) w = -(an * x - bn * xp);
-          else w = -(bn * xp + an * x);
-          w = ldexp(w, -g);
-        }
-        Wj[(int64_t)s * (CBM * 64) + cbl] = w;
-      }
-    }
-  }
-}
 
 // tile row r of one pencil: tiles (r, j), j = r .. M-1
 template <int MB>
 __global__ __launch_bounds__(solve_total(MB)) void solve_kernel(PencilDesc P, int r) {
-  solve_tile<MB>(P, r, r + (int)blockIdx.x);
+  __shared__ SolveSmem<MB> sm;
+  solve_tile<MB>(P, r, r + (int)blockIdx.x, sm);
 }
 
 // one lock-step of a batch: tile row M_p - 1 - t of every pencil p = blockIdx.y
 template <int MB>
 __global__ __launch_bounds__(solve_total(MB)) void solve_batched_kernel(const PencilDesc* __restrict__ D, int t) {
+  __shared__ SolveSmem<MB> sm;
   const PencilDesc P = D[blockIdx.y];
   const int r = P.ctrl->M - 1 - t;
-  solve_tile<MB>(P, r, r + (int)blockIdx.x);
+  solve_tile<MB>(P, r, r + (int)blockIdx.x, sm);
 }
 
 template <int MB>
