@@ -133,6 +133,8 @@ def main():
     ap.add_argument("--m", type=int, default=32768)
     ap.add_argument("--mb", type=int, default=0)
     ap.add_argument("--band", type=int, default=0)
+    ap.add_argument("--schedule", type=int, default=0, choices=(0, 1, 2),
+                    help="0/1: band wavefront with look-ahead; 2: persistent walker")
     ap.add_argument("--seed", type=int, default=400)
     ap.add_argument("--kind", default="normal", choices=("normal", "stress"))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -162,7 +164,7 @@ def main():
     S, T, blk = pencils.schur_pencil(m, args.seed, args.kind, threads=16)
     log(f"[bench] generated in {time.perf_counter() - t0:.1f} s; uploading")
     Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
-    solver = rt.Solver(m, mb=args.mb, normalize=True, band=args.band)
+    solver = rt.Solver(m, mb=args.mb, normalize=True, band=args.band, schedule=args.schedule)
     Z = rt.colmajor_empty(m)
     scales = torch.empty(m, dtype=torch.int32, device="cuda")
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
@@ -205,12 +207,15 @@ def main():
         "config": {
             "workload": f"all right eigenvectors of a real Schur pencil, m={m}, robust FP64 "
                         f"(power-of-two scale exponents), normalised output",
-            "m": m, "mb": int(st0["mb"]), "band": int(solver.opts.band) or 4, "tiles": int(st0["M"]),
+            "m": m, "mb": int(st0["mb"]), "band": rt.resolve_opts(m, mb=args.mb, band=args.band)[1],
+            "schedule": "persistent walker" if args.schedule == 2 else "band wavefront", "tiles": int(st0["M"]),
             "seed": args.seed,
             "generator": args.kind, "flops_per_step": F,
         },
         "roofline": {
-            "kernel": "update_kernel (robust tile update, FP64 MFMA 16x16x4)",
+            "kernel": ("walker_kernel (whole task graph: tile updates on FP64 MFMA 16x16x4 and solves; "
+                       "update flops over the walker's time)") if args.schedule == 2 else
+                      "update_kernel (robust tile update, FP64 MFMA 16x16x4)",
             "bound": "mfma",
             "achieved": round(achieved, 3),
             "peak": FP64_MFMA_PEAK,

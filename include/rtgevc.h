@@ -70,7 +70,19 @@ typedef struct rtgevc_opts {
   int32_t band;       /* tile rows per update band: 0 = automatic, else 1..8.  After the
                          rows of a band are solved (with small updates inside the band),
                          one contraction applies all of them to every tile above it.   */
-  int32_t reserved[5];/* must be zero                                                  */
+  int32_t schedule;   /* how the task graph of Algorithm 1 is walked:
+                         0 or 1: band wavefront (one launch per band step for all tile
+                             columns, look-ahead on a second stream);
+                         2: persistent walker (one launch; workgroups take tile tasks in
+                             a fixed priority order and wait on device-side dependency
+                             counters; one source row per update, so band is ignored;
+                             needs a larger workspace: W of every tile).
+                         Both give the same eigenvectors (schedule 2 equals schedule 1
+                         with band = 1 bit for bit).                                    */
+  int32_t watchdog;   /* schedule 2: bound on each dependency wait in polling rounds
+                         (0 = default, about two seconds).  A wait that runs out sets
+                         RTGEVC_INFO_WATCHDOG and the results are invalid.              */
+  int32_t reserved[3];/* must be zero                                                  */
 } rtgevc_opts;
 
 /* Bytes of device workspace rtgevc() needs for order m with these options

@@ -27,6 +27,7 @@ void launch_solve_batched(const PencilDesc* D, int n, int mb, int max_tiles, int
 void launch_update_batched(const PencilDesc* D, int n, int mb, int max_tiles, int t, hipStream_t s);
 void launch_consolidate_batched(const PencilDesc* D, int n, int64_t max_m, hipStream_t s);
 void launch_eigvals_out(const PencilDesc& P, double* are, double* aim, double* bet, hipStream_t s);
+hipError_t launch_walk(const PencilDesc& P, const WalkDesc& W, hipStream_t s);
 }  // namespace rgev
 
 using namespace rgev;
@@ -62,10 +63,16 @@ bool opts_ok(const rtgevc_opts* o) {
   if (o->mb != 0 && o->mb != 32 && o->mb != 64 && o->mb != 128) return false;
   if (o->normalize != 0 && o->normalize != 1) return false;
   if (o->band < 0 || o->band > kMaxBand) return false;
-  for (int i = 0; i < 5; ++i)
+  if (o->schedule < 0 || o->schedule > 2) return false;
+  if (o->watchdog < 0) return false;
+  for (int i = 0; i < 3; ++i)
     if (o->reserved[i] != 0) return false;
   return true;
 }
+
+// 1 = band wavefront on two streams, 2 = persistent walker
+int resolve_schedule(const rtgevc_opts* o) { return (o && o->schedule == 2) ? 2 : 1; }
+constexpr int kDefaultSpinLimit = 1 << 26;   // about two seconds of waiting
 
 struct Carve {
   size_t off = 0;
@@ -77,9 +84,11 @@ struct Carve {
   }
 };
 
-// Lays out the workspace; with base == nullptr it only measures.
-__host__ __device__ size_t carve(PencilDesc& P, char* base, int64_t m, int mb, int band) {
+// Lays out the workspace; with base == nullptr it only measures.  W keeps 2 band source
+// rows (band wavefront) or, with walk != nullptr, every source row (persistent walker).
+__host__ __device__ size_t carve(PencilDesc& P, char* base, int64_t m, int mb, int band, WalkDesc* walk = nullptr) {
   const int Mmax = tile_bound(m, mb);
+  const int wslots = walk ? Mmax : 2 * band;
   Carve c;
   P.ctrl = c.take<Ctrl>(base, 1);
   P.blk = c.take<int8_t>(base, m);
@@ -94,13 +103,20 @@ __host__ __device__ size_t carve(PencilDesc& P, char* base, int64_t m, int mb, i
   P.nu = c.take<double>(base, (size_t)Mmax * Mmax);
   P.exps = c.take<int32_t>(base, (size_t)Mmax * m);
   P.norms = c.take<double>(base, (size_t)Mmax * m);
-  P.W = c.take<double>(base, (size_t)2 * band * Mmax * w_tile_doubles(mb));
-  P.eW = c.take<int32_t>(base, (size_t)2 * band * m);
-  P.nW = c.take<double>(base, (size_t)2 * band * m);
+  P.W = c.take<double>(base, (size_t)wslots * Mmax * w_tile_doubles(mb));
+  P.eW = c.take<int32_t>(base, (size_t)wslots * m);
+  P.nW = c.take<double>(base, (size_t)wslots * m);
   P.mb = mb;
   P.Mmax = Mmax;
   P.band = band;
-  P.wslots = 2 * band;
+  P.wslots = wslots;
+  if (walk) {
+    walk->cnt = c.take<int32_t>(base, (size_t)Mmax * Mmax);
+    walk->solved = c.take<int32_t>(base, (size_t)Mmax * Mmax);
+    walk->levels = c.take<int64_t>(base, (size_t)2 * Mmax + 1);
+    walk->next = c.take<int32_t>(base, 1);
+    walk->tickets = c.take<int4>(base, (size_t)walk_tasks(Mmax));
+  }
   return c.off;
 }
 
@@ -298,7 +314,7 @@ int check_common(int64_t m, const double* S, int64_t lds, const double* T, int64
 
 PencilDesc make_desc(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt,
                      const int32_t* select, double* Z, int64_t ldz, int32_t* scales, int32_t* info,
-                     void* work, const rtgevc_opts* opts) {
+                     void* work, const rtgevc_opts* opts, WalkDesc* walk = nullptr) {
   PencilDesc P;
   memset(&P, 0, sizeof(P));
   P.m = m;
@@ -310,9 +326,10 @@ PencilDesc make_desc(int64_t m, const double* S, int64_t lds, const double* T, i
   P.Z = Z;
   P.scales = scales;
   P.select = select;
-  carve(P, static_cast<char*>(work), m, resolve_mb(m, opts), resolve_band(m, opts));
+  carve(P, static_cast<char*>(work), m, resolve_mb(m, opts), resolve_band(m, opts), walk);
   P.info = info ? info : &P.ctrl->info_local;
   P.normalize = opts ? opts->normalize : 1;
+  if (walk) walk->spin_limit = (opts && opts->watchdog > 0) ? opts->watchdog : kDefaultSpinLimit;
   return P;
 }
 
@@ -325,7 +342,9 @@ size_t rtgevc_workspace_size(int64_t m, const rtgevc_opts* opts) {
   if (m == 0) return kAlign;
   PencilDesc P;
   memset(&P, 0, sizeof(P));
-  return carve(P, nullptr, m, resolve_mb(m, opts), resolve_band(m, opts));
+  WalkDesc W;
+  return carve(P, nullptr, m, resolve_mb(m, opts), resolve_band(m, opts),
+               resolve_schedule(opts) == 2 ? &W : nullptr);
 }
 
 int rtgevc(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt, const int32_t* select,
@@ -337,6 +356,15 @@ int rtgevc(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt
   if (ldz < (m > 1 ? m : 1)) return -8;
   if (m == 0) return 0;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (resolve_schedule(opts) == 2) {
+    WalkDesc W;
+    PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts, &W);
+    launch_preprocess(P, s);
+    hipError_t err = launch_walk(P, W, s);
+    launch_consolidate(P, s);
+    if (err == hipSuccess) err = hipGetLastError();
+    return hip_code(err);
+  }
   PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts);
   std::lock_guard<std::mutex> lock(g_aux_mu);
   Aux* ax = nullptr;
@@ -376,7 +404,9 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
   for (int i = 0; i < nstats; ++i) stats[i] = 0.0;
   if (m == 0) return 0;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts);
+  const bool walker = resolve_schedule(opts) == 2;
+  WalkDesc W;
+  PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts, walker ? &W : nullptr);
   // events bracket every launch on the stream it runs on
   const int nev = 2 * (3 * P.Mmax + 8);
   std::lock_guard<std::mutex> lock(g_event_mu);
@@ -403,7 +433,14 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
   int32_t M = 0;
   err = hipMemcpyAsync(&M, &P.ctrl->M, sizeof(int32_t), hipMemcpyDeviceToHost, s);
   if (err == hipSuccess) err = hipStreamSynchronize(s);
-  if (err == hipSuccess) {
+  if (err == hipSuccess && walker) {
+    // the whole task graph is one launch (counted with the updates)
+    const int e0 = used;
+    mark();
+    err = launch_walk(P, W, s);
+    mark();
+    spans[nsp++] = Span{2, e0, e0 + 1};
+  } else if (err == hipSuccess) {
     const hipError_t e = enqueue_rows(P, M, s, *ax, [&](int kind, bool before, hipStream_t st) {
       mark_on(st);
       if (!before) {

@@ -19,7 +19,10 @@
 //                      overwrite what the previous band's update still reads), packed in
 //                      the operand order of the FP64 matrix instruction
 //   eW, nW [2R * m]    exponent and norm bound of W per source-row slot and column
+//   (the persistent walker keeps W, eW, nW of every source row: Mmax slots, and its
+//   work list and counters, see WalkDesc)
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -67,6 +70,25 @@ struct PencilDesc {
 };
 
 constexpr int kMaxBand = 8;
+
+// Work list and dependency counters of the persistent walker (schedule 2).
+struct WalkDesc {
+  int32_t* cnt;       // [Mmax * Mmax] updates applied to tile (k, j)
+  int32_t* solved;    // [Mmax * Mmax] tile (r, j) solved
+  int4* tickets;      // tasks in priority order: (type 0 solve / 1 update, k, r, j)
+  int64_t* levels;    // [2 Mmax + 1] first ticket of each level; the last entry is the count
+  int32_t* next;      // ticket dispenser
+  int32_t spin_limit; // bound on every dependency wait
+  int32_t pad;
+};
+
+// number of walker tasks for M tiles: per distance d = j - r, M - d solves and
+// (M - 1 - d)(M - d)/2 updates
+__host__ __device__ inline int64_t walk_tasks(int64_t M) {
+  int64_t n = 0;
+  for (int64_t d = 0; d < M; ++d) n += (M - d) + (M - 1 - d) * (M - d) / 2;
+  return n;
+}
 
 // W tile of one (source row, tile column) pair: 2*MB K-rows x MB columns.
 __host__ __device__ constexpr int64_t w_tile_doubles(int mb) { return 2LL * mb * mb; }

@@ -35,7 +35,7 @@ class RtgevcError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("mb", ctypes.c_int32), ("normalize", ctypes.c_int32), ("band", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("schedule", ctypes.c_int32), ("watchdog", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 _lib = None
@@ -80,16 +80,22 @@ EXPORTED = ("rtgevc_workspace_size", "rtgevc", "rtgevc_eigvals", "rtgevc_timed",
 TIMED_NSTATS = 12
 
 
-def make_opts(mb: int = 0, normalize: bool = True, band: int = 0) -> Opts:
+SCHEDULE_BANDS = 1     # band wavefront with look-ahead (default)
+SCHEDULE_WALKER = 2    # persistent walker with device-side dependency counters
+
+
+def make_opts(mb: int = 0, normalize: bool = True, band: int = 0, schedule: int = 0, watchdog: int = 0) -> Opts:
     o = Opts()
     o.mb = int(mb)
     o.normalize = 1 if normalize else 0
     o.band = int(band)
+    o.schedule = int(schedule)
+    o.watchdog = int(watchdog)
     return o
 
 
-def workspace_size(m: int, mb: int = 0, normalize: bool = True, band: int = 0) -> int:
-    o = make_opts(mb, normalize, band)
+def workspace_size(m: int, mb: int = 0, normalize: bool = True, band: int = 0, schedule: int = 0) -> int:
+    o = make_opts(mb, normalize, band, schedule)
     return int(load().rtgevc_workspace_size(int(m), ctypes.byref(o)))
 
 
@@ -155,10 +161,11 @@ class Solver:
     """Holds a workspace for repeated calls of one order m (the workspace is the only
     allocation, made once by torch; the library itself allocates nothing)."""
 
-    def __init__(self, m: int, mb: int = 0, normalize: bool = True, band: int = 0, device="cuda"):
+    def __init__(self, m: int, mb: int = 0, normalize: bool = True, band: int = 0, device="cuda",
+                 schedule: int = 0, watchdog: int = 0):
         import torch
         self.m = int(m)
-        self.opts = make_opts(mb, normalize, band)
+        self.opts = make_opts(mb, normalize, band, schedule, watchdog)
         self.nbytes = int(load().rtgevc_workspace_size(self.m, ctypes.byref(self.opts)))
         self.work = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
         self.device = device
@@ -215,10 +222,11 @@ class Solver:
         return out[0][:m], out[1][:m], out[2][:m], info
 
 
-def tgevc(S, T, select=None, normalize: bool = True, mb: int = 0, band: int = 0, stream=None) -> Result:
+def tgevc(S, T, select=None, normalize: bool = True, mb: int = 0, band: int = 0, stream=None,
+          schedule: int = 0) -> Result:
     """All (or the selected) right eigenvectors of the Schur pencil (S, T)."""
-    return Solver(S.shape[0], mb=mb, normalize=normalize, band=band, device=S.device).run(
-        S, T, select, stream=stream)
+    return Solver(S.shape[0], mb=mb, normalize=normalize, band=band, device=S.device,
+                  schedule=schedule).run(S, T, select, stream=stream)
 
 
 def _i64_array(vals):

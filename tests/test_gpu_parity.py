@@ -313,3 +313,71 @@ def test_full_size_stress_8192():
 
 def test_full_size_32768():
     _full_size(32768, 400, "normal", 12)
+
+
+# ---- persistent walker (schedule 2) ----
+
+@pytest.mark.parametrize("m,mb,seed", [(1, 32, 400), (33, 32, 401), (200, 64, 402), (300, 128, 403),
+                                       (700, 64, 404), (1000, 128, 405), (1500, 32, 406)])
+def test_walker_parity(m, mb, seed):
+    """The persistent walker against the oracle, and bit for bit against the band schedule
+    with one row per band (same updates in the same order per tile)."""
+    torch = _torch()
+    from paper_2003_04776_amd import rtgevc as rt
+    _say(f"[walker] m={m} mb={mb} seed={seed}")
+    S, T, blk = pencils.schur_pencil(m, seed)
+    Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
+    rw = rt.Solver(m, mb=mb, schedule=rt.SCHEDULE_WALKER).run(Sd, Td)
+    rb = rt.Solver(m, mb=mb, band=1).run(Sd, Td)
+    torch.cuda.synchronize()
+    assert int(rw.info.item()) == 0
+    Zw = rw.Z.cpu().numpy()
+    assert np.array_equal(Zw, rb.Z.cpu().numpy())
+    worst, errs, nill = compare(S, T, Zw)
+    _say(f"   max err {worst:.3e} ill {nill}")
+    assert worst <= TOL
+
+
+def test_walker_stress_unnormalised():
+    torch = _torch()
+    from paper_2003_04776_amd import rtgevc as rt
+    m, mb = 400, 64
+    S, T, blk = pencils.schur_pencil(m, 410, "stress")
+    Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
+    r = rt.Solver(m, mb=mb, normalize=False, schedule=rt.SCHEDULE_WALKER).run(Sd, Td)
+    rb = rt.Solver(m, mb=mb, normalize=False, band=1).run(Sd, Td)
+    torch.cuda.synchronize()
+    Z, sc = r.Z.cpu().numpy(), r.scales.cpu().numpy()
+    assert int(r.info.item()) & ~16 == 0
+    assert np.isfinite(Z).all() and (sc >= 0).all() and sc.max() > 1000
+    assert np.array_equal(Z, rb.Z.cpu().numpy()) and np.array_equal(sc, rb.scales.cpu().numpy())
+
+
+def test_walker_repeat_is_deterministic():
+    torch = _torch()
+    from paper_2003_04776_amd import rtgevc as rt
+    m = 900
+    S, T, _ = pencils.schur_pencil(m, 411)
+    Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
+    sol = rt.Solver(m, mb=32, schedule=rt.SCHEDULE_WALKER)
+    a = sol.run(Sd, Td).Z.clone()
+    for _ in range(3):
+        b = sol.run(Sd, Td).Z
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+
+
+def test_walker_watchdog_bit():
+    """A dependency-wait bound of one polling round (set from the host) makes waits give
+    up: the launch still drains and reports the watchdog bit."""
+    torch = _torch()
+    from paper_2003_04776_amd import rtgevc as rt
+    m = 1200
+    S, T, _ = pencils.schur_pencil(m, 412)
+    Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
+    r = rt.Solver(m, mb=32, schedule=rt.SCHEDULE_WALKER, watchdog=1).run(Sd, Td)
+    torch.cuda.synchronize()
+    assert int(r.info.item()) & rt.INFO_WATCHDOG
+    r2 = rt.Solver(m, mb=32, schedule=rt.SCHEDULE_WALKER).run(Sd, Td)
+    torch.cuda.synchronize()
+    assert int(r2.info.item()) == 0
