@@ -29,6 +29,23 @@ HBM_PEAK = 8000.0       # GB/s
 METRIC = "FP64-equiv TFLOP/s + time for all eigvecs at m=32768; mixed/FP64 speedup"
 
 
+# HBM traffic of the update kernel per launch from two rocprofv3 counter runs (FETCH_SIZE and
+# WRITE_SIZE, scaled by what the counters read for a plain 1 GiB device copy), for the default
+# workload; valid only while the kernel's sources hash to the value they had when the counters
+# were taken (profiles/update_kernel_m32768_fp64_traffic.md).
+TRAFFIC = {"sources_sha256_16": "7aba6f93b449e210", "bytes_per_launch": 1.7992e9,
+           "workload": (32768, 128, 4, 1)}   # m, mb, band, schedule
+
+
+def update_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("update_tile.hpp", "update.hip"):
+        with open(os.path.join(ROOT, "paper_2003_04776_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -142,6 +159,9 @@ def main():
     ap.add_argument("--workload", default="single", choices=("single", "batched"),
                     help="single: one pencil of order --m (the headline); batched: --count pencils")
     ap.add_argument("--count", type=int, default=512)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="before the timed steps, copy this many MiB once with a plain device copy "
+                         "(a kernel of known traffic, to calibrate memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for {args.gpus})",
@@ -169,6 +189,15 @@ def main():
     scales = torch.empty(m, dtype=torch.int32, device="cuda")
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
+    if args.copy_probe_mb > 0:
+        n = args.copy_probe_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {n * 8} bytes read and {n * 8} bytes written")
+        del src, dst
     for w in range(args.warmup):
         st = solver.run_timed(Sd, Td, Z, scales, info)
         log(f"[bench] warmup {w}: {st['total_ms']:.1f} ms device")
@@ -221,7 +250,11 @@ def main():
             "peak": FP64_MFMA_PEAK,
             "unit": "TFLOP/s",
             "frac": round(achieved / FP64_MFMA_PEAK, 4),
-            "traffic": None,
+            "traffic": (TRAFFIC["bytes_per_launch"]
+                        if (m, int(st0["mb"]), rt.resolve_opts(m, mb=args.mb, band=args.band)[1],
+                            2 if args.schedule == 2 else 1) == TRAFFIC["workload"]
+                        and update_sources_hash() == TRAFFIC["sources_sha256_16"] else None),
+            "traffic_unit": "bytes per launch (HBM read + write)",
             "launches": int(upd_launches),
             "avg_launch_ms": round(upd_ms / max(upd_launches, 1), 4),
             "flops_per_launch": upd_flops / max(upd_launches, 1),
