@@ -152,6 +152,10 @@ def main():
     ap.add_argument("--band", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=0, choices=(0, 1, 2),
                     help="0/1: band wavefront with look-ahead; 2: persistent walker")
+    ap.add_argument("--precision", type=int, default=0, choices=(0, 1),
+                    help="0: FP64 tile updates; 1: mixed (int8 matrix cores on split operands)")
+    ap.add_argument("--no-compare-mixed", dest="compare_mixed", action="store_false",
+                    help="skip the mixed-precision run that follows the FP64 one")
     ap.add_argument("--seed", type=int, default=400)
     ap.add_argument("--kind", default="normal", choices=("normal", "stress"))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -184,7 +188,8 @@ def main():
     S, T, blk = pencils.schur_pencil(m, args.seed, args.kind, threads=16)
     log(f"[bench] generated in {time.perf_counter() - t0:.1f} s; uploading")
     Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
-    solver = rt.Solver(m, mb=args.mb, normalize=True, band=args.band, schedule=args.schedule)
+    solver = rt.Solver(m, mb=args.mb, normalize=True, band=args.band, schedule=args.schedule,
+                       precision=args.precision)
     Z = rt.colmajor_empty(m)
     scales = torch.empty(m, dtype=torch.int32, device="cuda")
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
@@ -262,6 +267,30 @@ def main():
         "phases_ms": {k: round(st0[k], 3) for k in ("pre_ms", "solve_ms", "update_ms", "consolidate_ms", "total_ms")},
         "info": info_v,
     }
+    if args.compare_mixed and args.precision == 0 and args.schedule != 2:
+        # the mixed-precision mode on the same inputs: speed-up and agreement with the FP64 run
+        Zf = Z.clone()
+        mixed = rt.Solver(m, mb=args.mb, normalize=True, band=args.band, precision=1)
+        for w in range(args.warmup):
+            mixed.run_timed(Sd, Td, Z, scales, info)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mst = [mixed.run_timed(Sd, Td, Z, scales, info) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        mwall = (time.perf_counter() - t0) / max(args.steps, 1) * 1e3
+        mflops = sum(x["update_flops"] for x in mst)
+        mupd = sum(x["update_ms"] for x in mst)
+        out["mixed"] = {
+            "precision": "tile-update contraction on int8 matrix cores, operands split into 7 x 7-bit slices",
+            "ms_per_step": round(mwall, 3),
+            "value": round(F / (mwall * 1e-3) / 1e12, 4),
+            "speedup_vs_fp64": round(ms_per_step / mwall, 4),
+            "update_achieved_fp64_equiv_tflops": round(mflops / (mupd * 1e-3) / 1e12, 3) if mupd > 0 else None,
+            "max_abs_diff_vs_fp64": float((Z - Zf).abs().max().item()),
+            "info": int(info.item()),
+        }
+        log(f"[bench] mixed: {mwall:.1f} ms/step, speed-up {ms_per_step / mwall:.3f}")
+        del mixed, Zf
     if rank == 0 and not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a column sample")
         out["cpu_baseline"] = cpu_baseline(S, T, blk, m, args.cpu_seconds)

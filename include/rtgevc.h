@@ -82,7 +82,16 @@ typedef struct rtgevc_opts {
   int32_t watchdog;   /* schedule 2: bound on each dependency wait in polling rounds
                          (0 = default, about two seconds).  A wait that runs out sets
                          RTGEVC_INFO_WATCHDOG and the results are invalid.              */
-  int32_t reserved[3];/* must be zero                                                  */
+  int32_t precision;  /* 0 (default): tile updates on the FP64 matrix cores.
+                         1: mixed precision: the tile-update contraction is emulated on
+                            the int8 matrix cores from operands split into a power-of-two
+                            scale and 7 signed 7-bit slices (products of slices are exact,
+                            summed exactly in int32 per level and folded in FP64; error
+                            about 2 K 2^-49 of max|row| max|column| per product, K <= 256
+                            per source).  Solves, bounds, scale factors and consolidation
+                            stay FP64.  Needs more workspace (slices of every tile pair).
+                            Not with schedule 2.                                          */
+  int32_t reserved[2];/* must be zero                                                  */
 } rtgevc_opts;
 
 /* Bytes of device workspace rtgevc() needs for order m with these options

@@ -16,6 +16,7 @@
 
 #include "rtgevc.h"
 #include "layout.hpp"
+#include "slices.hpp"
 
 namespace rgev {
 void launch_preprocess(const PencilDesc& P, hipStream_t s);
@@ -65,10 +66,14 @@ bool opts_ok(const rtgevc_opts* o) {
   if (o->band < 0 || o->band > kMaxBand) return false;
   if (o->schedule < 0 || o->schedule > 2) return false;
   if (o->watchdog < 0) return false;
-  for (int i = 0; i < 3; ++i)
+  if (o->precision < 0 || o->precision > 1) return false;
+  if (o->precision == 1 && o->schedule == 2) return false;   // the walker runs FP64 updates
+  for (int i = 0; i < 2; ++i)
     if (o->reserved[i] != 0) return false;
   return true;
 }
+
+int resolve_precision(const rtgevc_opts* o) { return (o && o->precision == 1) ? 1 : 0; }
 
 // 1 = band wavefront on two streams, 2 = persistent walker
 int resolve_schedule(const rtgevc_opts* o) { return (o && o->schedule == 2) ? 2 : 1; }
@@ -86,7 +91,8 @@ struct Carve {
 
 // Lays out the workspace; with base == nullptr it only measures.  W keeps 2 band source
 // rows (band wavefront) or, with walk != nullptr, every source row (persistent walker).
-__host__ __device__ size_t carve(PencilDesc& P, char* base, int64_t m, int mb, int band, WalkDesc* walk = nullptr) {
+__host__ __device__ size_t carve(PencilDesc& P, char* base, int64_t m, int mb, int band, WalkDesc* walk = nullptr,
+                                 int precision = 0) {
   const int Mmax = tile_bound(m, mb);
   const int wslots = walk ? Mmax : 2 * band;
   Carve c;
@@ -110,6 +116,14 @@ __host__ __device__ size_t carve(PencilDesc& P, char* base, int64_t m, int mb, i
   P.Mmax = Mmax;
   P.band = band;
   P.wslots = wslots;
+  P.precision = precision;
+  if (precision == 1) {
+    const size_t pairs = (size_t)Mmax * (Mmax - 1) / 2;
+    P.Aslc = c.take<int4>(base, pairs * kSlices * slice_packets(mb));
+    P.Aexp = c.take<int32_t>(base, pairs * mb);
+    P.Wslc = c.take<int4>(base, (size_t)wslots * Mmax * kSlices * slice_packets(mb));
+    P.Wexp = c.take<int32_t>(base, (size_t)wslots * m);
+  }
   if (walk) {
     walk->cnt = c.take<int32_t>(base, (size_t)Mmax * Mmax);
     walk->solved = c.take<int32_t>(base, (size_t)Mmax * Mmax);
@@ -326,7 +340,7 @@ PencilDesc make_desc(int64_t m, const double* S, int64_t lds, const double* T, i
   P.Z = Z;
   P.scales = scales;
   P.select = select;
-  carve(P, static_cast<char*>(work), m, resolve_mb(m, opts), resolve_band(m, opts), walk);
+  carve(P, static_cast<char*>(work), m, resolve_mb(m, opts), resolve_band(m, opts), walk, resolve_precision(opts));
   P.info = info ? info : &P.ctrl->info_local;
   P.normalize = opts ? opts->normalize : 1;
   if (walk) walk->spin_limit = (opts && opts->watchdog > 0) ? opts->watchdog : kDefaultSpinLimit;
@@ -344,7 +358,7 @@ size_t rtgevc_workspace_size(int64_t m, const rtgevc_opts* opts) {
   memset(&P, 0, sizeof(P));
   WalkDesc W;
   return carve(P, nullptr, m, resolve_mb(m, opts), resolve_band(m, opts),
-               resolve_schedule(opts) == 2 ? &W : nullptr);
+               resolve_schedule(opts) == 2 ? &W : nullptr, resolve_precision(opts));
 }
 
 int rtgevc(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt, const int32_t* select,

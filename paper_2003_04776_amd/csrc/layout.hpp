@@ -21,6 +21,9 @@
 //   eW, nW [2R * m]    exponent and norm bound of W per source-row slot and column
 //   (the persistent walker keeps W, eW, nW of every source row: Mmax slots, and its
 //   work list and counters, see WalkDesc)
+//   Aslc, Aexp         mixed precision: split slices and row exponents of every tile pair
+//                      (k, r), k < r (triangular index), written by pre-processing
+//   Wslc, Wexp         mixed precision: split slices and column exponents of W per slot
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -61,12 +64,17 @@ struct PencilDesc {
   int32_t* eW;
   double* nW;
   Ctrl* ctrl;
+  // mixed precision (split operands for the int8 matrix instruction, see slices.hpp)
+  int4* Aslc;         // slices of every super-diagonal tile pair [S_kr | T_kr]
+  int32_t* Aexp;      // [pair][MB] row exponents of those tiles
+  int4* Wslc;         // slices of W per source-row slot and tile column
+  int32_t* Wexp;      // [slot][m] column exponents of W
   int32_t mb;
   int32_t Mmax;
   int32_t normalize;
   int32_t band;       // R: tile rows per update band
   int32_t wslots;     // 2R source-row slots of W, eW, nW
-  int32_t pad2;
+  int32_t precision;  // 0: FP64 contraction; 1: split operands on the int8 matrix cores
 };
 
 constexpr int kMaxBand = 8;

@@ -7,6 +7,7 @@
 
 #include "layout.hpp"
 #include "robust.hpp"
+#include "slices.hpp"
 
 namespace rgev {
 
@@ -267,6 +268,82 @@ __device__ __forceinline__ void pre_fixup_body(const PencilDesc& P) {
   }
 }
 
+// Mixed precision: split every super-diagonal tile pair A = [S_kr | T_kr] (prescaled)
+// into row exponents and kSlices int8 slices in the matrix-instruction layout (see
+// slices.hpp).  One workgroup per pair (k, r), k < r; runs after pre_fixup (psc known).
+constexpr int kSliceThreads = 256;
+
+template <int MB>
+__device__ __forceinline__ void pre_slices_tile(const PencilDesc& P, int k, int r) {
+  constexpr int HK = slice_half_k(MB), KS = slice_ksteps(MB), RBN = MB / 16;
+  __shared__ int rowexp[MB];
+  __shared__ double rowmax[kSliceThreads / MB > 0 ? kSliceThreads / MB : 1][MB];
+  const int k0 = P.edges[k], hk = P.edges[k + 1] - k0;
+  const int c0 = P.edges[r], hc = P.edges[r + 1] - c0;
+  const double psc = P.ctrl->psc;
+  const int64_t lds = P.lds, ldt = P.ldt;
+  const int64_t pair = pair_index(k, r);
+  // row maxima: thread (g, i) scans columns g, g + G, ... of row i (coalesced down columns)
+  constexpr int G = kSliceThreads / MB > 0 ? kSliceThreads / MB : 1;
+  const int tid = threadIdx.x;
+  if (tid < G * MB) {
+    const int i = tid % MB, g = tid / MB;
+    double mx = 0.0;
+    if (i < hk)
+      for (int l = g; l < hc; l += G)
+        mx = fmax(mx, fmax(fabs(P.S[(k0 + i) + (int64_t)(c0 + l) * lds]), fabs(P.T[(k0 + i) + (int64_t)(c0 + l) * ldt])));
+    rowmax[g][i] = psc * mx;
+  }
+  __syncthreads();
+  if (tid < MB) {
+    double mx = rowmax[0][tid];
+    for (int g = 1; g < G; ++g) mx = fmax(mx, rowmax[g][tid]);
+    const int e = slice_exponent(mx);
+    rowexp[tid] = e;
+    P.Aexp[pair * MB + tid] = e;
+  }
+  __syncthreads();
+  // packets: (kstep, row block, lane) -> 16 K values of one row, kSlices slices each
+  const int64_t npk = slice_packets(MB);
+  int4* out = P.Aslc + pair * kSlices * npk;
+  for (int64_t pk = tid; pk < npk; pk += kSliceThreads) {
+    const int l = (int)(pk % 64), rb = (int)((pk / 64) % RBN), ks = (int)(pk / (64 * RBN));
+    const int i = 16 * rb + l % 16;
+    const int e = rowexp[i];
+    double y[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+      const int kk = 64 * ks + 16 * (l / 16) + b;
+      const bool lower = kk >= HK;
+      const int cc = lower ? kk - HK : kk;
+      double x = 0.0;
+      if (i < hk && cc < hc)
+        x = lower ? P.T[(k0 + i) + (int64_t)(c0 + cc) * ldt] : P.S[(k0 + i) + (int64_t)(c0 + cc) * lds];
+      y[b] = ldexp(psc * x, -e);
+    }
+    int4 sl[kSlices];
+    slice16(y, sl);
+#pragma unroll
+    for (int p = 0; p < kSlices; ++p) out[p * npk + pk] = sl[p];
+  }
+  (void)KS;
+}
+
+__device__ __forceinline__ void pre_slices_body(const PencilDesc& P) {
+  const int M = P.ctrl->M;
+  const int64_t bid = blockIdx.x;
+  if (bid >= (int64_t)M * (M - 1) / 2) return;
+  int r = (int)((1.0 + sqrt(1.0 + 8.0 * (double)bid)) * 0.5);
+  while ((int64_t)r * (r - 1) / 2 > bid) --r;
+  while ((int64_t)(r + 1) * r / 2 <= bid) ++r;
+  const int k = (int)(bid - (int64_t)r * (r - 1) / 2);
+  switch (P.mb) {
+    case 32: pre_slices_tile<32>(P, k, r); break;
+    case 64: pre_slices_tile<64>(P, k, r); break;
+    default: pre_slices_tile<128>(P, k, r); break;
+  }
+}
+
 // Kernels: one pencil (descriptor by value), or one pencil per blockIdx.y of a table.
 #define RGEV_PRE_KERNELS(name, bounds)                                                      \
   __global__ bounds void name##_kernel(PencilDesc P) { name##_body(P); }                  \
@@ -281,6 +358,7 @@ RGEV_PRE_KERNELS(pre_tileof, )
 RGEV_PRE_KERNELS(pre_eig, )
 RGEV_PRE_KERNELS(pre_norms, __launch_bounds__(kNormThreads))
 RGEV_PRE_KERNELS(pre_fixup, )
+RGEV_PRE_KERNELS(pre_slices, __launch_bounds__(kSliceThreads))
 #undef RGEV_PRE_KERNELS
 
 void launch_preprocess(const PencilDesc& P, hipStream_t s) {
@@ -294,6 +372,8 @@ void launch_preprocess(const PencilDesc& P, hipStream_t s) {
   const int64_t npairs = (int64_t)P.Mmax * (P.Mmax + 1) / 2;
   pre_norms_kernel<<<(unsigned)npairs, kNormThreads, 0, s>>>(P);
   pre_fixup_kernel<<<64, 256, 0, s>>>(P);
+  if (P.precision == 1 && P.Mmax > 1)
+    pre_slices_kernel<<<(unsigned)((int64_t)P.Mmax * (P.Mmax - 1) / 2), kSliceThreads, 0, s>>>(P);
 }
 
 // The same sequence for n pencils of one table (orders <= max_m, tile counts <= max_tiles).

@@ -1,0 +1,63 @@
+// Split operands for the mixed-precision tile update: a double is carried as a power-of-two
+// scale and kSlices signed 7-bit slices, so products of slices are exact in the int8
+// matrix instruction's int32 accumulators.
+//
+// For a row (of [S_kr | T_kr]) or a column (of W) with largest magnitude below 2^e, every
+// entry x gives y = x 2^-e in (-1, 1) and
+//     y = sum_{p=1..7} a_p 2^(-7p) + rho,   a_p in [-127, 127] integers,  |rho| < 2^-49,
+// each a_p the integer part of the running remainder times 2^7 (exact in FP64).  A product
+// of two split operands is then 2^(e + f) sum_{p,q} 2^(-7(p+q)) sum_k a_p[i,k] w_q[k,c];
+// the pairs with p + q <= 8 are kept (the rest weigh below 2^-63 of the product), and the
+// pairs of one level L = p + q are summed exactly in int32 (|sum| <= 7 K 127^2 < 2^31 for
+// K <= 256).  The error is at most about 2 K 2^-49 max|A_i| max|W_c|.
+//
+// Fragment layout (matches the 16x16x64 int8 matrix instruction): a 16-byte packet per lane
+// holds 16 consecutive K values of one row (A) or one column (W); lane l of a 64-lane
+// fragment covers row/column 16 b + l % 16 and K values 64 s + 16 (l / 16) + 0..15.
+//   A slices of tile pair (k, r): [pair][p][kstep][row block][lane]
+//   W slices of tile (r, j):      [slot][p][kstep][col block][lane]
+// with K = [S columns | T columns] (A) = [X D rows | -X B rows] (W), each half padded to
+// kHalfK(MB) = MB rounded up to 64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rgev {
+
+constexpr int kSlices = 7;
+constexpr int kSliceLevels = kSlices;   // levels L = 2 .. kSlices + 1
+
+__host__ __device__ constexpr int slice_half_k(int mb) { return (mb + 63) / 64 * 64; }
+__host__ __device__ constexpr int slice_ksteps(int mb) { return 2 * slice_half_k(mb) / 64; }
+// int4 packets per slice of one A (or W) tile
+__host__ __device__ constexpr int64_t slice_packets(int mb) { return (int64_t)slice_ksteps(mb) * (mb / 16) * 64; }
+// triangular index of the tile pair (k, r), k < r
+__host__ __device__ inline int64_t pair_index(int k, int r) { return (int64_t)r * (r - 1) / 2 + k; }
+
+// 16 values (already scaled into (-1, 1)) -> kSlices packets of 16 signed bytes
+__device__ __forceinline__ void slice16(const double (&y)[16], int4 (&out)[kSlices]) {
+  double rem[16];
+#pragma unroll
+  for (int b = 0; b < 16; ++b) rem[b] = y[b];
+#pragma unroll
+  for (int p = 0; p < kSlices; ++p) {
+    int w[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+      const double t = rem[b] * 128.0;
+      const double a = trunc(t);
+      rem[b] = t - a;
+      w[b / 4] |= ((int)a & 0xff) << (8 * (b % 4));
+    }
+    out[p] = make_int4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+// exponent e with |x| < 2^e for the largest magnitude x of a row or column (0 for zero)
+__device__ __forceinline__ int slice_exponent(double vmax) {
+  int e = 0;
+  if (vmax > 0.0) frexp(vmax, &e);
+  return e;
+}
+
+}  // namespace rgev

@@ -20,6 +20,7 @@
 
 #include "layout.hpp"
 #include "robust.hpp"
+#include "slices.hpp"
 
 namespace rgev {
 
@@ -144,6 +145,7 @@ struct SolveSmem {
   int fcol[NT];                // scale exponent still owed by the rows above the group
   int ecol[NT];                // exponent of the second column of a pair
   int colG[NT];
+  int wexp[NT];                // mixed precision: column exponent of W
   int8_t tblk[MB];
   int8_t colKind[NT];
 };
@@ -540,7 +542,50 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, So
   }
   __syncthreads();
   // ---- W = 2^-g [X D ; -X B] in operand order: [kstep][col block][lane] ----
-  {
+  if (P.precision == 1) {
+    // split W for the int8 matrix instruction: column exponents, then kSlices slices
+    auto& wexp = sm.wexp;
+    constexpr int CBM = MB / 16, HK = slice_half_k(MB);
+    auto wval = [&](int i, bool lower, int n) -> double {
+      const int kd = colKind[n];
+      const double x = Y[i * LDY + n];
+      if (!lower) return colBe[n] * x;
+      const int np = kd == 1 ? n + 1 : (kd == 2 ? n - 1 : n);
+      const double xp = Y[i * LDY + np];
+      if (kd == 0) return -(colA[n] * x);
+      if (kd == 1) return -(colA[n] * x - colB[n] * xp);
+      return -(colB[n] * xp + colA[n] * x);
+    };
+    if (colthr) {
+      double mx = 0.0;
+      if (inrange)
+        for (int i = 0; i < hr; ++i) mx = fmax(mx, fmax(fabs(wval(i, false, lc)), fabs(wval(i, true, lc))));
+      const int f = slice_exponent(ldexp(mx, -colG[lc]));
+      wexp[lc] = f;
+      if (inrange) P.Wexp[(int64_t)(r % P.wslots) * m + c] = f;
+    }
+    __syncthreads();
+    const int64_t npk = slice_packets(MB);
+    int4* out = P.Wslc + ((int64_t)(r % P.wslots) * P.Mmax + j) * kSlices * npk;
+    for (int64_t pk = lc; pk < npk; pk += NTOT) {
+      const int l = (int)(pk % 64), cb = (int)((pk / 64) % CBM), ks = (int)(pk / (64 * CBM));
+      const int n = 16 * cb + l % 16;
+      const bool nok = n < hj;
+      const int sh = nok ? colG[n] + wexp[n] : 0;
+      double y[16];
+#pragma unroll
+      for (int b = 0; b < 16; ++b) {
+        const int kk = 64 * ks + 16 * (l / 16) + b;
+        const bool lower = kk >= HK;
+        const int i = lower ? kk - HK : kk;
+        y[b] = (nok && i < hr) ? ldexp(wval(i, lower, n), -sh) : 0.0;
+      }
+      int4 sl[kSlices];
+      slice16(y, sl);
+#pragma unroll
+      for (int p = 0; p < kSlices; ++p) out[p * npk + pk] = sl[p];
+    }
+  } else {
     constexpr int CBM = MB / 16;
     const int KP = (hr + 15) & ~15;        // rows of each half, padded to the update's K chunk
     const int KS = 2 * KP / 4;

@@ -53,9 +53,15 @@ static void launch_update_t(const PencilDesc& P, const UpdRange& U, hipStream_t 
 
 // Apply source rows [s_lo, s_hi] to target rows [k_lo, k_hi) of every tile column
 // j >= j_lo.  Returns false when there is nothing to launch.
+void launch_update_i8(const PencilDesc& P, const UpdRange& U, hipStream_t s);
+
 bool launch_update(const PencilDesc& P, int k_lo, int k_hi, int j_lo, int s_lo, int s_hi, hipStream_t s) {
   if (k_hi <= k_lo || j_lo >= P.Mmax) return false;
   const UpdRange U{k_lo, k_hi, j_lo, s_lo, s_hi};
+  if (P.precision == 1) {
+    launch_update_i8(P, U, s);
+    return true;
+  }
   switch (P.mb) {
     case 32: launch_update_t<32>(P, U, s); break;
     case 64: launch_update_t<64>(P, U, s); break;

@@ -46,6 +46,56 @@ struct UpdRange {
   int s_lo, s_hi;   // source tile rows (all below every target row)
 };
 
+// Per-column scales of a band update of tile (k, j), column c (Algorithm 3 with the band's
+// sources brought to one exponent): the common exponent of Y and of the sources' W
+// segments, one ProtectUpdate bounding the sum by the tile-pair norms, and the exponent
+// g[i] of source i's W relative to the band's.  Returns fy, fa (the factors 2^fy on Y and
+// 2^fa on the product) and en, the new exponent of the segment.
+__device__ __forceinline__ void band_column_scales(const PencilDesc& P, const UpdRange& U, int k, int64_t c,
+                                                   bool first, int ns, int& fy, int& fa, int& en,
+                                                   int (&g)[kMaxBand]) {
+  const int64_t m = P.m;
+  const int WSL = P.wslots;
+  const int kind = P.blk[c];
+  int eY = 0;
+  double nY = 0.0;
+  if (!first) {
+    eY = P.exps[(int64_t)k * m + c];
+    nY = P.norms[(int64_t)k * m + c];
+    if (kind == 1) nY += P.norms[(int64_t)k * m + c + 1];
+    else if (kind == 2) nY += P.norms[(int64_t)k * m + c - 1];
+  }
+  int eWs[kMaxBand];
+  double nWs[kMaxBand], nus[kMaxBand];
+  int ew = INT_MIN;
+#pragma unroll
+  for (int i = 0; i < kMaxBand; ++i) {
+    if (i < ns) {
+      const int s = U.s_lo + i;
+      const int64_t slot = (int64_t)(s % WSL) * m + c;
+      eWs[i] = P.eW[slot];
+      nWs[i] = P.nW[slot];
+      nus[i] = P.nu[(int64_t)k * P.Mmax + s];
+      ew = max(ew, eWs[i]);
+    }
+  }
+  const int ks = eY > ew ? eY : ew;
+  // |sum_s [S_ks | T_ks] W_s| <= sum_s nu_ks ||W_s|| (each term <= 2^1000, no overflow)
+  double xb = 0.0;
+#pragma unroll
+  for (int i = 0; i < kMaxBand; ++i) {
+    g[i] = 0;
+    if (i < ns) {
+      xb += nus[i] * ldexp(nWs[i], eWs[i] - ks);
+      g[i] = eWs[i] - ew;
+    }
+  }
+  const int q = protect_update(1.0, xb, ldexp(nY, eY - ks));
+  en = ks + q;
+  fy = eY - en;
+  fa = ew - en;
+}
+
 // Shared memory of one tile update with a WGR-row wave grid.
 template <int MB, int WGR>
 struct UpdSmem {
@@ -111,45 +161,7 @@ __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange&
     const int n = tid;
     int fy = 0, fa = 0, en = 0;
     int g[kMaxBand] = {};
-    if (n < hj) {
-      const int64_t c = c0 + n;
-      const int kind = P.blk[c];
-      int eY = 0;
-      double nY = 0.0;
-      if (!first) {
-        eY = P.exps[(int64_t)k * m + c];
-        nY = P.norms[(int64_t)k * m + c];
-        if (kind == 1) nY += P.norms[(int64_t)k * m + c + 1];
-        else if (kind == 2) nY += P.norms[(int64_t)k * m + c - 1];
-      }
-      int eWs[kMaxBand];
-      double nWs[kMaxBand], nus[kMaxBand];
-      int ew = INT_MIN;
-#pragma unroll
-      for (int i = 0; i < kMaxBand; ++i) {
-        if (i < ns) {
-          const int s = U.s_lo + i;
-          const int64_t slot = (int64_t)(s % WSL) * m + c;
-          eWs[i] = P.eW[slot];
-          nWs[i] = P.nW[slot];
-          nus[i] = P.nu[(int64_t)k * P.Mmax + s];
-          ew = max(ew, eWs[i]);
-        }
-      }
-      const int ks = eY > ew ? eY : ew;
-      // |sum_s [S_ks | T_ks] W_s| <= sum_s nu_ks ||W_s|| (each term <= 2^1000, no overflow)
-      double xb = 0.0;
-#pragma unroll
-      for (int i = 0; i < kMaxBand; ++i)
-        if (i < ns) {
-          xb += nus[i] * ldexp(nWs[i], eWs[i] - ks);
-          g[i] = eWs[i] - ew;
-        }
-      const int q = protect_update(1.0, xb, ldexp(nY, eY - ks));
-      en = ks + q;
-      fy = eY - en;
-      fa = ew - en;
-    }
+    if (n < hj) band_column_scales(P, U, k, c0 + n, first, ns, fy, fa, en, g);
     sfY[n] = fy;
     sfA[n] = fa;
     seN[n] = en;

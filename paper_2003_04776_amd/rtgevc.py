@@ -35,7 +35,8 @@ class RtgevcError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("mb", ctypes.c_int32), ("normalize", ctypes.c_int32), ("band", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("watchdog", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("schedule", ctypes.c_int32), ("watchdog", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 _lib = None
@@ -84,8 +85,14 @@ SCHEDULE_BANDS = 1     # band wavefront with look-ahead (default)
 SCHEDULE_WALKER = 2    # persistent walker with device-side dependency counters
 
 
-def make_opts(mb: int = 0, normalize: bool = True, band: int = 0, schedule: int = 0, watchdog: int = 0) -> Opts:
+PRECISION_FP64 = 0
+PRECISION_MIXED = 1    # tile-update contraction on the int8 matrix cores from split operands
+
+
+def make_opts(mb: int = 0, normalize: bool = True, band: int = 0, schedule: int = 0, watchdog: int = 0,
+              precision: int = 0) -> Opts:
     o = Opts()
+    o.precision = int(precision)
     o.mb = int(mb)
     o.normalize = 1 if normalize else 0
     o.band = int(band)
@@ -94,8 +101,9 @@ def make_opts(mb: int = 0, normalize: bool = True, band: int = 0, schedule: int 
     return o
 
 
-def workspace_size(m: int, mb: int = 0, normalize: bool = True, band: int = 0, schedule: int = 0) -> int:
-    o = make_opts(mb, normalize, band, schedule)
+def workspace_size(m: int, mb: int = 0, normalize: bool = True, band: int = 0, schedule: int = 0,
+                   precision: int = 0) -> int:
+    o = make_opts(mb, normalize, band, schedule, 0, precision)
     return int(load().rtgevc_workspace_size(int(m), ctypes.byref(o)))
 
 
@@ -162,10 +170,10 @@ class Solver:
     allocation, made once by torch; the library itself allocates nothing)."""
 
     def __init__(self, m: int, mb: int = 0, normalize: bool = True, band: int = 0, device="cuda",
-                 schedule: int = 0, watchdog: int = 0):
+                 schedule: int = 0, watchdog: int = 0, precision: int = 0):
         import torch
         self.m = int(m)
-        self.opts = make_opts(mb, normalize, band, schedule, watchdog)
+        self.opts = make_opts(mb, normalize, band, schedule, watchdog, precision)
         self.nbytes = int(load().rtgevc_workspace_size(self.m, ctypes.byref(self.opts)))
         self.work = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
         self.device = device
@@ -223,10 +231,10 @@ class Solver:
 
 
 def tgevc(S, T, select=None, normalize: bool = True, mb: int = 0, band: int = 0, stream=None,
-          schedule: int = 0) -> Result:
+          schedule: int = 0, precision: int = 0) -> Result:
     """All (or the selected) right eigenvectors of the Schur pencil (S, T)."""
     return Solver(S.shape[0], mb=mb, normalize=normalize, band=band, device=S.device,
-                  schedule=schedule).run(S, T, select, stream=stream)
+                  schedule=schedule, precision=precision).run(S, T, select, stream=stream)
 
 
 def _i64_array(vals):

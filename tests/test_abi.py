@@ -67,10 +67,12 @@ def test_argument_errors_before_any_gpu_work():
     bad = rt.make_opts(mb=48)
     assert _call(opts=bad) == -13
     bad = rt.make_opts()
-    bad.reserved[2] = 1
+    bad.reserved[1] = 1
     assert _call(opts=bad) == -13
     assert _call(opts=rt.make_opts(schedule=3)) == -13
     assert _call(opts=rt.make_opts(watchdog=-1)) == -13
+    assert _call(opts=rt.make_opts(precision=2)) == -13
+    assert _call(opts=rt.make_opts(precision=1, schedule=2)) == -13
     assert _call(m=0, S=None, T=None, Z=None, work=None, lds=1, ldt=1, ldz=1) == 0
 
 

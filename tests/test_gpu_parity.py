@@ -265,13 +265,13 @@ def test_repeat_is_deterministic():
 
 # ------------------------------------------------------------- full sizes --
 
-def _full_size(m, seed, kind, nsample, mb=0):
+def _full_size(m, seed, kind, nsample, mb=0, precision=0):
     torch = _torch()
     from paper_2003_04776_amd import rtgevc as rt
-    _say(f"[full] m={m} kind={kind} seed={seed}: generating")
+    _say(f"[full] m={m} kind={kind} seed={seed} precision={precision}: generating")
     S, T, blk = pencils.schur_pencil(m, seed, kind, threads=16)
     Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
-    solver = rt.Solver(m, mb=mb)
+    solver = rt.Solver(m, mb=mb, precision=precision)
     _say("   running")
     res = solver.run(Sd, Td)
     torch.cuda.synchronize()
@@ -313,6 +313,18 @@ def test_full_size_stress_8192():
 
 def test_full_size_32768():
     _full_size(32768, 400, "normal", 12)
+
+
+def test_full_size_mixed_8192():
+    _full_size(8192, 100, "normal", 48, precision=1)
+
+
+def test_full_size_mixed_stress_8192():
+    _full_size(8192, 200, "stress", 32, precision=1)
+
+
+def test_full_size_mixed_32768():
+    _full_size(32768, 400, "normal", 12, precision=1)
 
 
 # ---- persistent walker (schedule 2) ----
@@ -381,3 +393,48 @@ def test_walker_watchdog_bit():
     r2 = rt.Solver(m, mb=32, schedule=rt.SCHEDULE_WALKER).run(Sd, Td)
     torch.cuda.synchronize()
     assert int(r2.info.item()) == 0
+
+
+# ---- mixed precision (tile-update contraction on the int8 matrix cores) ----
+
+@pytest.mark.parametrize("m,mb,band,seed", [(1, 32, 0, 500), (100, 32, 2, 501), (300, 64, 4, 502),
+                                            (700, 128, 4, 503), (1000, 128, 1, 504), (1100, 64, 8, 505)])
+def test_mixed_parity(m, mb, band, seed):
+    """Mixed precision against the oracle (same bar as FP64) and against the FP64 path."""
+    torch = _torch()
+    from paper_2003_04776_amd import rtgevc as rt
+    _say(f"[mixed] m={m} mb={mb} band={band} seed={seed}")
+    S, T, blk = pencils.schur_pencil(m, seed)
+    Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
+    rx = rt.Solver(m, mb=mb, band=band, precision=rt.PRECISION_MIXED).run(Sd, Td)
+    rd = rt.Solver(m, mb=mb, band=band).run(Sd, Td)
+    torch.cuda.synchronize()
+    assert int(rx.info.item()) == 0
+    Zx = rx.Z.cpu().numpy()
+    assert np.isfinite(Zx).all()
+    d = float(np.max(np.abs(Zx - rd.Z.cpu().numpy()))) if m else 0.0
+    worst, errs, nill = compare(S, T, Zx)
+    _say(f"   max err {worst:.3e} ill {nill}; mixed vs FP64 {d:.2e}")
+    assert worst <= TOL
+    ar, ai, be, _ = oracle.eigvals(S, T)
+    eta = residuals(S, T, Zx, ar, ai, be)
+    assert max(eta.values()) <= 64 * m * U
+
+
+def test_mixed_stress_unnormalised():
+    torch = _torch()
+    from paper_2003_04776_amd import rtgevc as rt
+    m, mb = 521, 128
+    S, T, blk = pencils.schur_pencil(m, 510, "stress")
+    Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
+    r = rt.Solver(m, mb=mb, normalize=False, precision=rt.PRECISION_MIXED).run(Sd, Td)
+    torch.cuda.synchronize()
+    Z, sc = r.Z.cpu().numpy(), r.scales.cpu().numpy()
+    assert int(r.info.item()) & ~16 == 0
+    assert np.isfinite(Z).all() and (sc >= 0).all() and sc.max() > 1000
+    Zn, _, _ = run_gpu(S, T, mb=mb)
+    rn = rt.Solver(m, mb=mb, precision=rt.PRECISION_MIXED).run(Sd, Td)
+    torch.cuda.synchronize()
+    worst, errs, nill = compare(S, T, rn.Z.cpu().numpy())
+    _say(f"   mixed stress: max err {worst:.3e} ill {nill} max scale {sc.max()}")
+    assert worst <= TOL
