@@ -9,22 +9,24 @@ namespace rgev {
 // tile row r of one pencil: tiles (r, j), j = r .. M-1
 template <int MB>
 __global__ __launch_bounds__(solve_total(MB)) void solve_kernel(PencilDesc P, int r) {
+  constexpr int CS = SolveShape<MB>::CS;
   __shared__ SolveSmem<MB> sm;
-  solve_tile<MB>(P, r, r + (int)blockIdx.x, sm);
+  solve_tile<MB>(P, r, r + (int)blockIdx.x / CS, (int)blockIdx.x % CS, sm);
 }
 
 // one lock-step of a batch: tile row M_p - 1 - t of every pencil p = blockIdx.y
 template <int MB>
 __global__ __launch_bounds__(solve_total(MB)) void solve_batched_kernel(const PencilDesc* __restrict__ D, int t) {
+  constexpr int CS = SolveShape<MB>::CS;
   __shared__ SolveSmem<MB> sm;
   const PencilDesc P = D[blockIdx.y];
   const int r = P.ctrl->M - 1 - t;
-  solve_tile<MB>(P, r, r + (int)blockIdx.x, sm);
+  solve_tile<MB>(P, r, r + (int)blockIdx.x / CS, (int)blockIdx.x % CS, sm);
 }
 
 template <int MB>
 static void launch_solve_t(const PencilDesc& P, int r, hipStream_t s) {
-  solve_kernel<MB><<<P.Mmax - r, solve_total(MB), 0, s>>>(P, r);
+  solve_kernel<MB><<<(P.Mmax - r) * SolveShape<MB>::CS, solve_total(MB), 0, s>>>(P, r);
 }
 
 void launch_solve(const PencilDesc& P, int r, hipStream_t s) {
@@ -40,11 +42,16 @@ void launch_solve(const PencilDesc& P, int r, hipStream_t s) {
 void launch_solve_batched(const PencilDesc* D, int n, int mb, int max_tiles, int t, hipStream_t s) {
   const int gx = (t + 1 < max_tiles) ? t + 1 : max_tiles;
   if (gx <= 0 || n <= 0) return;
-  const dim3 grid((unsigned)gx, (unsigned)n);
   switch (mb) {
-    case 32: solve_batched_kernel<32><<<grid, solve_total(32), 0, s>>>(D, t); break;
-    case 64: solve_batched_kernel<64><<<grid, solve_total(64), 0, s>>>(D, t); break;
-    default: solve_batched_kernel<128><<<grid, solve_total(128), 0, s>>>(D, t); break;
+    case 32:
+      solve_batched_kernel<32><<<dim3(gx * SolveShape<32>::CS, n), solve_total(32), 0, s>>>(D, t);
+      break;
+    case 64:
+      solve_batched_kernel<64><<<dim3(gx * SolveShape<64>::CS, n), solve_total(64), 0, s>>>(D, t);
+      break;
+    default:
+      solve_batched_kernel<128><<<dim3(gx * SolveShape<128>::CS, n), solve_total(128), 0, s>>>(D, t);
+      break;
   }
 }
 

@@ -132,30 +132,46 @@ constexpr int solve_threads(int mb) { return mb < 64 ? 64 : mb; }
 // copy phases (one wave per SIMD)
 constexpr int solve_total(int mb) { return mb < 64 ? 64 : 2 * mb; }
 
+// Column slices: columns are independent, so a tile may be solved by CS workgroups, split
+// at column SW (moved one right rather than split a complex pair).  With SW = MB / 2 a slice
+// needs half the LDS and can share a CU with a tile-update workgroup; measured on the band
+// schedule at m = 32768 that is slower (585 ms -> 614 ms: co-resident solves displace update
+// workgroups and double the CU time spent in solves), so one workgroup per tile is used.
+template <int MB>
+struct SolveShape {
+  static constexpr int SW = MB;                     // nominal columns per workgroup
+  static constexpr int CS = MB / SW;                // workgroups per tile (1 or 2)
+  static constexpr int NCY = CS > 1 ? SW + 1 : MB;  // most columns a workgroup holds
+  // row stride of the tile in LDS: = 1 mod 32 doubles, so that a thread per row sweeping
+  // the columns and a thread per column sweeping the rows are both conflict-free
+  static constexpr int LDY = NCY % 32 == 1 ? NCY : NCY + 1;
+};
+
 // Shared memory of one tile solve.
 template <int MB>
 struct SolveSmem {
-  static constexpr int NT = solve_threads(MB), LDY = MB + 1, G = 8;
-  double Y[MB * LDY];          // the tile (odd stride: row and column sweeps are conflict-free)
-  double Bop[2 * G][NT];       // [-beta z ; alpha z] of the group, own parts
+  static constexpr int LDY = SolveShape<MB>::LDY, BW = SolveShape<MB>::NCY, G = 8;
+  double Y[MB * LDY];          // the tile's columns held by this workgroup
+  double Bop[2 * G][BW];       // [-beta z ; alpha z] of the group, own parts
   double Sg[G][G], Tg[G][G];   // diagonal block of the group: [row][column]
   double tcnS[MB], tcnT[MB];
-  double cmax[NT];
-  double colA[NT], colB[NT], colBe[NT];
-  int fcol[NT];                // scale exponent still owed by the rows above the group
-  int ecol[NT];                // exponent of the second column of a pair
-  int colG[NT];
-  int wexp[NT];                // mixed precision: column exponent of W
+  double cmax[BW];
+  double colA[BW], colB[BW], colBe[BW];
+  int fcol[BW];                // scale exponent still owed by the rows above the group
+  int ecol[BW];                // exponent of the second column of a pair
+  int colG[BW];
+  int wexp[BW];                // mixed precision: column exponent of W
   int8_t tblk[MB];
-  int8_t colKind[NT];
+  int8_t colKind[BW];
 };
 
-// Solve of tile (r, j) of one pencil (a workgroup of solve_total(MB) threads).
+// Solve of column slice z of tile (r, j) of one pencil (a workgroup of solve_total(MB)
+// threads; slices z = 0 .. SolveShape<MB>::CS - 1).
 template <int MB>
-__device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, SolveSmem<MB>& sm) {
-  constexpr int NT = solve_threads(MB);   // one thread per column, at least one full wave
+__device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, int z, SolveSmem<MB>& sm) {
   constexpr int NTOT = solve_total(MB);
-  constexpr int LDY = MB + 1;   // odd stride: row and column sweeps are both conflict-free
+  constexpr int SW = SolveShape<MB>::SW, NCY = SolveShape<MB>::NCY;
+  constexpr int LDY = SolveShape<MB>::LDY;
   constexpr int G = 8;          // rows per group (recursive blocking inside the tile)
   auto& Y = sm.Y;
   auto& Bop = sm.Bop;
@@ -173,22 +189,34 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, So
   auto& colG = sm.colG;
   auto& colKind = sm.colKind;
 
+  __syncthreads();   // a previous solve in this workgroup is done with the shared memory
   const int M = P.ctrl->M;
   if (r < 0 || r >= M || j >= M) return;
   const int64_t m = P.m;
   const int r0 = P.edges[r], hr = P.edges[r + 1] - r0;
   const int c0 = P.edges[j], hj = P.edges[j + 1] - c0;
+  // columns [own_lo, own_hi) of tile j: split at SW, moved one right rather than split a pair
+  constexpr int CS = SolveShape<MB>::CS;
+  int sp = SW;
+  if (CS > 1 && sp < hj && P.blk[c0 + sp] == 2) ++sp;
+  const int own_lo = z == 0 ? 0 : sp;
+  const int own_hi = z == CS - 1 ? hj : min(sp, hj);
+  if (own_lo >= own_hi) return;
+  const int lo = own_lo, hw = own_hi - own_lo;
+  const bool last = own_hi == hj;     // this workgroup also clears W past the tile's columns
   const bool tip = (r == j);
   const double psc = P.ctrl->psc;
   const double* S = P.S;
   const double* T = P.T;
   const int64_t lds = P.lds, ldt = P.ldt, ldz = P.ldz;
 
-  const int lc = threadIdx.x;
+  const int lc = threadIdx.x;            // column thread lc holds tile column lo + lc
   const int wave = lc / 64, lane = lc % 64;
-  const bool inrange = lc < hj;
-  const bool colthr = lc < NT;
-  const int64_t c = c0 + lc;
+  const bool inrange = lc < hw;
+  const bool colthr = lc < NCY;
+  const int tcol = lo + lc;
+  const int64_t c = c0 + tcol;
+  const bool own = inrange;
   int kind = 0;
   bool selected = false;
   double a = 0.0, b = 0.0, be = 0.0;
@@ -202,7 +230,7 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, So
   const int partner = kind == 1 ? lc + 1 : (kind == 2 ? lc - 1 : lc);
   const bool pair = kind == 1;                 // this thread carries the pair (lc, lc + 1)
   const bool owner = selected && kind != 2;
-  const int pc = (kind == 2 ? lc - 1 : lc) + (c0 - r0);   // local row of own block (tip tile)
+  const int pc = (kind == 2 ? tcol - 1 : tcol) + (c0 - r0);   // local row of own block (tip tile)
   const double aabs = fabs(a) + fabs(b);
   int e = 0;
   double ybound = 0.0;
@@ -219,19 +247,19 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, So
   if (!tip) {
     // thread lc reads row lc of every column (coalesced down the columns), 16 loads in flight
     if (lc < hr) {
-      const double* zrow = P.Z + (r0 + lc) + (int64_t)c0 * ldz;
-      for (int col0 = 0; col0 < hj; col0 += 16) {
+      const double* zrow = P.Z + (r0 + lc) + (int64_t)(c0 + lo) * ldz;
+      for (int col0 = 0; col0 < hw; col0 += 16) {
         double v[16];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) v[t] = (col0 + t < hj) ? zrow[(int64_t)(col0 + t) * ldz] : 0.0;
+        for (int t = 0; t < 16; ++t) v[t] = (col0 + t < hw) ? zrow[(int64_t)(col0 + t) * ldz] : 0.0;
 #pragma unroll
         for (int t = 0; t < 16; ++t)
-          if (col0 + t < hj) Y[lc * LDY + col0 + t] = v[t];
+          if (col0 + t < hw) Y[lc * LDY + col0 + t] = v[t];
       }
     }
     if (inrange) {
       e = P.exps[(int64_t)r * m + c];
-      ybound = P.norms[(int64_t)r * m + c] + (kind != 0 ? P.norms[(int64_t)r * m + c0 + partner] : 0.0);
+      ybound = P.norms[(int64_t)r * m + c] + (kind != 0 ? P.norms[(int64_t)r * m + c0 + lo + partner] : 0.0);
     }
   }
 
@@ -295,7 +323,7 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, So
     // its rows from the top, the rows above it are updated in place, and the stack
     // shifts by the block size, so every register index is a constant.
     Cx stk[G];
-    const int yc0 = lc < MB ? lc : 0, yc1 = pair ? lc + 1 : yc0;   // (threads past the tile read column 0)
+    const int yc0 = lc < NCY ? lc : 0, yc1 = pair ? lc + 1 : yc0;   // (threads past the columns read column 0)
 #pragma unroll
     for (int k = 0; k < G; ++k) {
       const int row = g1 - k >= 0 ? g1 - k : 0;   // (rows above the group: never stored)
@@ -456,7 +484,7 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, So
     // ---- rank-2G update of the rows above the group on the FP64 matrix cores ----
     // Y[0:g0, :] <- 2^-fcol Y[0:g0, :] + [S | T][0:g0, group] * [-beta z ; alpha z]
     if (g0 > 0) {
-      const int nrb = (g0 + 15) / 16, ncb = (hj + 15) / 16;
+      const int nrb = (g0 + 15) / 16, ncb = (hw + 15) / 16;
       constexpr int nw = NTOT / 64;
       // A wave owns whole column blocks; its row blocks are independent chains, issued
       // interleaved.  NR (a compile-time bound on the row blocks) keeps every operand in
@@ -467,21 +495,22 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, So
         constexpr int NR = decltype(nr_c)::value;
         for (int cb = wave; cb < ncb; cb += nw) {
           const int col = 16 * cb + lane % 16;
-          const int fs = fcol[col];
+          const int colr = col < NCY ? col : NCY - 1;   // (columns past those held: dropped)
+          const int fs = fcol[colr];
           d4 acc[NR];
 #pragma unroll
           for (int rb = 0; rb < NR; ++rb)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-              acc[rb][v] = ldexp(Y[(16 * rb + lane / 16 + 4 * v) * LDY + col], -fs);
+              acc[rb][v] = ldexp(Y[(16 * rb + lane / 16 + 4 * v) * LDY + colr], -fs);
 #pragma unroll
           for (int st = 0; st < 4; ++st) {
-            const double bf = Bop[4 * st + lane / 16][col];
+            const double bf = Bop[4 * st + lane / 16][colr];
 #pragma unroll
             for (int rb = 0; rb < NR; ++rb)
               acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(psc * af[rb][st], bf, acc[rb], 0, 0, 0);
           }
-          const bool cok = col < hj;
+          const bool cok = col < hw;
 #pragma unroll
           for (int rb = 0; rb < NR; ++rb)
 #pragma unroll
@@ -517,7 +546,7 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, So
     colBe[lc] = be;
     colKind[lc] = (int8_t)kind;
   }
-  if (inrange) {
+  if (own) {
     P.exps[(int64_t)r * m + c] = e;
     P.norms[(int64_t)r * m + c] = nx;
   }
@@ -529,7 +558,7 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, So
     int g = 0;
     if (nxb > 1.0) frexp(nxb, &g);
     if (colthr) colG[lc] = g;
-    if (inrange) {
+    if (own) {
       const int64_t slot = (int64_t)(r % P.wslots) * m;
       P.eW[slot + c] = e + g;
       P.nW[slot + c] = ldexp(nxb, -g);
@@ -538,7 +567,7 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, So
   // ---- write the solved tile to Z (thread lc writes row lc: coalesced down each column) ----
   if (lc < hr) {
     double* zrow = P.Z + (r0 + lc) + (int64_t)c0 * ldz;
-    for (int col = 0; col < hj; ++col) zrow[(int64_t)col * ldz] = Y[lc * LDY + col];
+    for (int col = own_lo; col < own_hi; ++col) zrow[(int64_t)col * ldz] = Y[lc * LDY + (col - lo)];
   }
   __syncthreads();
   // ---- W = 2^-g [X D ; -X B] in operand order: [kstep][col block][lane] ----
@@ -562,15 +591,23 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, So
         for (int i = 0; i < hr; ++i) mx = fmax(mx, fmax(fabs(wval(i, false, lc)), fabs(wval(i, true, lc))));
       const int f = slice_exponent(ldexp(mx, -colG[lc]));
       wexp[lc] = f;
-      if (inrange) P.Wexp[(int64_t)(r % P.wslots) * m + c] = f;
+      if (own) P.Wexp[(int64_t)(r % P.wslots) * m + c] = f;
     }
     __syncthreads();
     const int64_t npk = slice_packets(MB);
     int4* out = P.Wslc + ((int64_t)(r % P.wslots) * P.Mmax + j) * kSlices * npk;
-    for (int64_t pk = lc; pk < npk; pk += NTOT) {
-      const int l = (int)(pk % 64), cb = (int)((pk / 64) % CBM), ks = (int)(pk / (64 * CBM));
-      const int n = 16 * cb + l % 16;
-      const bool nok = n < hj;
+    // the column blocks this workgroup's columns touch (the last one also clears the blocks
+    // past the tile); each packet is one column's, written only by that column's workgroup
+    constexpr int KSW = slice_ksteps(MB);
+    const int cb_lo = own_lo / 16, cb_hi = last ? CBM : (own_hi + 15) / 16, ob = cb_hi - cb_lo;
+    for (int q = lc; q < KSW * ob * 64; q += NTOT) {
+      const int l = q % 64, cbo = (q / 64) % ob, ks = q / (64 * ob);
+      const int cb = cb_lo + cbo;
+      const int64_t pk = ((int64_t)ks * CBM + cb) * 64 + l;
+      const int nt = 16 * cb + l % 16;        // tile column
+      if (nt < own_lo || (nt >= own_hi && !(last && nt >= hj))) continue;
+      const bool nok = nt < own_hi;
+      const int n = nok ? nt - lo : 0;        // held column
       const int sh = nok ? colG[n] + wexp[n] : 0;
       double y[16];
 #pragma unroll
@@ -590,11 +627,17 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, So
     const int KP = (hr + 15) & ~15;        // rows of each half, padded to the update's K chunk
     const int KS = 2 * KP / 4;
     double* Wj = P.W + ((int64_t)(r % P.wslots) * P.Mmax + j) * w_tile_doubles(MB);
-    // a thread keeps one (column block, lane) position and walks the K steps
-    for (int cbl = lc; cbl < CBM * 64; cbl += NTOT) {
-      const int n = 16 * (cbl / 64) + cbl % 16;
+    // a thread keeps one (column block, lane) position of the column blocks this
+    // workgroup's columns touch (the last one also clears past the tile) and walks the K
+    // steps; an entry is written only by its column's workgroup
+    const int cb_lo = own_lo / 16, cb_hi = last ? CBM : (own_hi + 15) / 16;
+    for (int q = lc; q < (cb_hi - cb_lo) * 64; q += NTOT) {
+      const int cbl = cb_lo * 64 + q;
+      const int nt = 16 * (cbl / 64) + cbl % 16;   // tile column
+      if (nt < own_lo || (nt >= own_hi && !(last && nt >= hj))) continue;
       const int l16 = (cbl % 64) / 16;
-      const bool nok = n < hj;
+      const bool nok = nt < own_hi;
+      const int n = nok ? nt - lo : 0;             // held column
       const int g = nok ? colG[n] : 0;
       const int kd = nok ? colKind[n] : 0;
       const double an = nok ? colA[n] : 0.0, bn = nok ? colB[n] : 0.0, ben = nok ? colBe[n] : 0.0;

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(solve_total(MB)) void walker_kernel(PencilDesc P, W
     if (tk.x < 0) break;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // see the producers' results
     if (tk.x == 0) {
-      solve_tile<MB>(P, tk.z, tk.w, sm.s);
+      for (int z = 0; z < SolveShape<MB>::CS; ++z) solve_tile<MB>(P, tk.z, tk.w, z, sm.s);
     } else {
       const UpdRange U{tk.y, tk.y + 1, tk.w, tk.z, tk.z};
       update_tile<MB, WGR, WGC>(P, U, tk.y, tk.w, sm.u);
