@@ -51,11 +51,23 @@ __device__ __forceinline__ int protect_update(double t, double x, double y) {
   return q > 0 ? q : 0;
 }
 
+// 1/x from the hardware reciprocal estimate refined by two Newton-Raphson steps
+// (r <- r + r (1 - x r); each step squares the relative error), for normal x whose
+// reciprocal is normal: the divisions of the diagonal solves, whose divisors are at least
+// smin >= the smallest normal number and whose quotients are bounded by ProtectDivision.
+// A shorter dependent chain than the correctly rounded division, within a few ulps of it.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
 // Complex quotient (a + ib) / (c + id) by Smith's method, with the refinements of
 // Baudin & Smith (2012) for intermediate products that underflow.  Requires |d| <= |c|.
 __device__ __forceinline__ void smith_core(double a, double b, double c, double d, double& e, double& f) {
-  const double r = d / c;
-  const double t = 1.0 / (c + d * r);
+  const double r = d * recip(c);
+  const double t = recip(c + d * r);
   if (r != 0.0 || d == 0.0) {
     // (d == 0 lands here too: r = 0 and the products with r vanish)
     const double br = b * r;

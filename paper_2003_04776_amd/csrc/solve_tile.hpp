@@ -361,7 +361,8 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
             if (fabs(m21) < smin) { m21 = smin; flags |= kInfoPerturbed; }
             const int qd = with_margin(protect_division(cn1(nn), fabs(m21)));
             const Cx ns = cscl(nn, qd);
-            z0 = cx(ns.r / m21, ns.i / m21);
+            const double rm = recip(m21);
+            z0 = cx(ns.r * rm, ns.i * rm);
             z1 = cx(ldexp(1.0, -qd), 0.0);
             qs += qd;
           }
