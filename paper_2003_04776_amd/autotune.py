@@ -1,8 +1,9 @@
 """Autotuner: sweeps the performance parameters of the solver on the GPU and writes the
 table the library compiles in.
 
-Parameters are performance choices only — tile size mb and update band R for single
-pencils, tile size per order bucket for batches — never bounds: every choice computes
+Parameters are performance choices only — tile size mb, update band R and schedule (band
+wavefront or persistent walker) for single pencils, tile size per order bucket for batches —
+never bounds: every choice computes
 the same eigenvectors, so a table from another machine is safe, merely slower.
 
     python -m paper_2003_04776_amd.autotune [--out-dir DIR] [--quick]
@@ -33,18 +34,23 @@ BANDS = (1, 2, 4, 8)
 
 
 def single_candidates(m):
+    """(mb, band, schedule) candidates: the band wavefront with every band size, and the
+    persistent walker (one source row per update) up to m = 8192 (beyond, its workspace of
+    every tile's W grows past 1 GB and it has never been competitive)."""
     for mb in MBS:
         if m >= 8192 and mb == 32:
             continue       # thousands of tile rows: never competitive, and slow to sweep
         if mb > 2 * m:
             continue
         for band in BANDS:
-            yield mb, band
+            yield mb, band, 1
+        if m <= 8192:
+            yield mb, 1, 2
 
 
-def time_single(m, mb, band, Sd, Td, Z, sc, info, reps):
+def time_single(m, mb, band, schedule, Sd, Td, Z, sc, info, reps):
     from paper_2003_04776_amd import rtgevc as rt
-    solver = rt.Solver(m, mb=mb, band=band)
+    solver = rt.Solver(m, mb=mb, band=band, schedule=schedule)
     solver.run_timed(Sd, Td, Z, sc, info)          # warm-up (first launch of each kernel)
     best = math.inf
     for _ in range(reps):
@@ -71,14 +77,15 @@ def time_batch(ms, mb, Sd, Td, reps):
 
 
 def choose_single(results):
-    """results: {m: {(mb, band): ms}} -> table entries (m_max, mb, band), sizes ascending;
-    each measured size's best choice covers up to the geometric midpoint to the next."""
+    """results: {m: {(mb, band, schedule): ms}} -> table entries (m_max, mb, band, schedule),
+    sizes ascending; each measured size's best choice covers up to the geometric midpoint to
+    the next."""
     sizes = sorted(results)
     out = []
     for i, m in enumerate(sizes):
-        (mb, band), _ = min(results[m].items(), key=lambda kv: kv[1])
+        (mb, band, schedule), _ = min(results[m].items(), key=lambda kv: kv[1])
         m_max = int(math.sqrt(m * sizes[i + 1])) if i + 1 < len(sizes) else None
-        out.append((m_max, mb, band))
+        out.append((m_max, mb, band, schedule))
     return out
 
 
@@ -100,8 +107,8 @@ def render_inc(single, batch, source):
         "// Single pencils: the first entry with m <= m_max applies.",
         "static const TuneSingle kTuneSingle[] = {",
     ]
-    for m_max, mb, band in single:
-        lines.append(f"    {{{m_max if m_max is not None else 'INT64_MAX'}, {mb}, {band}}},")
+    for m_max, mb, band, schedule in single:
+        lines.append(f"    {{{m_max if m_max is not None else 'INT64_MAX'}, {mb}, {band}, {schedule}}},")
     lines += ["};", "// Pencils of a batch (tile size per order bucket).", "static const TuneBatch kTuneBatch[] = {"]
     for m_max, mb in batch:
         lines.append(f"    {{{m_max if m_max is not None else 'INT64_MAX'}, {mb}}},")
@@ -135,11 +142,11 @@ def main():
         sc = torch.empty(m, dtype=torch.int32, device="cuda")
         info = torch.zeros(1, dtype=torch.int32, device="cuda")
         single[m] = {}
-        for mb, band in single_candidates(m):
-            t = time_single(m, mb, band, Sd, Td, Z, sc, info, args.reps)
-            single[m][(mb, band)] = t
-            record["single"].setdefault(str(m), {})[f"mb={mb},band={band}"] = round(t, 4)
-            print(f"[tune] single m={m} mb={mb} band={band}: {t:.3f} ms", flush=True)
+        for mb, band, schedule in single_candidates(m):
+            t = time_single(m, mb, band, schedule, Sd, Td, Z, sc, info, args.reps)
+            single[m][(mb, band, schedule)] = t
+            record["single"].setdefault(str(m), {})[f"mb={mb},band={band},schedule={schedule}"] = round(t, 4)
+            print(f"[tune] single m={m} mb={mb} band={band} schedule={schedule}: {t:.3f} ms", flush=True)
         del Sd, Td, Z
         torch.cuda.empty_cache()
     batch = {}
@@ -162,7 +169,7 @@ def main():
         del Sd, Td
         torch.cuda.empty_cache()
     ch_single, ch_batch = choose_single(single), choose_batch(batch)
-    record["chosen_single"] = [{"m_max": a, "mb": b, "band": c} for a, b, c in ch_single]
+    record["chosen_single"] = [{"m_max": a, "mb": b, "band": c, "schedule": d} for a, b, c, d in ch_single]
     record["chosen_batch"] = [{"m_max": a, "mb": b} for a, b in ch_batch]
     os.makedirs(args.out_dir, exist_ok=True)
     with open(os.path.join(args.out_dir, "tuning.json"), "w") as f:

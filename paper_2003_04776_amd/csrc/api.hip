@@ -40,7 +40,7 @@ __host__ __device__ inline size_t up(size_t x) { return (x + kAlign - 1) / kAlig
 
 struct TuneSingle {
   int64_t m_max;
-  int32_t mb, band;
+  int32_t mb, band, schedule;
 };
 struct TuneBatch {
   int64_t m_max;
@@ -56,6 +56,7 @@ const TuneSingle& tune_single(int64_t m) {
 }
 
 int resolve_band(int64_t m, const rtgevc_opts* o) { return (o && o->band) ? o->band : tune_single(m).band; }
+int resolve_schedule(int64_t m, const rtgevc_opts* o);
 
 int resolve_mb(int64_t m, const rtgevc_opts* o) { return (o && o->mb) ? o->mb : tune_single(m).mb; }
 
@@ -75,8 +76,12 @@ bool opts_ok(const rtgevc_opts* o) {
 
 int resolve_precision(const rtgevc_opts* o) { return (o && o->precision == 1) ? 1 : 0; }
 
-// 1 = band wavefront on two streams, 2 = persistent walker
-int resolve_schedule(const rtgevc_opts* o) { return (o && o->schedule == 2) ? 2 : 1; }
+// 1 = band wavefront on two streams, 2 = persistent walker (FP64 updates only)
+int resolve_schedule(int64_t m, const rtgevc_opts* o) {
+  if (o && o->schedule) return o->schedule;
+  if (o && o->precision == 1) return 1;
+  return tune_single(m).schedule;
+}
 constexpr int kDefaultSpinLimit = 1 << 26;   // about two seconds of waiting
 
 struct Carve {
@@ -358,7 +363,7 @@ size_t rtgevc_workspace_size(int64_t m, const rtgevc_opts* opts) {
   memset(&P, 0, sizeof(P));
   WalkDesc W;
   return carve(P, nullptr, m, resolve_mb(m, opts), resolve_band(m, opts),
-               resolve_schedule(opts) == 2 ? &W : nullptr, resolve_precision(opts));
+               resolve_schedule(m, opts) == 2 ? &W : nullptr, resolve_precision(opts));
 }
 
 int rtgevc(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt, const int32_t* select,
@@ -370,7 +375,7 @@ int rtgevc(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt
   if (ldz < (m > 1 ? m : 1)) return -8;
   if (m == 0) return 0;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (resolve_schedule(opts) == 2) {
+  if (resolve_schedule(m, opts) == 2) {
     WalkDesc W;
     PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts, &W);
     launch_preprocess(P, s);
@@ -418,7 +423,7 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
   for (int i = 0; i < nstats; ++i) stats[i] = 0.0;
   if (m == 0) return 0;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const bool walker = resolve_schedule(opts) == 2;
+  const bool walker = resolve_schedule(m, opts) == 2;
   WalkDesc W;
   PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts, walker ? &W : nullptr);
   // events bracket every launch on the stream it runs on
@@ -600,10 +605,13 @@ int rtgevc_resolve_opts(int64_t m, int32_t batched, const rtgevc_opts* opts, rtg
   if (batched) {
     out->mb = batch_mb(m, opts);
     out->band = 1;
+    out->schedule = 1;
   } else {
     out->mb = resolve_mb(m, opts);
     out->band = resolve_band(m, opts);
+    out->schedule = resolve_schedule(m, opts);
   }
+  out->precision = opts ? opts->precision : 0;
   return 0;
 }
 

@@ -107,11 +107,15 @@ def workspace_size(m: int, mb: int = 0, normalize: bool = True, band: int = 0, s
     return int(load().rtgevc_workspace_size(int(m), ctypes.byref(o)))
 
 
-def resolve_opts(m: int, batched: bool = False, mb: int = 0, band: int = 0, normalize: bool = True):
-    """(mb, band) the library would use for order m with these options."""
-    o, out = make_opts(mb, normalize, band), Opts()
+def resolve_opts(m: int, batched: bool = False, mb: int = 0, band: int = 0, normalize: bool = True,
+                 schedule: int = 0, precision: int = 0, with_schedule: bool = False):
+    """(mb, band) — and the schedule with with_schedule — the library would use for order m
+    with these options."""
+    o, out = make_opts(mb, normalize, band, schedule, 0, precision), Opts()
     _check(load().rtgevc_resolve_opts(int(m), 1 if batched else 0, ctypes.byref(o), ctypes.byref(out)),
            "rtgevc_resolve_opts")
+    if with_schedule:
+        return int(out.mb), int(out.band), int(out.schedule)
     return int(out.mb), int(out.band)
 
 
