@@ -11,16 +11,21 @@
 // A launch applies a band of source rows s in [s_lo, s_hi] (only s <= j for tile column
 // j) to the target tiles k in [k_lo, k_hi), j in [j_lo, M): each source's W keeps its
 // own exponent, the per-column factors that bring the band to one exponent are exact
-// powers of two applied while W is staged, and one ProtectUpdate bounds the sum.
+// powers of two applied to the W fragments as they are loaded, and one ProtectUpdate
+// bounds the sum.
 //
-// One workgroup per target tile (k, j).  The K dimension (2 h_s per source, each half
-// padded to 16) is streamed in chunks of 16 through two LDS stages; the loads of the
-// chunk after next are issued before the matrix cores start on the current chunk, so
-// every global load has two chunks of compute to arrive (one barrier per chunk).  The
-// waves split the tile into a WGR x WGC grid (2 x 4 for MB = 128: 64 x 32 per wave,
-// so four waves share each SIMD when two workgroups share a CU).  Tiles are visited in
-// 8 x 8 blocks, each XCD taking a contiguous range of blocks, so the S/T and W tiles
-// that neighbouring workgroups share stay in that XCD's L2.
+// One workgroup per target tile (k, j); its waves split the tile into a WGR x WGC grid
+// (2 x 2 for MB = 128: 64 x 64 per wave, 16 independent accumulators, two waves per SIMD
+// when two workgroups share a CU).  Each wave streams its own matrix-core fragments straight from global memory into
+// registers, with no LDS staging and no barrier in the K loop: an A fragment (16 rows x 4
+// K values of column-major S or T) is four fully used 128-byte lines, a W fragment one
+// 512-byte run of the packed W tile, and the waves sharing rows or columns of the tile
+// meet in L1.  The loads of step t + 2 are in flight while the matrix cores run step t.
+// The padded K rows need no mask: their W rows are zero and the A columns they meet are
+// clamped to the source tile's last column (finite values); A rows past the target tile
+// are clamped into the matrix and their outputs never stored.  Tiles are visited in 8 x 8
+// blocks, each XCD taking a contiguous range of blocks, so the S/T and W tiles that
+// neighbouring workgroups share stay in that XCD's L2.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -33,12 +38,14 @@ namespace rgev {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+
 constexpr int kChunk = 16;   // K rows per LDS stage
 
-template <int MB> struct UpdShape;   // wave grid per tile size
-template <> struct UpdShape<128> { static constexpr int R = 2, C = 4; };
-template <> struct UpdShape<64> { static constexpr int R = 2, C = 4; };
-template <> struct UpdShape<32> { static constexpr int R = 2, C = 2; };
+// wave grid R x C per tile size and S, the register slots of the fragment pipeline
+template <int MB> struct UpdShape;
+template <> struct UpdShape<128> { static constexpr int R = 2, C = 2, S = 3; };
+template <> struct UpdShape<64> { static constexpr int R = 2, C = 4, S = 3; };
+template <> struct UpdShape<32> { static constexpr int R = 2, C = 2, S = 3; };
 
 struct UpdRange {
   int k_lo, k_hi;   // target tile rows [k_lo, k_hi)
@@ -99,8 +106,6 @@ __device__ __forceinline__ void band_column_scales(const PencilDesc& P, const Up
 // Shared memory of one tile update with a WGR-row wave grid.
 template <int MB, int WGR>
 struct UpdSmem {
-  double As[2][kChunk * MB];   // [k][row]
-  double Ws[2][kChunk * MB];   // packed [kstep][col block][lane]
   int sfY[MB], sfA[MB], seN[MB];
   int sg[kMaxBand][MB];        // exponent of each source's W relative to the band's
   int sgany[kMaxBand];
@@ -118,11 +123,6 @@ __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange&
   constexpr int RB = WR / 16;           // row blocks per wave
   constexpr int CB = WC / 16;           // column blocks per wave
   constexpr int CBM = MB / 16;          // column blocks of a W tile
-  constexpr int TPR = kUpdThreads / MB; // threads per A row in the stage load
-  constexpr int AK = kChunk / TPR;      // A values per thread per stage
-  constexpr int WV = kChunk * MB / kUpdThreads;   // W values per thread per stage
-  auto& As = sm.As;
-  auto& Ws = sm.Ws;
   auto& sfY = sm.sfY;
   auto& sfA = sm.sfA;
   auto& seN = sm.seN;
@@ -142,12 +142,14 @@ __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange&
   const int ns = s_end - U.s_lo + 1;
   const bool first = (j <= U.s_hi);
   int cs[kMaxBand + 1];     // cumulative K chunks per source
+  int es[kMaxBand + 1];     // first row of each source tile (and the end of the last)
   cs[0] = 0;
+  es[0] = P.edges[U.s_lo];
 #pragma unroll
   for (int i = 0; i < kMaxBand; ++i) {
     const int s = U.s_lo + i;
-    const int hs = i < ns ? P.edges[s + 1] - P.edges[s] : 0;
-    cs[i + 1] = cs[i] + 2 * ((hs + 15) & ~15) / kChunk;
+    es[i + 1] = i < ns ? P.edges[s + 1] : es[i];
+    cs[i + 1] = cs[i] + 2 * ((es[i + 1] - es[i] + 15) & ~15) / kChunk;
   }
   const int tid = threadIdx.x;
   if (tid < kMaxBand) sgany[tid] = 0;
@@ -172,71 +174,55 @@ __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange&
     }
   }
 
-  // ---- K loop ----
+  // ---- K loop: fragments straight from global memory into registers ----
+  // K step t of a source (4 K values) with q = KP / 4 steps per half: the S columns
+  // e_s + 4 t + 0..3 for t < q, else the T columns e_s + 4 (t - q) + 0..3.  A lane's A
+  // fragment element is row 16 a + li of its wave's rows and K value lk; its W fragment
+  // element is the packed entry (step, column block, lane) of the source's W tile.
   const double psc = P.ctrl->psc;
-  const int nch = cs[ns];
-  const int arow = tid % MB;           // stage-load row of this thread
-  const int akof = tid / MB;           // first k of this thread (stride TPR)
-  const bool arow_ok = arow < hk;
-  const double* __restrict__ Srow = P.S + (k0 + arow);
-  const double* __restrict__ Trow = P.T + (k0 + arow);
+  const int nst = cs[ns] * (kChunk / 4);   // K steps of the band
+  __syncthreads();   // per-column scales and W exponent flags published
+  int sgbits = 0;    // sources whose W exponents differ from the band's in some column
+#pragma unroll
+  for (int i = 0; i < kMaxBand; ++i) sgbits |= (sgany[i] != 0) << i;
+  const bool fix_a = psc != 1.0;
 
-  // chunk c -> source index i, lower (T) half or not, first K row of the chunk
-  struct ChunkPos { int i, kb, hs; bool lower; int cc; };
-  auto where = [&](int c) {
-    ChunkPos p{0, 0, 0, false, 0};
+  int rowA[RB];      // clamped matrix rows of the lane's A elements
 #pragma unroll
-    for (int i = 1; i < kMaxBand; ++i)
-      if (i < ns && c >= cs[i]) p.i = i;
-    const int s = U.s_lo + p.i;
-    const int e_s = P.edges[s];
-    p.hs = P.edges[s + 1] - e_s;
-    p.cc = c - cs[p.i];
-    const int half = (cs[p.i + 1] - cs[p.i]) / 2;
-    p.lower = p.cc >= half;
-    p.kb = e_s + kChunk * (p.lower ? p.cc - half : p.cc);   // absolute column of S or T
-    return p;
+  for (int a = 0; a < RB; ++a) rowA[a] = min(k0 + WR * wr + 16 * a + li, (int)m - 1);
+  // loader state: the next K step to load
+  int ls_i = 0, ls_t = 0, ls_q = 0, ls_es = 0, ls_clast = 0;
+  const double* ls_w = nullptr;
+  auto enter_source = [&](int i) {
+    ls_i = i;
+    ls_t = 0;
+    ls_es = es[i];
+    ls_clast = es[i + 1] - 1;
+    ls_q = ((es[i + 1] - es[i] + 15) & ~15) / 4;
+    ls_w = P.W + ((int64_t)((U.s_lo + i) % WSL) * P.Mmax + j) * w_tile_doubles(MB) + (CB * wc) * 64 + lane;
   };
-
-  // Every load is unconditional (a masked element reads a valid address), and the
-  // zero mask is applied only when the chunk is written to LDS, so the loads stay in
-  // flight while the matrix cores work.
-  const double* safe = P.S;
-  auto fetch = [&](int c, double (&ra)[AK], double (&rw)[WV]) {
-    const ChunkPos p = where(c);
-    const int s = U.s_lo + p.i;
-    const int64_t ld = p.lower ? P.ldt : P.lds;
-    const double* pa = (p.lower ? Trow : Srow) + (int64_t)(p.kb + akof) * ld;
-    const int64_t step = (int64_t)TPR * ld;
-    const int krel = p.kb - P.edges[s] + akof;
+  enter_source(0);
+  // Loads are unconditional (past the band's last step the loader stays on that step and
+  // reloads it), so the compiler's count of loads in flight stays exact and a wave waits
+  // only for the slot it is about to use; everything that needs the data (the rare
+  // scalings, the zeroing of the steps past the end) happens when the slot is used.
+  auto load = [&](double (&af)[RB], double (&bf)[CB], int (&sgl)[CB]) {
+    const bool lower = ls_t >= ls_q;
+    const double* base = lower ? P.T : P.S;
+    const int64_t ld = lower ? P.ldt : P.lds;
+    const int col = min(ls_es + 4 * (lower ? ls_t - ls_q : ls_t) + lk, ls_clast);
+    const double* colp = base + (int64_t)col * ld;
 #pragma unroll
-    for (int i = 0; i < AK; ++i) {
-      const bool ok = arow_ok && (krel + TPR * i < p.hs);
-      ra[i] = *(ok ? pa + i * step : safe);
+    for (int a = 0; a < RB; ++a) af[a] = colp[rowA[a]];
+    const double* wp = ls_w + (int64_t)ls_t * (CBM * 64);
+#pragma unroll
+    for (int q = 0; q < CB; ++q) bf[q] = wp[q * 64];
+    if (sgbits) {
+#pragma unroll
+      for (int q = 0; q < CB; ++q) sgl[q] = sg[ls_i][16 * (CB * wc + q) + li];
     }
-    const double* wsrc = P.W + ((int64_t)(s % WSL) * P.Mmax + j) * w_tile_doubles(MB) +
-                         (int64_t)p.cc * kChunk * MB + tid;
-#pragma unroll
-    for (int i = 0; i < WV; ++i) rw[i] = wsrc[i * kUpdThreads];
-  };
-  auto stash = [&](int b, int c, const double (&ra)[AK], const double (&rw)[WV]) {
-    const ChunkPos p = where(c);
-    const int krel = p.kb - P.edges[U.s_lo + p.i] + akof;
-#pragma unroll
-    for (int i = 0; i < AK; ++i) {
-      const bool ok = arow_ok && (krel + TPR * i < p.hs);
-      As[b][(akof + TPR * i) * MB + arow] = ok ? psc * ra[i] : 0.0;
-    }
-    if (sgany[p.i]) {
-#pragma unroll
-      for (int i = 0; i < WV; ++i) {
-        const int n = 16 * (((i * kUpdThreads + tid) / 64) % CBM) + tid % 16;
-        Ws[b][i * kUpdThreads + tid] = ldexp(rw[i], sg[p.i][n]);
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < WV; ++i) Ws[b][i * kUpdThreads + tid] = rw[i];
-    }
+    if (ls_t + 1 < 2 * ls_q) ++ls_t;
+    else if (ls_i + 1 < ns) enter_source(ls_i + 1);
   };
 
   d4 acc[RB][CB];
@@ -244,44 +230,63 @@ __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange&
   for (int a = 0; a < RB; ++a)
 #pragma unroll
     for (int b = 0; b < CB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-
-  double ra0[AK], rw0[WV], ra1[AK], rw1[WV], ra2[AK], rw2[WV];
-  fetch(0, ra0, rw0);
-  if (1 < nch) fetch(1, ra1, rw1);
-  __syncthreads();   // per-column scales published; old scales all read before any rewrite
-  stash(0, 0, ra0, rw0);
-  __syncthreads();
-  for (int c = 0; c < nch; ++c) {
-    const int b = c & 1;
-    if (c + 2 < nch) fetch(c + 2, ra2, rw2);
+  // operands swapped: acc holds (A W)^T blocks, so a lane's four accumulator registers
+  // are one C row of four columns and a wave's store covers whole lines
+  auto use = [&](double (&af)[RB], double (&bf)[CB], const int (&sgl)[CB], bool live) {
+    if (!live) {             // a step past the band's end: W = 0
 #pragma unroll
-    for (int s = 0; s < kChunk / 4; ++s) {
-      double af[RB], bf[CB];
+      for (int q = 0; q < CB; ++q) bf[q] = 0.0;
+    } else {
+      // rare: a prescaled pencil, or sources whose W exponents differ from the band's
+      if (fix_a) {
 #pragma unroll
-      for (int a = 0; a < RB; ++a) af[a] = As[b][(4 * s + lk) * MB + WR * wr + 16 * a + li];
+        for (int a = 0; a < RB; ++a) af[a] *= psc;
+      }
+      if (sgbits) {
 #pragma unroll
-      for (int q = 0; q < CB; ++q) bf[q] = Ws[b][(s * CBM + CB * wc + q) * 64 + lane];
-      // operands swapped: acc holds (A W)^T blocks, so a lane's four accumulator
-      // registers are one C row of four columns and a wave's store covers whole lines
-#pragma unroll
-      for (int a = 0; a < RB; ++a)
-#pragma unroll
-        for (int q = 0; q < CB; ++q)
-          acc[a][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[q], af[a], acc[a][q], 0, 0, 0);
+        for (int q = 0; q < CB; ++q) bf[q] = ldexp(bf[q], sgl[q]);
+      }
     }
-    if (c + 1 < nch) stash(b ^ 1, c + 1, ra1, rw1);
-    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < AK; ++i) ra1[i] = ra2[i];
+    for (int a = 0; a < RB; ++a)
 #pragma unroll
-    for (int i = 0; i < WV; ++i) rw1[i] = rw2[i];
+      for (int q = 0; q < CB; ++q)
+        acc[a][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[q], af[a], acc[a][q], 0, 0, 0);
+  };
+
+  // NS register slots rotate through an unrolled loop: the loads of step t + NS - 1 are in
+  // flight while the matrix cores run step t; the step count is rounded up to NS
+  constexpr int NS = UpdShape<MB>::S;
+  double af[NS][RB], bf[NS][CB];
+  int sgl[NS][CB] = {};
+  const int nrun = (nst + NS - 1) / NS * NS;
+#pragma unroll
+  for (int u = 0; u < NS - 1; ++u) load(af[u], bf[u], sgl[u]);
+  for (int t0 = 0; t0 < nrun; t0 += NS) {
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      load(af[(u + NS - 1) % NS], bf[(u + NS - 1) % NS], sgl[(u + NS - 1) % NS]);
+      use(af[u], bf[u], sgl[u], t0 + u < nst);
+    }
   }
 
   // ---- epilogue: Y <- 2^fY Y - 2^fA acc and the new segment norms ----
   // block (a, q) of the transposed product: lane holds C row 16 a + lane % 16 (within
-  // the wave's rows) for columns 16 q + lane / 16 + 4 v, v = 0..3
+  // the wave's rows) for columns 16 q + lane / 16 + 4 v, v = 0..3.  The old Y of a column
+  // block is loaded at once, from addresses clamped into the tile, so the loads overlap;
+  // only the stores are masked.
 #pragma unroll
   for (int q = 0; q < CB; ++q) {
+    double yo[4][RB];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int nc = min(WC * wc + 16 * q + lk + 4 * v, hj - 1);
+#pragma unroll
+      for (int a = 0; a < RB; ++a) {
+        const int ic = min(WR * wr + 16 * a + li, hk - 1);
+        yo[v][a] = first ? 0.0 : P.Z[(k0 + ic) + (int64_t)(c0 + nc) * P.ldz];
+      }
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int n = WC * wc + 16 * q + lk + 4 * v;
@@ -293,8 +298,7 @@ __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange&
         for (int a = 0; a < RB; ++a) {
           const int i = WR * wr + 16 * a + li;
           if (i < hk) {
-            const double yo = first ? 0.0 : zc[16 * a];
-            const double yn = ldexp(yo, fy) - ldexp(acc[a][q][v], fa);
+            const double yn = ldexp(yo[v][a], fy) - ldexp(acc[a][q][v], fa);
             zc[16 * a] = yn;
             cmx = fmax(cmx, fabs(yn));
           }
