@@ -44,7 +44,7 @@ constexpr int kChunk = 16;   // K rows per LDS stage
 // wave grid R x C per tile size and S, the register slots of the fragment pipeline
 template <int MB> struct UpdShape;
 template <> struct UpdShape<128> { static constexpr int R = 2, C = 2, S = 3; };
-template <> struct UpdShape<64> { static constexpr int R = 2, C = 4, S = 3; };
+template <> struct UpdShape<64> { static constexpr int R = 2, C = 2, S = 3; };
 template <> struct UpdShape<32> { static constexpr int R = 2, C = 2, S = 3; };
 
 struct UpdRange {
