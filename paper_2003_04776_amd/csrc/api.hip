@@ -128,6 +128,8 @@ __host__ __device__ size_t carve(PencilDesc& P, char* base, int64_t m, int mb, i
     P.Aexp = c.take<int32_t>(base, pairs * mb);
     P.Wslc = c.take<int4>(base, (size_t)wslots * Mmax * kSlices * slice_packets(mb));
     P.Wexp = c.take<int32_t>(base, (size_t)wslots * m);
+    P.exps_next = c.take<int32_t>(base, (size_t)Mmax * m);
+    P.norms_next = c.take<unsigned long long>(base, (size_t)Mmax * m);
   }
   if (walk) {
     walk->cnt = c.take<int32_t>(base, (size_t)Mmax * Mmax);

@@ -69,6 +69,12 @@ struct PencilDesc {
   int32_t* Aexp;      // [pair][MB] row exponents of those tiles
   int4* Wslc;         // slices of W per source-row slot and tile column
   int32_t* Wexp;      // [slot][m] column exponents of W
+  // the new segment exponents and norms of a mixed-precision update launch whose tiles are
+  // split over several workgroups (row groups): norms combined by an atomic maximum on the
+  // bits of the non-negative doubles, published into exps/norms (and cleared) once the
+  // launch is done, so that no workgroup reads a segment another one has already rewritten
+  int32_t* exps_next;            // [Mmax * m]
+  unsigned long long* norms_next; // [Mmax * m], zero between launches
   int32_t mb;
   int32_t Mmax;
   int32_t normalize;

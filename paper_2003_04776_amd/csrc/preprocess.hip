@@ -266,6 +266,8 @@ __device__ __forceinline__ void pre_fixup_body(const PencilDesc& P) {
     P.cnS[c] = ldexp(P.cnS[c], shift) * (1.0 + 2.220446049250313e-16);
     P.cnT[c] = ldexp(P.cnT[c], shift) * (1.0 + 2.220446049250313e-16);
   }
+  if (P.precision == 1)   // the mixed-precision updates combine their norms here
+    for (int64_t i = tid; i < (int64_t)P.Mmax * P.m; i += stride) P.norms_next[i] = 0ull;
 }
 
 // Mixed precision: split every super-diagonal tile pair A = [S_kr | T_kr] (prescaled)
