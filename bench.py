@@ -280,8 +280,10 @@ def main():
         mwall = (time.perf_counter() - t0) / max(args.steps, 1) * 1e3
         mflops = sum(x["update_flops"] for x in mst)
         mupd = sum(x["update_ms"] for x in mst)
+        mmb, mband = rt.resolve_opts(m, mb=args.mb, band=args.band, precision=1)
         out["mixed"] = {
             "precision": "tile-update contraction on int8 matrix cores, operands split into 7 x 7-bit slices",
+            "mb": mmb, "band": mband,
             "ms_per_step": round(mwall, 3),
             "value": round(F / (mwall * 1e-3) / 1e12, 4),
             "speedup_vs_fp64": round(ms_per_step / mwall, 4),

@@ -2,8 +2,8 @@
 table the library compiles in.
 
 Parameters are performance choices only — tile size mb, update band R and schedule (band
-wavefront or persistent walker) for single pencils, tile size per order bucket for batches —
-never bounds: every choice computes
+wavefront or persistent walker) for single pencils in FP64, tile size and band for the
+mixed-precision mode, tile size per order bucket for batches — never bounds: every choice computes
 the same eigenvectors, so a table from another machine is safe, merely slower.
 
     python -m paper_2003_04776_amd.autotune [--out-dir DIR] [--quick]
@@ -48,9 +48,18 @@ def single_candidates(m):
             yield mb, 1, 2
 
 
-def time_single(m, mb, band, schedule, Sd, Td, Z, sc, info, reps):
+def mixed_candidates(m):
+    """(mb, band) candidates of the mixed-precision mode (band wavefront only)."""
+    for mb in MBS:
+        if mb == 32 or mb > 2 * m:
+            continue
+        for band in BANDS:
+            yield mb, band
+
+
+def time_single(m, mb, band, schedule, Sd, Td, Z, sc, info, reps, precision=0):
     from paper_2003_04776_amd import rtgevc as rt
-    solver = rt.Solver(m, mb=mb, band=band, schedule=schedule)
+    solver = rt.Solver(m, mb=mb, band=band, schedule=schedule, precision=precision)
     solver.run_timed(Sd, Td, Z, sc, info)          # warm-up (first launch of each kernel)
     best = math.inf
     for _ in range(reps):
@@ -76,16 +85,21 @@ def time_batch(ms, mb, Sd, Td, reps):
     return best
 
 
-def choose_single(results):
-    """results: {m: {(mb, band, schedule): ms}} -> table entries (m_max, mb, band, schedule),
-    sizes ascending; each measured size's best choice covers up to the geometric midpoint to
-    the next."""
+def choose_single(results, mixed=None):
+    """results: {m: {(mb, band, schedule): ms}}, mixed: {m: {(mb, band): ms}} -> table entries
+    (m_max, mb, band, schedule, mb_mixed, band_mixed), sizes ascending; each measured size's
+    best choice covers up to the geometric midpoint to the next.  Without mixed timings the
+    mixed columns repeat the FP64 tile size and band."""
     sizes = sorted(results)
     out = []
     for i, m in enumerate(sizes):
         (mb, band, schedule), _ = min(results[m].items(), key=lambda kv: kv[1])
+        if mixed and mixed.get(m):
+            (mbx, bandx), _ = min(mixed[m].items(), key=lambda kv: kv[1])
+        else:
+            mbx, bandx = mb, band
         m_max = int(math.sqrt(m * sizes[i + 1])) if i + 1 < len(sizes) else None
-        out.append((m_max, mb, band, schedule))
+        out.append((m_max, mb, band, schedule, mbx, bandx))
     return out
 
 
@@ -104,11 +118,12 @@ def render_inc(single, batch, source):
         "// Performance parameters chosen per problem size (never bounds: every choice computes",
         "// the same eigenvectors).  Written by paper_2003_04776_amd/autotune.py from a sweep on",
         f"// the GPU ({source}).",
-        "// Single pencils: the first entry with m <= m_max applies.",
+        "// Single pencils: the first entry with m <= m_max applies: {m_max, mb, band, schedule} for",
+        "// FP64, then {mb, band} for mixed precision.",
         "static const TuneSingle kTuneSingle[] = {",
     ]
-    for m_max, mb, band, schedule in single:
-        lines.append(f"    {{{m_max if m_max is not None else 'INT64_MAX'}, {mb}, {band}, {schedule}}},")
+    for m_max, mb, band, schedule, mbx, bandx in single:
+        lines.append(f"    {{{m_max if m_max is not None else 'INT64_MAX'}, {mb}, {band}, {schedule}, {mbx}, {bandx}}},")
     lines += ["};", "// Pencils of a batch (tile size per order bucket).", "static const TuneBatch kTuneBatch[] = {"]
     for m_max, mb in batch:
         lines.append(f"    {{{m_max if m_max is not None else 'INT64_MAX'}, {mb}}},")
@@ -132,7 +147,7 @@ def main():
 
     dev = torch.cuda.get_device_properties(0)
     record = {"device": dev.name, "gcn_arch": getattr(dev, "gcnArchName", ""), "single": {}, "batch": {}}
-    single = {}
+    single, mixed = {}, {}
     sizes = [m for m in SINGLE_SIZES if not (args.quick and m > 8192)]
     for m in sizes:
         S, T, _ = pencils.schur_pencil(m, 500 + m, threads=16)
@@ -147,6 +162,12 @@ def main():
             single[m][(mb, band, schedule)] = t
             record["single"].setdefault(str(m), {})[f"mb={mb},band={band},schedule={schedule}"] = round(t, 4)
             print(f"[tune] single m={m} mb={mb} band={band} schedule={schedule}: {t:.3f} ms", flush=True)
+        mixed[m] = {}
+        for mb, band in mixed_candidates(m):
+            t = time_single(m, mb, band, 1, Sd, Td, Z, sc, info, args.reps, precision=1)
+            mixed[m][(mb, band)] = t
+            record.setdefault("mixed", {}).setdefault(str(m), {})[f"mb={mb},band={band}"] = round(t, 4)
+            print(f"[tune] mixed m={m} mb={mb} band={band}: {t:.3f} ms", flush=True)
         del Sd, Td, Z
         torch.cuda.empty_cache()
     batch = {}
@@ -168,8 +189,9 @@ def main():
             print(f"[tune] batch [{lo},{hi}) x{len(ms)} mb={mb}: {t:.3f} ms", flush=True)
         del Sd, Td
         torch.cuda.empty_cache()
-    ch_single, ch_batch = choose_single(single), choose_batch(batch)
-    record["chosen_single"] = [{"m_max": a, "mb": b, "band": c, "schedule": d} for a, b, c, d in ch_single]
+    ch_single, ch_batch = choose_single(single, mixed), choose_batch(batch)
+    record["chosen_single"] = [{"m_max": a, "mb": b, "band": c, "schedule": d, "mb_mixed": e, "band_mixed": f}
+                               for a, b, c, d, e, f in ch_single]
     record["chosen_batch"] = [{"m_max": a, "mb": b} for a, b in ch_batch]
     os.makedirs(args.out_dir, exist_ok=True)
     with open(os.path.join(args.out_dir, "tuning.json"), "w") as f:

@@ -40,7 +40,8 @@ __host__ __device__ inline size_t up(size_t x) { return (x + kAlign - 1) / kAlig
 
 struct TuneSingle {
   int64_t m_max;
-  int32_t mb, band, schedule;
+  int32_t mb, band, schedule;   // FP64
+  int32_t mb_mixed, band_mixed; // mixed precision (always the band wavefront)
 };
 struct TuneBatch {
   int64_t m_max;
@@ -55,10 +56,17 @@ const TuneSingle& tune_single(int64_t m) {
   return kTuneSingle[n - 1];
 }
 
-int resolve_band(int64_t m, const rtgevc_opts* o) { return (o && o->band) ? o->band : tune_single(m).band; }
+bool mixed(const rtgevc_opts* o) { return o && o->precision == 1; }
+int resolve_band(int64_t m, const rtgevc_opts* o) {
+  if (o && o->band) return o->band;
+  return mixed(o) ? tune_single(m).band_mixed : tune_single(m).band;
+}
 int resolve_schedule(int64_t m, const rtgevc_opts* o);
 
-int resolve_mb(int64_t m, const rtgevc_opts* o) { return (o && o->mb) ? o->mb : tune_single(m).mb; }
+int resolve_mb(int64_t m, const rtgevc_opts* o) {
+  if (o && o->mb) return o->mb;
+  return mixed(o) ? tune_single(m).mb_mixed : tune_single(m).mb;
+}
 
 bool opts_ok(const rtgevc_opts* o) {
   if (!o) return true;
