@@ -55,7 +55,7 @@ template <int MB> struct I8Shape {
 template <int MB>
 __device__ __forceinline__ void update_i8_tile(const PencilDesc& P, const UpdRange& U, int k, int j, int cg,
                                                int rg) {
-  constexpr int NW = I8Shape<MB>::NW, ROWS = I8Shape<MB>::ROWS, COLS = I8Shape<MB>::COLS;
+  constexpr int NW = I8Shape<MB>::NW, COLS = I8Shape<MB>::COLS;
   constexpr int NRG = I8Shape<MB>::NRG;
   constexpr int KS = slice_ksteps(MB), RBN = MB / 16, CBM = MB / 16;
   static_assert(KS % 2 == 0, "the A fragments alternate between two buffers per K step");

@@ -117,7 +117,6 @@ struct UpdSmem {
 template <int MB, int WGR, int WGC>
 __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange& U, int k, int j,
                                             UpdSmem<MB, WGR>& sm) {
-  constexpr int kUpdThreads = 64 * WGR * WGC;
   constexpr int WR = MB / WGR;          // rows per wave
   constexpr int WC = MB / WGC;          // columns per wave
   constexpr int RB = WR / 16;           // row blocks per wave
