@@ -155,7 +155,8 @@ int rtgevc_timed(int64_t m, const double *S, int64_t lds, const double *T, int64
  * pencil's arguments obey the rules of rtgevc().  work: device workspace, 256-byte
  * aligned, of at least rtgevc_batched_workspace_size(count, m, opts) bytes.  opts as
  * for rtgevc(); its band is not used (the batch always applies one source row per
- * step), its mb, when non-zero, applies to every pencil.
+ * step), nor its schedule and precision (the batch runs FP64 tile updates in lock-step);
+ * its mb, when non-zero, applies to every pencil.
  *
  * Pencils are grouped by tile size (automatic per order unless opts->mb is set); each
  * group runs in lock-step (step t solves tile row M_p - 1 - t of every pencil p of the
