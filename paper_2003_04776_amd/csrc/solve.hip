@@ -8,7 +8,7 @@ namespace rgev {
 
 // tile row r of one pencil: tiles (r, j), j = r .. M-1
 template <int MB>
-__global__ __launch_bounds__(solve_total(MB)) void solve_kernel(PencilDesc P, int r) {
+__global__ __launch_bounds__(solve_total(MB), solve_waves_per_simd(MB)) void solve_kernel(PencilDesc P, int r) {
   constexpr int CS = SolveShape<MB>::CS;
   __shared__ SolveSmem<MB> sm;
   solve_tile<MB>(P, r, r + (int)blockIdx.x / CS, (int)blockIdx.x % CS, sm);
@@ -16,7 +16,7 @@ __global__ __launch_bounds__(solve_total(MB)) void solve_kernel(PencilDesc P, in
 
 // one lock-step of a batch: tile row M_p - 1 - t of every pencil p = blockIdx.y
 template <int MB>
-__global__ __launch_bounds__(solve_total(MB)) void solve_batched_kernel(const PencilDesc* __restrict__ D, int t) {
+__global__ __launch_bounds__(solve_total(MB), solve_waves_per_simd(MB)) void solve_batched_kernel(const PencilDesc* __restrict__ D, int t) {
   constexpr int CS = SolveShape<MB>::CS;
   __shared__ SolveSmem<MB> sm;
   const PencilDesc P = D[blockIdx.y];
