@@ -101,7 +101,7 @@ def bench_batched(args):
         S, T, _ = pencils.schur_pencil(m, 3000 + i)
         Sd.append(rt.colmajor_to_device(S))
         Td.append(rt.colmajor_to_device(T))
-    bs = rt.BatchSolver(ms, mb=args.mb)
+    bs = rt.BatchSolver(ms, mb=args.mb, band=args.band)
     Z, sc, info = bs.outputs()
     bs.run(Sd, Td, Z, sc, info)
     torch.cuda.synchronize()
@@ -136,7 +136,8 @@ def bench_batched(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{len(ms)} independent real Schur pencils, orders U{{64..2048}} (seed 3999), all "
                                f"eigenvectors, robust FP64, one batched call replayed from a graph",
-                   "sum_m": sum(ms), "flops_per_step": F, "mb": args.mb or "automatic"},
+                   "sum_m": sum(ms), "flops_per_step": F, "mb": args.mb or "automatic",
+                   "band": rt.resolve_opts(max(ms), batched=True, mb=args.mb, band=args.band)[1]},
         "info_nonzero": int((info != 0).sum().item()),
     }
     print(json.dumps(out), flush=True)

@@ -154,14 +154,15 @@ int rtgevc_timed(int64_t m, const double *S, int64_t lds, const double *T, int64
  * pencil); info is a DEVICE int32[count] (or NULL) receiving each pencil's bits.  Every
  * pencil's arguments obey the rules of rtgevc().  work: device workspace, 256-byte
  * aligned, of at least rtgevc_batched_workspace_size(count, m, opts) bytes.  opts as
- * for rtgevc(); its band is not used (the batch always applies one source row per
- * step), nor its schedule and precision (the batch runs FP64 tile updates in lock-step);
- * its mb, when non-zero, applies to every pencil.
+ * for rtgevc(); its mb and band, when non-zero, apply to every pencil (band 0: 2); its
+ * schedule and precision are not used (the batch runs FP64 tile updates in lock-step).
  *
  * Pencils are grouped by tile size (automatic per order unless opts->mb is set); each
- * group runs in lock-step (step t solves tile row M_p - 1 - t of every pencil p of the
- * group and updates the rows above it), one launch per step and kernel for the whole
- * group.  The call enqueues kernels only: no allocation, no copy, no synchronisation,
+ * group runs in lock-step over bands of R tile rows (step t solves the rows of band
+ * B_p - 1 - t of every pencil p of the group, bottom-up with the updates inside the band,
+ * then applies the band to the rows above it), one launch per part of a step and kernel
+ * for the whole group.  The eigenvectors equal those of rtgevc() with the same tile size
+ * and band.  The call enqueues kernels only: no allocation, no copy, no synchronisation,
  * so it can be captured in a HIP graph and replayed (the host arrays are read during
  * the call; the device pointers they hold must stay valid for every replay).
  * Returns 0 when enqueued; -i for argument i (1-based; per-pencil violations report

@@ -6,6 +6,7 @@
 //                          update rows above from row r (every tile column j >= r at once)
 //                   ->  post-processing (consolidation / normalisation).
 // All work is enqueued on the caller's stream; nothing is allocated, nothing waits.
+#include <algorithm>
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -24,8 +25,9 @@ void launch_solve(const PencilDesc& P, int r, hipStream_t s);
 bool launch_update(const PencilDesc& P, int k_lo, int k_hi, int j_lo, int s_lo, int s_hi, hipStream_t s);
 void launch_consolidate(const PencilDesc& P, hipStream_t s);
 void launch_preprocess_batched(const PencilDesc* D, int n, int64_t max_m, int max_tiles, hipStream_t s);
-void launch_solve_batched(const PencilDesc* D, int n, int mb, int max_tiles, int t, hipStream_t s);
-void launch_update_batched(const PencilDesc* D, int n, int mb, int max_tiles, int t, hipStream_t s);
+void launch_solve_batched(const PencilDesc* D, int n, int mb, int max_tiles, int R, int t, int io, hipStream_t s);
+void launch_update_batched(const PencilDesc* D, int n, int mb, int max_tiles, int R, int t, int io, int band,
+                           int kmax, hipStream_t s);
 void launch_consolidate_batched(const PencilDesc* D, int n, int64_t max_m, hipStream_t s);
 void launch_eigvals_out(const PencilDesc& P, double* are, double* aim, double* bet, hipStream_t s);
 hipError_t launch_walk(const PencilDesc& P, const WalkDesc& W, hipStream_t s);
@@ -152,9 +154,12 @@ __host__ __device__ size_t carve(PencilDesc& P, char* base, int64_t m, int mb, i
 int hip_code(hipError_t e) { return e == hipSuccess ? 0 : -1000 - (int)e; }
 
 // ---- batches ----
-// Pencils are grouped by tile size; each group runs in lock-step: step t solves tile row
-// M_p - 1 - t of every pencil p of the group and applies it to all rows above, so one
-// launch carries the same step of the whole group.  The descriptor table lives at the
+// Pencils are grouped by tile size; each group runs in lock-step over bands of R tile rows
+// (the single-pencil band schedule without the look-ahead): step t takes band B_p - 1 - t
+// of every pencil p of the group (B_p bands from the top, the last one possibly short),
+// solves its rows bottom-up, each followed by the in-band update of the band rows above
+// it, then applies the band to every row above it; one launch carries the same part of a
+// step for the whole group.  The descriptor table lives at the
 // start of the workspace and is written by small set-up kernels whose arguments carry
 // the per-pencil parameters by value, so the whole call is a fixed sequence of kernel
 // launches (a HIP graph can capture and replay it).
@@ -167,13 +172,14 @@ struct BatchArg {
   int32_t* scales;
   const int32_t* select;
   int32_t* info;
-  int32_t mb, normalize;
+  int32_t mb, normalize, band;
 };
-constexpr int kSetupPerLaunch = 32;   // 32 x 96 bytes of kernel arguments per launch
+constexpr int kSetupPerLaunch = 32;   // 32 x 104 bytes of kernel arguments per launch
 struct BatchSetup {
   BatchArg a[kSetupPerLaunch];
   int32_t n, first;
 };
+static_assert(sizeof(BatchSetup) <= 4096, "kernel arguments of one set-up launch");
 
 __global__ void batch_setup_kernel(BatchSetup su, PencilDesc* table, char* work) {
   const int i = threadIdx.x;
@@ -189,13 +195,16 @@ __global__ void batch_setup_kernel(BatchSetup su, PencilDesc* table, char* work)
   P.Z = a.Z;
   P.scales = a.scales;
   P.select = a.select;
-  carve(P, work + a.off, a.m, a.mb, 1);
+  carve(P, work + a.off, a.m, a.mb, a.band);
   P.info = a.info ? a.info : &P.ctrl->info_local;
   P.normalize = a.normalize;
   table[su.first + i] = P;
 }
 
 constexpr int kBatchMbs[3] = {32, 64, 128};
+constexpr int kBatchBand = 2;   // source rows per lock-step update of a batch (opts->band overrides)
+
+int batch_band(const rtgevc_opts* o) { return (o && o->band) ? o->band : kBatchBand; }
 
 int batch_mb(int64_t m, const rtgevc_opts* o) {
   if (o && o->mb) return o->mb;
@@ -213,7 +222,7 @@ size_t batch_layout(int32_t count, const int64_t* m, const rtgevc_opts* o, int64
     if (m[i] <= 0) continue;
     PencilDesc P;
     memset(&P, 0, sizeof(P));
-    off += carve(P, nullptr, m[i], batch_mb(m[i], o), 1);
+    off += carve(P, nullptr, m[i], batch_mb(m[i], o), batch_band(o));
   }
   return off;
 }
@@ -554,6 +563,7 @@ int rtgevc_batched(int32_t count, const int64_t* m, const double* const* S, cons
   char* base = static_cast<char*>(work);
   PencilDesc* table = reinterpret_cast<PencilDesc*>(base);
   const int normalize = opts ? opts->normalize : 1;
+  const int R = batch_band(opts);
   hipError_t err = hipSuccess;
   int first = 0;
   for (int g = 0; g < 3 && err == hipSuccess; ++g) {
@@ -578,6 +588,7 @@ int rtgevc_batched(int32_t count, const int64_t* m, const double* const* S, cons
       a.info = info ? info + i : nullptr;
       a.mb = mb;
       a.normalize = normalize;
+      a.band = R;
       args.push_back(a);
       if (m[i] > max_m) max_m = m[i];
       const int tb = tile_bound(m[i], mb);
@@ -595,9 +606,19 @@ int rtgevc_batched(int32_t count, const int64_t* m, const double* const* S, cons
     }
     const PencilDesc* D = table + first;
     launch_preprocess_batched(D, n, max_m, max_tiles, s);
-    for (int t = 0; t < max_tiles; ++t) {
-      launch_solve_batched(D, n, mb, max_tiles, t, s);
-      launch_update_batched(D, n, mb, max_tiles, t, s);
+    // the device's tile count of a pencil is at most tile_bound, so its band of step t
+    // starts at most at R (ceil(tile_bound / R) - 1 - t)
+    std::vector<int> bands;
+    for (const BatchArg& a : args) bands.push_back((tile_bound(a.m, mb) + R - 1) / R);
+    const int steps = (max_tiles + R - 1) / R;
+    for (int t = 0; t < steps; ++t) {
+      for (int io = 0; io < R; ++io) {
+        launch_solve_batched(D, n, mb, max_tiles, R, t, io, s);
+        if (io + 1 < R) launch_update_batched(D, n, mb, max_tiles, R, t, io, 0, R - 1, s);
+      }
+      int kmax = 0;
+      for (int nb : bands) kmax = std::max(kmax, R * (nb - 1 - t));
+      launch_update_batched(D, n, mb, max_tiles, R, t, 0, 1, kmax, s);
     }
     launch_consolidate_batched(D, n, max_m, s);
     err = hipGetLastError();
@@ -614,7 +635,7 @@ int rtgevc_resolve_opts(int64_t m, int32_t batched, const rtgevc_opts* opts, rtg
   out->normalize = opts ? opts->normalize : 1;
   if (batched) {
     out->mb = batch_mb(m, opts);
-    out->band = 1;
+    out->band = batch_band(opts);
     out->schedule = 1;
   } else {
     out->mb = resolve_mb(m, opts);

@@ -14,13 +14,18 @@ __global__ __launch_bounds__(solve_total(MB), solve_waves_per_simd(MB)) void sol
   solve_tile<MB>(P, r, r + (int)blockIdx.x / CS, (int)blockIdx.x % CS, sm);
 }
 
-// one lock-step of a batch: tile row M_p - 1 - t of every pencil p = blockIdx.y
+// one solve of a batch's lock-step t: in band B_p - 1 - t of every pencil p = blockIdx.y
+// (bands of R tile rows from the top, B_p of them), the row io places above the band's
+// last row; tiles (r, j), j >= r
 template <int MB>
-__global__ __launch_bounds__(solve_total(MB), solve_waves_per_simd(MB)) void solve_batched_kernel(const PencilDesc* __restrict__ D, int t) {
+__global__ __launch_bounds__(solve_total(MB), solve_waves_per_simd(MB)) void solve_batched_kernel(const PencilDesc* __restrict__ D, int R, int t, int io) {
   constexpr int CS = SolveShape<MB>::CS;
   __shared__ SolveSmem<MB> sm;
   const PencilDesc P = D[blockIdx.y];
-  const int r = P.ctrl->M - 1 - t;
+  const int M = P.ctrl->M;
+  const int b = (M + R - 1) / R - 1 - t;
+  const int r_hi = min(R * b + R - 1, M - 1);
+  const int r = b >= 0 && r_hi - io >= R * b ? r_hi - io : -1;   // -1: no row (solve_tile returns)
   solve_tile<MB>(P, r, r + (int)blockIdx.x / CS, (int)blockIdx.x % CS, sm);
 }
 
@@ -39,18 +44,19 @@ void launch_solve(const PencilDesc& P, int r, hipStream_t s) {
 
 // Batch step t for the n pencils of table D (all with tile size mb and at most
 // max_tiles tiles): grid (t + 1) x n; pencils with fewer than t + 1 tiles exit at once.
-void launch_solve_batched(const PencilDesc* D, int n, int mb, int max_tiles, int t, hipStream_t s) {
-  const int gx = (t + 1 < max_tiles) ? t + 1 : max_tiles;
+void launch_solve_batched(const PencilDesc* D, int n, int mb, int max_tiles, int R, int t, int io, hipStream_t s) {
+  // a band-R lock-step t reaches at most R (t + 1) tile columns: M - R b <= R (t + 1)
+  const int gx = (R * (t + 1) < max_tiles) ? R * (t + 1) : max_tiles;
   if (gx <= 0 || n <= 0) return;
   switch (mb) {
     case 32:
-      solve_batched_kernel<32><<<dim3(gx * SolveShape<32>::CS, n), solve_total(32), 0, s>>>(D, t);
+      solve_batched_kernel<32><<<dim3(gx * SolveShape<32>::CS, n), solve_total(32), 0, s>>>(D, R, t, io);
       break;
     case 64:
-      solve_batched_kernel<64><<<dim3(gx * SolveShape<64>::CS, n), solve_total(64), 0, s>>>(D, t);
+      solve_batched_kernel<64><<<dim3(gx * SolveShape<64>::CS, n), solve_total(64), 0, s>>>(D, R, t, io);
       break;
     default:
-      solve_batched_kernel<128><<<dim3(gx * SolveShape<128>::CS, n), solve_total(128), 0, s>>>(D, t);
+      solve_batched_kernel<128><<<dim3(gx * SolveShape<128>::CS, n), solve_total(128), 0, s>>>(D, R, t, io);
       break;
   }
 }

@@ -26,19 +26,31 @@ void update_kernel(PencilDesc P, UpdRange U) {
   update_tile<MB, UpdShape<MB>::R, UpdShape<MB>::C>(P, U, k, j, sm);
 }
 
-// one lock-step of a batch: source row r = M_p - 1 - t of pencil p = blockIdx.y applied to
-// every tile (k, j), k < r <= j; blockIdx.x enumerates (k, j) row-major
+// one update of a batch's lock-step t for pencil p = blockIdx.y, in its band B_p - 1 - t
+// (tile rows [r_lo, r_hi]): band = 0: the in-band update after the solve of row
+// r = r_hi - io, targets k in [r_lo, r), j >= r, source r; band = 1: the band applied to
+// every row above it, targets k < r_lo, j >= r_lo, sources r_lo .. r_hi (the ranges of the
+// single-pencil band schedule).  blockIdx.x enumerates (k - k_lo, j - j_lo) with J columns.
 template <int MB>
 __global__ __launch_bounds__(64 * UpdShape<MB>::R * UpdShape<MB>::C, UpdShape<MB>::R * UpdShape<MB>::C / 2)
-void update_batched_kernel(const PencilDesc* __restrict__ D, int t) {
+void update_batched_kernel(const PencilDesc* __restrict__ D, int R, int t, int io, int band, int J) {
   const PencilDesc P = D[blockIdx.y];
   const int M = P.ctrl->M;
-  const int r = M - 1 - t;
-  if (r <= 0) return;
-  const int nj = M - r;
-  const int k = (int)blockIdx.x / nj, j = r + (int)blockIdx.x % nj;
-  if (k >= r) return;
-  const UpdRange U{0, r, r, r, r};
+  const int b = (M + R - 1) / R - 1 - t;
+  if (b < 0) return;
+  const int r_lo = R * b, r_hi = min(r_lo + R - 1, M - 1);
+  UpdRange U;
+  if (band) {
+    if (r_lo == 0) return;
+    U = UpdRange{0, r_lo, r_lo, r_lo, r_hi};
+  } else {
+    const int r = r_hi - io;
+    if (r <= r_lo) return;
+    U = UpdRange{r_lo, r, r, r, r};
+  }
+  const int kk = (int)blockIdx.x / J, jj = (int)blockIdx.x % J;
+  const int k = U.k_lo + kk, j = U.j_lo + jj;
+  if (k >= U.k_hi || j >= M) return;
   __shared__ UpdSmem<MB, UpdShape<MB>::R> sm;
   update_tile<MB, UpdShape<MB>::R, UpdShape<MB>::C>(P, U, k, j, sm);
 }
@@ -70,16 +82,19 @@ bool launch_update(const PencilDesc& P, int k_lo, int k_hi, int j_lo, int s_lo, 
   return true;
 }
 
-// Batch step t (see update_batched_kernel): the grid covers (k, j) for the largest pencil,
-// k < r and r <= j < M with r = M - 1 - t, so at most (max_tiles - 1 - t) (t + 1) tiles.
-void launch_update_batched(const PencilDesc* D, int n, int mb, int max_tiles, int t, hipStream_t s) {
-  const int64_t nk = (int64_t)max_tiles - 1 - t, nj = t + 1;
-  if (nk <= 0 || n <= 0) return;
-  const dim3 grid((unsigned)(nk * nj), (unsigned)n);
+// Batch lock-step t, band R (see update_batched_kernel): kmax bounds the target rows (R - 1
+// in a band; for the band update, the largest first row of the step's bands), and the
+// columns j - j_lo < R (t + 1).
+void launch_update_batched(const PencilDesc* D, int n, int mb, int max_tiles, int R, int t, int io, int band,
+                           int kmax, hipStream_t s) {
+  const int64_t J = (R * (t + 1) < max_tiles) ? R * (t + 1) : max_tiles;
+  if (kmax <= 0 || J <= 0 || n <= 0) return;
+  const dim3 grid((unsigned)(kmax * J), (unsigned)n);
+  const int Ji = (int)J;
   switch (mb) {
-    case 32: update_batched_kernel<32><<<grid, 64 * UpdShape<32>::R * UpdShape<32>::C, 0, s>>>(D, t); break;
-    case 64: update_batched_kernel<64><<<grid, 64 * UpdShape<64>::R * UpdShape<64>::C, 0, s>>>(D, t); break;
-    default: update_batched_kernel<128><<<grid, 64 * UpdShape<128>::R * UpdShape<128>::C, 0, s>>>(D, t); break;
+    case 32: update_batched_kernel<32><<<grid, 64 * UpdShape<32>::R * UpdShape<32>::C, 0, s>>>(D, R, t, io, band, Ji); break;
+    case 64: update_batched_kernel<64><<<grid, 64 * UpdShape<64>::R * UpdShape<64>::C, 0, s>>>(D, R, t, io, band, Ji); break;
+    default: update_batched_kernel<128><<<grid, 64 * UpdShape<128>::R * UpdShape<128>::C, 0, s>>>(D, R, t, io, band, Ji); break;
   }
 }
 

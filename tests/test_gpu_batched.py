@@ -85,19 +85,23 @@ def test_batched_parity_mixed_sizes(mb):
         assert max(eta.values()) <= 64 * m * U
 
 
-def test_batched_matches_single_calls():
-    """A pencil gives the same eigenvectors alone and inside a batch (same tile size)."""
+@pytest.mark.parametrize("band", [1, 3, 4])
+def test_batched_matches_single_calls(band):
+    """A pencil gives the same eigenvectors alone and inside a batch (same tile size and
+    band: the batch's lock-step applies the same tile updates in the same groups)."""
     torch = _torch()
     from paper_2003_04776_amd import rtgevc as rt
-    ms = [300, 129, 700]
+    ms = [300, 129, 700, 64, 1]
     batch = _batch(ms, 3100)
     Sd, Td = _upload(batch)
-    Z, _, _ = rt.tgevc_batched(Sd, Td, mb=64)
+    Z, _, info = rt.tgevc_batched(Sd, Td, mb=64, band=band)
+    torch.cuda.synchronize()
+    assert int(info.abs().sum().item()) == 0
     for i in range(len(ms)):
-        r = rt.tgevc(Sd[i], Td[i], mb=64, band=1)
+        r = rt.tgevc(Sd[i], Td[i], mb=64, band=band)
         torch.cuda.synchronize()
         d = float((Z[i] - r.Z).abs().max())
-        _say(f"   pencil {i} m={ms[i]}: batched vs single {d:.2e}")
+        _say(f"   band {band} pencil {i} m={ms[i]}: batched vs single {d:.2e}")
         assert d <= 1e-13
 
 
