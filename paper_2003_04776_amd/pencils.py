@@ -25,12 +25,19 @@ Recipe (per pencil, seed ``seed``):
 * ``kind="stress"``: every diagonal t is 10**U[-12, -6] and every off-diagonal entry
   of S and T is multiplied by 1e100 (the 2x2 internals a, b, c stay unscaled), so
   unscaled substitution overflows within a few rows.
+* ``kind="zeroinf"``: the normal pencil with one zero eigenvalue (s = 0 in the 1x1 block
+  one third of the way down the list of 1x1 blocks) and one infinite eigenvalue (t = 0
+  in the block two thirds down): distinct eigenvalues, so every eigenvector is defined.
+* ``kind="degenerate"``: the normal pencil where, after its regular draws, every 1x1
+  block's column draws one more uniform u: u < 0.01 sets s = 0 (zero eigenvalue),
+  0.01 <= u < 0.02 sets t = 0 (infinite eigenvalue) -- about 1 percent of each, as in the
+  pencils of the paper's experiments (Section 6), so some eigenvalues repeat.
 """
 from __future__ import annotations
 
 import numpy as np
 
-KINDS = ("normal", "stress")
+KINDS = ("normal", "stress", "zeroinf", "degenerate")
 
 
 def _stream(seed: int, j: int) -> np.random.Generator:
@@ -64,6 +71,11 @@ def fill_columns(S: np.ndarray, T: np.ndarray, kind_arr: np.ndarray, seed: int,
     """Write columns [j0, j1) of S and T (arrays indexed [row, col], any strides)."""
     m = kind_arr.shape[0]
     offscale = 1e100 if kind == "stress" else 1.0
+    zero_at = inf_at = -1
+    if kind == "zeroinf":
+        ones = np.flatnonzero(kind_arr == 0)
+        if len(ones) >= 2:
+            zero_at, inf_at = int(ones[len(ones) // 3]), int(ones[(2 * len(ones)) // 3])
     for j in range(j0, j1):
         rng = _stream(seed, j + 1)
         b0 = j - 1 if kind_arr[j] == 2 else j
@@ -93,6 +105,17 @@ def fill_columns(S: np.ndarray, T: np.ndarray, kind_arr: np.ndarray, seed: int,
             if offscale != 1.0:
                 cs *= offscale
                 ct *= offscale
+        if kind_arr[j] == 0:
+            if j == zero_at:
+                S[j, j] = 0.0
+            elif j == inf_at:
+                T[j, j] = 0.0
+            elif kind == "degenerate":
+                u = rng.random()
+                if u < 0.01:
+                    S[j, j] = 0.0
+                elif u < 0.02:
+                    T[j, j] = 0.0
     del m
 
 

@@ -85,6 +85,36 @@ def test_parity_small(m, mb, seed):
     assert max(eta.values()) <= 64 * m * U
 
 
+@pytest.mark.parametrize("m,mb,seed,kind,precision", [(300, 64, 40, "zeroinf", 0), (700, 128, 41, "zeroinf", 0),
+                                                      (701, 128, 42, "zeroinf", 1), (1000, 64, 43, "degenerate", 0),
+                                                      (1000, 128, 44, "degenerate", 1)])
+def test_zero_and_infinite_eigenvalues(m, mb, seed, kind, precision):
+    """Zero (s_jj = 0) and infinite (t_jj = 0, beta = 0) eigenvalues, as in the pencils of
+    the paper's experiments: one of each (distinct eigenvalues), or about 1 percent of each
+    (repeated: their singular pivots are perturbed, info bit 16, and the columns whose
+    double and extended-precision oracles disagree are left out of the comparison)."""
+    torch = _torch()
+    from paper_2003_04776_amd import rtgevc as rt
+    _say(f"[zero/inf] m={m} mb={mb} seed={seed} kind={kind} precision={precision}")
+    S, T, blk = pencils.schur_pencil(m, seed, kind)
+    Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
+    r = rt.Solver(m, mb=mb, precision=precision).run(Sd, Td)
+    torch.cuda.synchronize()
+    Zg, info = r.Z.cpu().numpy(), int(r.info.item())
+    if kind == "zeroinf":
+        assert info == 0, info
+    else:
+        assert info & ~16 == 0, info
+    assert np.isfinite(Zg).all()
+    worst, errs, nill = compare(S, T, Zg)
+    _say(f"   max err {worst:.3e} (ill {nill})")
+    assert worst <= TOL
+    ar, ai, be, _ = oracle.eigvals(S, T)
+    assert (be == 0).sum() >= 1 and ((ar == 0) & (ai == 0)).sum() >= 1
+    eta = residuals(S, T, Zg, ar, ai, be)
+    assert max(eta.values()) <= 64 * m * U
+
+
 @pytest.mark.parametrize("m,mb,band,seed", [(300, 32, 1, 30), (301, 32, 2, 31), (333, 32, 3, 32),
                                              (450, 32, 4, 33), (1000, 64, 3, 34), (1100, 128, 4, 35),
                                              (700, 64, 1, 36)])

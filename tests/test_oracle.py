@@ -189,20 +189,22 @@ def _mp_eigvec(S, T, p, kind, dps=80):
     """Independent reference: the eigenvalue of the diagonal block from mpmath's
     standard eigensolver of T_b^-1 S_b, then row-oriented block back-substitution
     in 80-digit arithmetic with unbounded exponent range and no scaling at all
-    (2x2 diagonal blocks solved by mpmath's LU on the 2x2 system)."""
+    (2x2 diagonal blocks solved by mpmath's LU on the 2x2 system).  A 1x1 block uses
+    the homogeneous matrix t_pp S - s_pp T, a multiple of S - lambda T that stays
+    defined for an infinite eigenvalue (t_pp = 0)."""
     mpmath.mp.dps = dps
     nb = 2 if kind[p] == 1 else 1
     n = p + nb
     Sm = mpmath.matrix([[mpmath.mpf(float(S[i, j])) for j in range(n)] for i in range(n)])
     Tm = mpmath.matrix([[mpmath.mpf(float(T[i, j])) if i <= j else 0 for j in range(n)] for i in range(n)])
     if nb == 1:
-        lam = Sm[p, p] / Tm[p, p]
+        lam = None
     else:
         Sb = Sm[p:p + 2, p:p + 2]
         Tb = Tm[p:p + 2, p:p + 2]
         ev = mpmath.eig(mpmath.inverse(Tb) * Sb, left=False, right=False)
         lam = [e for e in ev if mpmath.im(e) > 0][0]
-    M = Sm - lam * Tm
+    M = Tm[p, p] * Sm - Sm[p, p] * Tm if nb == 1 else Sm - lam * Tm
     z = [mpmath.mpc(0)] * n
     if nb == 1:
         z[p] = mpmath.mpc(1)
@@ -225,7 +227,8 @@ def _mp_eigvec(S, T, p, kind, dps=80):
 
 
 @pytest.mark.parametrize("kind,seed,m", [("normal", 11, 12), ("normal", 12, 9), ("stress", 13, 12),
-                                         ("stress", 14, 10), ("normal", 15, 7)])
+                                         ("stress", 14, 10), ("normal", 15, 7), ("zeroinf", 16, 12),
+                                         ("zeroinf", 17, 9)])
 def test_tiny_pencils_against_high_precision(kind, seed, m):
     S, T, blk = pencils.schur_pencil(m, seed, kind)
     Z, sc, info = oracle.tgevc(S, T)
@@ -272,7 +275,10 @@ def _match_scipy(S, T, Z, blk, ar, ai, be, w, V):
         if blk[p] == 2:
             continue
         lam = lam_o[p]
-        j = int(np.argmin(np.abs(w - lam)))
+        if np.isinf(lam):   # an infinite eigenvalue: LAPACK's beta = 0 gives a non-finite w
+            j = int(np.flatnonzero(~np.isfinite(w))[0])
+        else:
+            j = int(np.argmin(np.where(np.isfinite(w), np.abs(w - lam), np.inf)))
         assert j not in used
         used.add(j)
         v = V[:, j]
@@ -282,10 +288,12 @@ def _match_scipy(S, T, Z, blk, ar, ai, be, w, V):
     return worst
 
 
-@pytest.mark.parametrize("m,seed", [(20, 21), (40, 22), (64, 23)])
-def test_against_lapack_generalized_eig(m, seed):
-    """Eigenvectors parallel to those of LAPACK xGGEV (scipy.linalg.eig(S, T))."""
-    S, T, blk = pencils.schur_pencil(m, seed)
+@pytest.mark.parametrize("m,seed,kind", [(20, 21, "normal"), (40, 22, "normal"), (64, 23, "normal"),
+                                         (40, 24, "zeroinf"), (64, 25, "zeroinf")])
+def test_against_lapack_generalized_eig(m, seed, kind):
+    """Eigenvectors parallel to those of LAPACK xGGEV (scipy.linalg.eig(S, T)), also with a
+    zero and an infinite eigenvalue."""
+    S, T, blk = pencils.schur_pencil(m, seed, kind)
     Z, sc, info = oracle.tgevc(S, T)
     ar, ai, be, _ = oracle.eigvals(S, T)
     w, V = scipy.linalg.eig(S, T)
@@ -320,13 +328,15 @@ def test_all_real_upper_triangular():
 # --------------------------------------------------------------- invariants --
 
 @pytest.mark.parametrize("m,seed,kind", [(256, 0, "normal"), (256, 1, "normal"), (200, 200, "stress"),
-                                         (1200, 2, "normal")])
+                                         (1200, 2, "normal"), (400, 18, "degenerate")])
 def test_residual_bound_and_finiteness(m, seed, kind):
     """Normwise residual of S V D - T V B = 0 (Section 2.2) within 64 m u, no
-    Inf/NaN, integer scales >= 0, and double vs extended precision agreement."""
+    Inf/NaN, integer scales >= 0, and double vs extended precision agreement.  The
+    degenerate pencil repeats zero and infinite eigenvalues, whose singular pivots are
+    perturbed (info bit 16) and still meet the residual bound."""
     S, T, blk = pencils.schur_pencil(m, seed, kind)
     Z, sc, info = oracle.tgevc(S, T)
-    assert info == 0
+    assert info == (16 if kind == "degenerate" else 0)
     Zu, scu, _ = oracle.tgevc(S, T, normalize=False)
     assert np.isfinite(Z).all() and np.isfinite(Zu).all()
     assert (scu >= 0).all()
