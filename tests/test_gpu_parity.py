@@ -35,13 +35,13 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def run_gpu(S, T, mb=0, select=None, normalize=True, ld=None, band=0):
+def run_gpu(S, T, mb=0, select=None, normalize=True, ld=None, band=0, precision=0):
     torch = _torch()
     from paper_2003_04776_amd import rtgevc as rt
     m = S.shape[0]
     Sd = rt.colmajor_to_device(S, ld=ld)
     Td = rt.colmajor_to_device(T, ld=ld)
-    solver = rt.Solver(m, mb=mb, normalize=normalize, band=band)
+    solver = rt.Solver(m, mb=mb, normalize=normalize, band=band, precision=precision)
     res = solver.run(Sd, Td, select=select)
     torch.cuda.synchronize()
     return res.Z.cpu().numpy(), res.scales.cpu().numpy(), int(res.info.item())
@@ -168,16 +168,18 @@ def test_unnormalised_representation():
         assert np.max(np.abs(Zu[:, c] / n - Zo[:, c])) <= TOL
 
 
-def test_leading_dimension_padding():
+@pytest.mark.parametrize("mb,precision", [(64, 0), (128, 1)])
+def test_leading_dimension_padding(mb, precision):
     m = 301
     S, T, blk = pencils.schur_pencil(m, 22, ld=m + 7)
-    Zg, sc, info = run_gpu(S, T, mb=64, ld=m + 7)
+    Zg, sc, info = run_gpu(S, T, mb=mb, ld=m + 7, precision=precision)
     assert info == 0
     worst, _, _ = compare(np.asfortranarray(S), np.asfortranarray(T), Zg)
     assert worst <= TOL
 
 
-def test_select_subset():
+@pytest.mark.parametrize("mb,precision", [(64, 0), (128, 1)])
+def test_select_subset(mb, precision):
     m = 400
     S, T, blk = pencils.schur_pencil(m, 23)
     rng = np.random.default_rng(0)
@@ -185,7 +187,7 @@ def test_select_subset():
     pairs = np.nonzero(blk == 1)[0]
     sel[pairs[0]] = 1
     sel[pairs[0] + 1] = 0           # closure needed
-    Zg, sc, info = run_gpu(S, T, mb=64, select=sel)
+    Zg, sc, info = run_gpu(S, T, mb=mb, select=sel, precision=precision)
     assert info == 32
     Zo, _, io = oracle.tgevc(S, T, select=sel)
     assert io == 32
