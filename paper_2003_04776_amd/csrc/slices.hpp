@@ -34,23 +34,29 @@ __host__ __device__ constexpr int64_t slice_packets(int mb) { return (int64_t)sl
 // triangular index of the tile pair (k, r), k < r
 __host__ __device__ inline int64_t pair_index(int k, int r) { return (int64_t)r * (r - 1) / 2 + k; }
 
-// 16 values (already scaled into (-1, 1)) -> kSlices packets of 16 signed bytes
+// 16 values (already scaled into (-1, 1)) -> kSlices packets of 16 signed bytes.  The
+// slices a_p = trunc(128 r_{p-1}) with r_0 = |y|, r_p = 128 r_{p-1} - a_p (each step exact)
+// are the base-128 digits of N = floor(|y| 2^49), signed like y.  N is formed exactly in two
+// parts, hi = floor(|y| 2^21) (3 digits) and lo = floor((|y| 2^21 - hi) 2^28) (4 digits),
+// so the digits come from integer shifts instead of seven dependent FP64 steps.
+static_assert(kSlices == 7, "the digit split below is for 7 slices of 7 bits");
 __device__ __forceinline__ void slice16(const double (&y)[16], int4 (&out)[kSlices]) {
-  double rem[16];
+  int w[kSlices][4] = {};
 #pragma unroll
-  for (int b = 0; b < 16; ++b) rem[b] = y[b];
+  for (int b = 0; b < 16; ++b) {
+    const double ay = fabs(y[b]);
+    const double h = trunc(ay * 2097152.0);                     // |y| 2^21, exact
+    const int hi = (int)h;
+    const int lo = (int)((ay * 2097152.0 - h) * 268435456.0);  // exact fraction times 2^28, truncated
+    const bool neg = y[b] < 0.0;
 #pragma unroll
-  for (int p = 0; p < kSlices; ++p) {
-    int w[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int b = 0; b < 16; ++b) {
-      const double t = rem[b] * 128.0;
-      const double a = trunc(t);
-      rem[b] = t - a;
-      w[b / 4] |= ((int)a & 0xff) << (8 * (b % 4));
+    for (int p = 0; p < kSlices; ++p) {
+      const int d = p < 3 ? (hi >> (7 * (2 - p))) & 127 : (lo >> (7 * (6 - p))) & 127;
+      w[p][b / 4] |= ((neg ? -d : d) & 0xff) << (8 * (b % 4));
     }
-    out[p] = make_int4(w[0], w[1], w[2], w[3]);
   }
+#pragma unroll
+  for (int p = 0; p < kSlices; ++p) out[p] = make_int4(w[p][0], w[p][1], w[p][2], w[p][3]);
 }
 
 // exponent e with |x| < 2^e for the largest magnitude x of a row or column (0 for zero)
