@@ -63,29 +63,29 @@ __device__ __forceinline__ void band_column_scales(const PencilDesc& P, const Up
                                                    int (&g)[kMaxBand]) {
   const int64_t m = P.m;
   const int WSL = P.wslots;
+  // every load is issued at once (the pair partner's norm and the sources past ns from
+  // clamped addresses, then discarded), so the prologue waits for memory only once
   const int kind = P.blk[c];
-  int eY = 0;
-  double nY = 0.0;
-  if (!first) {
-    eY = P.exps[(int64_t)k * m + c];
-    nY = P.norms[(int64_t)k * m + c];
-    if (kind == 1) nY += P.norms[(int64_t)k * m + c + 1];
-    else if (kind == 2) nY += P.norms[(int64_t)k * m + c - 1];
-  }
+  const int64_t yo = (int64_t)k * m;
+  const int eY0 = P.exps[yo + c];
+  const double nY0 = P.norms[yo + c];
+  const double nYp = P.norms[yo + min(c + 1, m - 1)], nYm = P.norms[yo + max(c - 1, (int64_t)0)];
   int eWs[kMaxBand];
   double nWs[kMaxBand], nus[kMaxBand];
-  int ew = INT_MIN;
 #pragma unroll
   for (int i = 0; i < kMaxBand; ++i) {
-    if (i < ns) {
-      const int s = U.s_lo + i;
-      const int64_t slot = (int64_t)(s % WSL) * m + c;
-      eWs[i] = P.eW[slot];
-      nWs[i] = P.nW[slot];
-      nus[i] = P.nu[(int64_t)k * P.Mmax + s];
-      ew = max(ew, eWs[i]);
-    }
+    const int s = U.s_lo + min(i, max(ns - 1, 0));
+    const int64_t slot = (int64_t)(s % WSL) * m + c;
+    eWs[i] = P.eW[slot];
+    nWs[i] = P.nW[slot];
+    nus[i] = P.nu[(int64_t)k * P.Mmax + s];
   }
+  const int eY = first ? 0 : eY0;
+  const double nY = first ? 0.0 : (kind == 1 ? nY0 + nYp : (kind == 2 ? nY0 + nYm : nY0));
+  int ew = INT_MIN;
+#pragma unroll
+  for (int i = 0; i < kMaxBand; ++i)
+    if (i < ns) ew = max(ew, eWs[i]);
   const int ks = eY > ew ? eY : ew;
   // |sum_s [S_ks | T_ks] W_s| <= sum_s nu_ks ||W_s|| (each term <= 2^1000, no overflow)
   double xb = 0.0;
@@ -108,7 +108,7 @@ template <int MB, int WGR>
 struct UpdSmem {
   int sfY[MB], sfA[MB], seN[MB];
   int sg[kMaxBand][MB];        // exponent of each source's W relative to the band's
-  int sgany[kMaxBand];
+  int sgw[(MB + 63) / 64];     // per wave of column threads: bit i set if some sg[i] != 0
   double red[WGR][MB];
 };
 
@@ -126,7 +126,7 @@ __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange&
   auto& sfA = sm.sfA;
   auto& seN = sm.seN;
   auto& sg = sm.sg;
-  auto& sgany = sm.sgany;
+  auto& sgw = sm.sgw;
   auto& red = sm.red;
 
   const int M = P.ctrl->M;
@@ -142,48 +142,32 @@ __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange&
   const bool first = (j <= U.s_hi);
   int cs[kMaxBand + 1];     // cumulative K chunks per source
   int es[kMaxBand + 1];     // first row of each source tile (and the end of the last)
+  int ev[kMaxBand + 1];     // (edges past the band from clamped addresses, discarded: these
+#pragma unroll              // loads need not wait for M)
+  for (int i = 0; i <= kMaxBand; ++i) ev[i] = P.edges[min(U.s_lo + i, P.Mmax)];
   cs[0] = 0;
-  es[0] = P.edges[U.s_lo];
+  es[0] = ev[0];
 #pragma unroll
   for (int i = 0; i < kMaxBand; ++i) {
-    const int s = U.s_lo + i;
-    es[i + 1] = i < ns ? P.edges[s + 1] : es[i];
+    es[i + 1] = i < ns ? ev[i + 1] : es[i];
     cs[i + 1] = cs[i] + 2 * ((es[i + 1] - es[i] + 15) & ~15) / kChunk;
   }
   const int tid = threadIdx.x;
-  if (tid < kMaxBand) sgany[tid] = 0;
-  __syncthreads();
   const int wave = tid / 64, lane = tid % 64;
   const int wr = wave / WGC, wc = wave % WGC;
   const int li = lane % 16, lk = lane / 16;
-
-  // ---- per-column scales (Algorithm 3): common exponent, ProtectUpdate ----
-  if (tid < MB) {
-    const int n = tid;
-    int fy = 0, fa = 0, en = 0;
-    int g[kMaxBand] = {};
-    if (n < hj) band_column_scales(P, U, k, c0 + n, first, ns, fy, fa, en, g);
-    sfY[n] = fy;
-    sfA[n] = fa;
-    seN[n] = en;
-#pragma unroll
-    for (int i = 0; i < kMaxBand; ++i) {
-      sg[i][n] = g[i];
-      if (g[i] != 0) atomicOr(&sgany[i], 1);
-    }
-  }
 
   // ---- K loop: fragments straight from global memory into registers ----
   // K step t of a source (4 K values) with q = KP / 4 steps per half: the S columns
   // e_s + 4 t + 0..3 for t < q, else the T columns e_s + 4 (t - q) + 0..3.  A lane's A
   // fragment element is row 16 a + li of its wave's rows and K value lk; its W fragment
   // element is the packed entry (step, column block, lane) of the source's W tile.
+  // The first slots are loaded before the per-column scales are computed, so their
+  // latency and that of the scales' loads overlap; their W exponent fixups (which need
+  // the scales) are read once the scales are published.
   const double psc = P.ctrl->psc;
   const int nst = cs[ns] * (kChunk / 4);   // K steps of the band
-  __syncthreads();   // per-column scales and W exponent flags published
   int sgbits = 0;    // sources whose W exponents differ from the band's in some column
-#pragma unroll
-  for (int i = 0; i < kMaxBand; ++i) sgbits |= (sgany[i] != 0) << i;
   const bool fix_a = psc != 1.0;
 
   int rowA[RB];      // clamped matrix rows of the lane's A elements
@@ -205,7 +189,8 @@ __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange&
   // reloads it), so the compiler's count of loads in flight stays exact and a wave waits
   // only for the slot it is about to use; everything that needs the data (the rare
   // scalings, the zeroing of the steps past the end) happens when the slot is used.
-  auto load = [&](double (&af)[RB], double (&bf)[CB], int (&sgl)[CB]) {
+  auto load = [&](double (&af)[RB], double (&bf)[CB], int (&sgl)[CB], int& src) {
+    src = ls_i;
     const bool lower = ls_t >= ls_q;
     const double* base = lower ? P.T : P.S;
     const int64_t ld = lower ? P.ldt : P.lds;
@@ -258,34 +243,68 @@ __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange&
   constexpr int NS = UpdShape<MB>::S;
   double af[NS][RB], bf[NS][CB];
   int sgl[NS][CB] = {};
+  int src[NS];
   const int nrun = (nst + NS - 1) / NS * NS;
 #pragma unroll
-  for (int u = 0; u < NS - 1; ++u) load(af[u], bf[u], sgl[u]);
+  for (int u = 0; u < NS - 1; ++u) load(af[u], bf[u], sgl[u], src[u]);
+
+  // ---- per-column scales (Algorithm 3): common exponent, ProtectUpdate ----
+  if (tid < MB) {
+    const int n = tid;
+    int fy = 0, fa = 0, en = 0;
+    int g[kMaxBand] = {};
+    if (n < hj) band_column_scales(P, U, k, c0 + n, first, ns, fy, fa, en, g);
+    sfY[n] = fy;
+    sfA[n] = fa;
+    seN[n] = en;
+    int bits = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxBand; ++i) {
+      sg[i][n] = g[i];
+      bits |= (__ballot(g[i] != 0) != 0) << i;
+    }
+    if (lane == 0) sgw[wave] = bits;
+  }
+  __syncthreads();   // per-column scales and W exponent flags published
+#pragma unroll
+  for (int w = 0; w < (MB + 63) / 64; ++w) sgbits |= sgw[w];
+  if (sgbits) {
+#pragma unroll
+    for (int u = 0; u < NS - 1; ++u)
+#pragma unroll
+      for (int q = 0; q < CB; ++q) sgl[u][q] = sg[src[u]][16 * (CB * wc + q) + li];
+  }
+
   for (int t0 = 0; t0 < nrun; t0 += NS) {
 #pragma unroll
     for (int u = 0; u < NS; ++u) {
-      load(af[(u + NS - 1) % NS], bf[(u + NS - 1) % NS], sgl[(u + NS - 1) % NS]);
+      load(af[(u + NS - 1) % NS], bf[(u + NS - 1) % NS], sgl[(u + NS - 1) % NS], src[(u + NS - 1) % NS]);
       use(af[u], bf[u], sgl[u], t0 + u < nst);
     }
   }
 
   // ---- epilogue: Y <- 2^fY Y - 2^fA acc and the new segment norms ----
   // block (a, q) of the transposed product: lane holds C row 16 a + lane % 16 (within
-  // the wave's rows) for columns 16 q + lane / 16 + 4 v, v = 0..3.  The old Y of a column
-  // block is loaded at once, from addresses clamped into the tile, so the loads overlap;
-  // only the stores are masked.
-#pragma unroll
-  for (int q = 0; q < CB; ++q) {
-    double yo[4][RB];
+  // the wave's rows) for columns 16 q + lane / 16 + 4 v, v = 0..3.  The old Y of column
+  // block q + 1 is loaded before block q is written (from addresses clamped into the
+  // tile; only the stores are masked), so the epilogue waits for memory about once.
+  auto load_yo = [&](double (&y)[4][RB], int q) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int nc = min(WC * wc + 16 * q + lk + 4 * v, hj - 1);
 #pragma unroll
       for (int a = 0; a < RB; ++a) {
         const int ic = min(WR * wr + 16 * a + li, hk - 1);
-        yo[v][a] = first ? 0.0 : P.Z[(k0 + ic) + (int64_t)(c0 + nc) * P.ldz];
+        const double z = P.Z[(k0 + ic) + (int64_t)(c0 + nc) * P.ldz];   // (unused on a first update)
+        y[v][a] = first ? 0.0 : z;
       }
     }
+  };
+  double yo[2][4][RB];
+  load_yo(yo[0], 0);
+#pragma unroll
+  for (int q = 0; q < CB; ++q) {
+    if (q + 1 < CB) load_yo(yo[(q + 1) % 2], q + 1);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int n = WC * wc + 16 * q + lk + 4 * v;
@@ -297,7 +316,7 @@ __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange&
         for (int a = 0; a < RB; ++a) {
           const int i = WR * wr + 16 * a + li;
           if (i < hk) {
-            const double yn = ldexp(yo[v][a], fy) - ldexp(acc[a][q][v], fa);
+            const double yn = ldexp(yo[q % 2][v][a], fy) - ldexp(acc[a][q][v], fa);
             zc[16 * a] = yn;
             cmx = fmax(cmx, fabs(yn));
           }
