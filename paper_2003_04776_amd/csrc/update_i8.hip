@@ -206,7 +206,18 @@ __device__ __forceinline__ void update_i8_tile(const PencilDesc& P, const UpdRan
   }
 
   // ---- epilogue: Y <- 2^fY Y - 2^fA acc and the new segment norms ----
+  // (the lane's old Y is loaded at once, from addresses clamped into the tile, so the
+  // epilogue waits for memory once; only the stores are masked)
   const int i = 16 * rb + li;            // the lane's row in the tile
+  double yo[2][4];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int n = min(n0 + 16 * q + 4 * lk + v, hj - 1);
+      const double z = P.Z[(k0 + min(i, hk - 1)) + (int64_t)(c0 + n) * P.ldz];   // (unused on a first update)
+      yo[q][v] = first ? 0.0 : z;
+    }
 #pragma unroll
   for (int q = 0; q < 2; ++q)
 #pragma unroll
@@ -216,8 +227,7 @@ __device__ __forceinline__ void update_i8_tile(const PencilDesc& P, const UpdRan
       if (n < hj && i < hk) {
         const int fy = sfY[nl], fa = sfA[nl];
         double* zc = P.Z + (k0 + i) + (int64_t)(c0 + n) * P.ldz;
-        const double yo = first ? 0.0 : *zc;
-        const double yn = ldexp(yo, fy) - ldexp(acc[q][v], fa);
+        const double yn = ldexp(yo[q][v], fy) - ldexp(acc[q][v], fa);
         *zc = yn;
         cmx = fabs(yn);
       }
