@@ -82,18 +82,6 @@ __device__ __forceinline__ void update_i8_tile(const PencilDesc& P, const UpdRan
   const int rb = rg * NW + wave;           // the wave's row block (16 rows) in the tile
   const int n0 = g0;
 
-  if (tid < COLS) {
-    const int n = g0 + tid;
-    int fy = 0, fa = 0, en = 0;
-    int g[kMaxBand] = {};
-    if (n < hj) band_column_scales(P, U, k, c0 + n, first, ns, fy, fa, en, g);
-    sfY[tid] = fy;
-    sfA[tid] = fa;
-    seN[tid] = en;
-#pragma unroll
-    for (int i = 0; i < kMaxBand; ++i) sgc[i][tid] = g[i];
-  }
-
   // lane's outputs: row 16 rb + li, columns n0 + 16 q + 4 lk + v (q = 0..1, v = 0..3)
   double acc[2][4];
 #pragma unroll
@@ -173,9 +161,23 @@ __device__ __forceinline__ void update_i8_tile(const PencilDesc& P, const UpdRan
   // A fragments double-buffered in registers, W in two LDS stages: the loads of step t + 1
   // (every one unconditional: past the band's last step they repeat it) are in flight while
   // the matrix cores run step t; one barrier per step
+  // (the first step's loads are issued before the per-column scales are computed, so their
+  // latency and that of the scales' loads overlap)
   v4i aA[kSlices], aB[kSlices];
   load_a(a_ptr(0, 0), aA);
   issue_w(w_ptr(0, 0), 0);
+  if (tid < COLS) {
+    const int n = g0 + tid;
+    int fy = 0, fa = 0, en = 0;
+    int g[kMaxBand] = {};
+    if (n < hj) band_column_scales(P, U, k, c0 + n, first, ns, fy, fa, en, g);
+    sfY[tid] = fy;
+    sfA[tid] = fa;
+    seN[tid] = en;
+#pragma unroll
+    for (int i = 0; i < kMaxBand; ++i) sgc[i][tid] = g[i];
+  }
+
   wait_loads();
   __syncthreads();   // also publishes the per-column scales
   for (int si = 0; si < ns; ++si) {
