@@ -131,3 +131,39 @@ def tgevc(S: np.ndarray, T: np.ndarray, select=None, normalize: bool = True,
              sel.ctypes.data_as(i32p) if sel is not None else None,
              _dp(Z), max(m, 1), scales.ctypes.data_as(i32p), int(bool(normalize)), int(threads))
     return Z, scales[:m], int(info)
+
+
+def backtransform(V: np.ndarray, Z: np.ndarray, scales, blk, normalize: bool = True):
+    """Eigenvectors of the original pencil from those of its Schur form.
+
+    If (A, B) = (Q S V^T, Q T V^T) with Q, V orthogonal (the generalized Schur
+    decomposition the paper starts from, Section 2), then S z = lambda T z gives
+    A (V z) = lambda B (V z): the eigenvector of (A, B) is x = V z.  Column c of the
+    result represents 2^xs[c] X[:, c] = V (2^scales[c] Z[:, c]); a complex pair
+    (blk[p] == 1) is z = Z[:, p] + i Z[:, p+1] and shares one exponent.  Each column (or
+    pair) is brought to a maximum magnitude in [1/2, 1) by a power of two before the
+    product, so nothing overflows.  normalize: max_i |x_i| (real) or max_i |x_i| + |y_i|
+    (pair) equal to one and xs = 0, as for the eigenvectors of the Schur form.
+    Returns (X, xs)."""
+    m = Z.shape[0]
+    X = np.zeros((m, m), dtype=np.float64, order="F")
+    xs = np.zeros(m, dtype=np.int32)
+    c = 0
+    while c < m:
+        cols = [c, c + 1] if (blk[c] == 1 and c + 1 < m) else [c]
+        zmax = max(float(np.max(np.abs(Z[:, k]))) for k in cols)
+        if zmax > 0.0:
+            e = int(np.frexp(zmax)[1])
+            for k in cols:
+                X[:, k] = V @ np.ldexp(Z[:, k], -e)
+            if normalize:
+                t = np.abs(X[:, cols[0]]) + (np.abs(X[:, cols[1]]) if len(cols) == 2 else 0.0)
+                tmax = float(np.max(t))
+                if tmax > 0.0:
+                    for k in cols:
+                        X[:, k] = X[:, k] / tmax
+            else:
+                for k in cols:
+                    xs[k] = int(scales[cols[0]]) + e
+        c += len(cols)
+    return X, xs

@@ -18,12 +18,15 @@ def block_kinds_from_S(S: np.ndarray) -> np.ndarray:
     return kind
 
 
-def residuals(S, T, Z, ar, ai, be, cols=None):
+def residuals(S, T, Z, ar, ai, be, cols=None, kind=None):
     """eta_c = ||S Z_c D - T Z_c B||_1 / ((||S||_1 + ||T||_1) ||Z_c||_1) for each
     selected column c, with (alpha, beta) rescaled so max(beta, |a|+|b|) = 1
-    (equation of Section 2.2, large-matrix form, column by column)."""
+    (equation of Section 2.2, large-matrix form, column by column).  kind: the block
+    structure (taken from S's sub-diagonal unless given, e.g. for a dense pencil
+    equivalent to a Schur pencil)."""
     m = S.shape[0]
-    kind = block_kinds_from_S(S)
+    if kind is None:
+        kind = block_kinds_from_S(S)
     nS = np.abs(S).sum(axis=0).max() if m else 0.0
     nT = np.abs(T).sum(axis=0).max() if m else 0.0
     if cols is None:
