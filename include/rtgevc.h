@@ -49,7 +49,7 @@ extern "C" {
 #endif
 
 /* info bits */
-#define RTGEVC_INFO_NONFINITE      1   /* NaN or Inf in S or T                              */
+#define RTGEVC_INFO_NONFINITE      1   /* NaN or Inf in S or T (back-transformation: V, Z)  */
 #define RTGEVC_INFO_BAD_STRUCTURE  2   /* two consecutive non-zero sub-diagonal entries      */
 #define RTGEVC_INFO_REAL_PAIR      4   /* a 2x2 block with real eigenvalues (assumption 2)   */
 #define RTGEVC_INFO_INDEFINITE     8   /* alpha = beta = 0 in a 1x1 block: e_p returned      */
@@ -125,6 +125,43 @@ int rtgevc(int64_t m, const double *S, int64_t lds, const double *T, int64_t ldt
 int rtgevc_eigvals(int64_t m, const double *S, int64_t lds, const double *T, int64_t ldt,
                    double *alpha_re, double *alpha_im, double *beta, int32_t *info,
                    void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream);
+
+/* Back-transformation to the eigenvectors of the original pencil (the step after the
+ * path).  If (A, B) = (Q S V^T, Q T V^T) is the generalized Schur decomposition the method
+ * starts from (Section 2: Q, V orthogonal, (S, T) the real Schur pencil given to rtgevc),
+ * then S z = lambda T z gives A (V z) = lambda B (V z): the eigenvectors of (A, B) are
+ * X = V Z.  For every column c:
+ *     2^xscales[c] X[:, c] = V (2^scales[c] Z[:, c]),
+ * with Z, scales the output of rtgevc() (Z upper quasi-triangular: the entries below its
+ * first sub-diagonal, and the sub-diagonal entries of columns that do not start a complex
+ * pair, are not read).  A complex pair (p, p+1) keeps its real form: X[:, p] + i X[:, p+1]
+ * is the eigenvector for alpha_im[p] > 0, and both columns share one exponent.  When
+ * m max|V| max|Z_c| could exceed Omega = 2^1020, Z_c is scaled down by a power of two
+ * before the product (exact, entries below the smallest normal number may flush to zero)
+ * and the exponent added to xscales[c], so nothing overflows.
+ *   S         device double, column-major, leading dimension lds >= max(1, m): only its
+ *             sub-diagonal is read (the 2x2 block structure).
+ *   V         device double, column-major m x m, leading dimension ldv >= max(1, m).
+ *   Z, ldz    as returned by rtgevc(); scales: device int32[m] or NULL (all zero).
+ *   X, ldx    device double output, column-major m x m.  X may be Z itself (with
+ *             ldx == ldz: the result overwrites the input); X must not overlap V.
+ *   xscales   device int32[m] output.
+ *   info      device int32 output or NULL: RTGEVC_INFO_NONFINITE if V or Z holds a NaN or
+ *             an infinity (the result is then not meaningful).
+ *   opts      NULL or options: mb (64 or 128; 0 or 32: 128 from m = 2048, else 64) is
+ *             the tile of the contraction; normalize (default 1): each eigenvector is
+ *             divided by max_i |x_i| (real) or max_i |x_i| + |y_i| (pair) and xscales = 0.
+ *             The other fields are not used.
+ *   work      device workspace of at least rtgevc_backtransform_workspace_size(m, opts)
+ *             bytes, 256-byte aligned (about 4 m^2 bytes: Z in the matrix-core operand order).
+ * Asynchronous on stream, no allocation or synchronisation: capturable in a HIP graph.
+ * Returns 0 when enqueued, -i for invalid argument i (-9: X overlaps V; -10: X is Z with
+ * ldx != ldz; -13/-14: workspace NULL, misaligned or too small), or -1000 - hipError. */
+size_t rtgevc_backtransform_workspace_size(int64_t m, const rtgevc_opts *opts);
+int rtgevc_backtransform(int64_t m, const double *S, int64_t lds, const double *V, int64_t ldv,
+                         const double *Z, int64_t ldz, const int32_t *scales, double *X, int64_t ldx,
+                         int32_t *xscales, int32_t *info, void *work, size_t work_bytes,
+                         const rtgevc_opts *opts, void *stream);
 
 /* Benchmark variant of rtgevc(): the same work on the same stream, with a HIP event
  * recorded before and after every kernel launch (on the stream the launch runs on).

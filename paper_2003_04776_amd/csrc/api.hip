@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "rtgevc.h"
+#include "back.hpp"
 #include "layout.hpp"
 #include "slices.hpp"
 
@@ -30,6 +31,7 @@ void launch_update_batched(const PencilDesc* D, int n, int mb, int max_tiles, in
                            int kmax, hipStream_t s);
 void launch_consolidate_batched(const PencilDesc* D, int n, int64_t max_m, hipStream_t s);
 void launch_eigvals_out(const PencilDesc& P, double* are, double* aim, double* bet, hipStream_t s);
+void launch_backtransform(const BackDesc& B, hipStream_t s);
 hipError_t launch_walk(const PencilDesc& P, const WalkDesc& W, hipStream_t s);
 }  // namespace rgev
 
@@ -371,6 +373,26 @@ PencilDesc make_desc(int64_t m, const double* S, int64_t lds, const double* T, i
   return P;
 }
 
+// tile size of the back-transformation: 64 or 128 (opts->mb; 0 or 32: 128 from m = 2048)
+int back_mb(int64_t m, const rtgevc_opts* o) {
+  if (o && (o->mb == 64 || o->mb == 128)) return o->mb;
+  return m >= 2048 ? 128 : 64;
+}
+
+// workspace of the back-transformation (base == nullptr: size only)
+size_t back_carve(BackDesc& B, char* base, int64_t m, int mb) {
+  const int nt = (int)((m + mb - 1) / mb);
+  Carve c;
+  B.blk = c.take<int8_t>(base, m);
+  B.zmax = c.take<double>(base, m);
+  B.vmax = c.take<unsigned long long>(base, 1);
+  B.info_local = c.take<int32_t>(base, 1);
+  B.Zp = c.take<double>(base, (size_t)back_tile_offset(mb, nt));
+  B.mb = mb;
+  B.nt = nt;
+  return c.off;
+}
+
 }  // namespace
 
 extern "C" {
@@ -428,6 +450,55 @@ int rtgevc_eigvals(int64_t m, const double* S, int64_t lds, const double* T, int
   PencilDesc P = make_desc(m, S, lds, T, ldt, nullptr, nullptr, m, nullptr, info, work, opts);
   launch_preprocess(P, s);
   launch_eigvals_out(P, alpha_re, alpha_im, beta, s);
+  return hip_code(hipGetLastError());
+}
+
+size_t rtgevc_backtransform_workspace_size(int64_t m, const rtgevc_opts* opts) {
+  if (m < 0) return 0;
+  if (m == 0) return kAlign;
+  BackDesc B;
+  memset(&B, 0, sizeof(B));
+  return back_carve(B, nullptr, m, back_mb(m, opts));
+}
+
+int rtgevc_backtransform(int64_t m, const double* S, int64_t lds, const double* V, int64_t ldv,
+                         const double* Z, int64_t ldz, const int32_t* scales, double* X, int64_t ldx,
+                         int32_t* xscales, int32_t* info, void* work, size_t work_bytes,
+                         const rtgevc_opts* opts, void* stream) {
+  const int64_t lo = m > 1 ? m : 1;
+  if (m < 0) return -1;
+  if (m > 0 && !S) return -2;
+  if (lds < lo) return -3;
+  if (m > 0 && !V) return -4;
+  if (ldv < lo) return -5;
+  if (m > 0 && !Z) return -6;
+  if (ldz < lo) return -7;
+  if (m > 0 && !X) return -9;
+  if (ldx < lo) return -10;
+  if (m > 0 && !xscales) return -11;
+  if (!opts_ok(opts)) return -15;
+  if (m == 0) return 0;
+  if (!work || (reinterpret_cast<uintptr_t>(work) % kAlign) != 0) return -13;
+  if (work_bytes < rtgevc_backtransform_workspace_size(m, opts)) return -14;
+  if (X != Z && X == V) return -9;   // X may be Z, never V
+  if (X == Z && ldx != ldz) return -10;
+  BackDesc B;
+  memset(&B, 0, sizeof(B));
+  B.m = m;
+  B.S = S;
+  B.lds = lds;
+  B.V = V;
+  B.ldv = ldv;
+  B.Z = Z;
+  B.ldz = ldz;
+  B.scales = scales;
+  B.X = X;
+  B.ldx = ldx;
+  B.xscales = xscales;
+  back_carve(B, static_cast<char*>(work), m, back_mb(m, opts));
+  B.info = info ? info : B.info_local;
+  B.normalize = opts ? opts->normalize : 1;
+  launch_backtransform(B, static_cast<hipStream_t>(stream));
   return hip_code(hipGetLastError());
 }
 
@@ -647,24 +718,20 @@ int rtgevc_resolve_opts(int64_t m, int32_t batched, const rtgevc_opts* opts, rtg
 }
 
 const char* rtgevc_strerror(int code) {
+  // -i names argument i of the entry point that returned it
+  static const char* const kArg[] = {
+      "", "argument 1 (m) is negative or invalid", "argument 2 is NULL or invalid",
+      "argument 3 is invalid (a leading dimension below max(1, m)?)", "argument 4 is NULL or invalid",
+      "argument 5 is invalid (a leading dimension below max(1, m)?)", "argument 6 is NULL or invalid",
+      "argument 7 is NULL or invalid", "argument 8 is NULL or invalid", "argument 9 is NULL or invalid",
+      "argument 10 is NULL or invalid", "argument 11 is NULL or invalid (workspace NULL or not 256-byte aligned?)",
+      "argument 12 is invalid (workspace too small, or options?)", "argument 13 is invalid (workspace or options?)",
+      "argument 14 is invalid (workspace too small?)", "argument 15 is invalid (options or stats?)",
+      "argument 16 is invalid"};
   if (code == 0) return "success";
   if (code <= -1000) return hipGetErrorString(static_cast<hipError_t>(-1000 - code));
-  switch (code) {
-    case -1: return "argument 1 (m) is negative";
-    case -2: return "argument 2 (S) is NULL";
-    case -3: return "argument 3 (lds) is below max(1, m)";
-    case -4: return "argument 4 (T) is NULL";
-    case -5: return "argument 5 (ldt) is below max(1, m)";
-    case -6: return "argument 6 is invalid";
-    case -7: return "argument 7 is NULL";
-    case -8: return "argument 8 is invalid (NULL or leading dimension below max(1, m))";
-    case -10: return "argument 10 is invalid";
-    case -11: return "argument 11 is invalid (workspace NULL or not 256-byte aligned, or too small)";
-    case -12: return "argument 12 is invalid (workspace too small, or options)";
-    case -13: return "argument 13 (opts) is invalid";
-    case -15: return "argument 15 (stats) is NULL or too short";
-    default: return "invalid argument";
-  }
+  if (code < 0 && code >= -16) return kArg[-code];
+  return "invalid argument";
 }
 
 const char* rtgevc_version(void) { return "0.1.0"; }

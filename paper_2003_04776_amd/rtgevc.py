@@ -65,6 +65,10 @@ def load():
     L.rtgevc_batched_workspace_size.argtypes = [ctypes.c_int32, vp, op]
     L.rtgevc_batched.restype = ctypes.c_int
     L.rtgevc_batched.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, op, vp]
+    L.rtgevc_backtransform_workspace_size.restype = sz
+    L.rtgevc_backtransform_workspace_size.argtypes = [i64, op]
+    L.rtgevc_backtransform.restype = ctypes.c_int
+    L.rtgevc_backtransform.argtypes = [i64, vp, i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, vp, sz, op, vp]
     L.rtgevc_resolve_opts.restype = ctypes.c_int
     L.rtgevc_resolve_opts.argtypes = [i64, ctypes.c_int32, op, op]
     L.rtgevc_strerror.restype = ctypes.c_char_p
@@ -76,8 +80,8 @@ def load():
 
 
 EXPORTED = ("rtgevc_workspace_size", "rtgevc", "rtgevc_eigvals", "rtgevc_timed",
-            "rtgevc_batched_workspace_size", "rtgevc_batched", "rtgevc_resolve_opts", "rtgevc_strerror",
-            "rtgevc_version")
+            "rtgevc_batched_workspace_size", "rtgevc_batched", "rtgevc_backtransform_workspace_size",
+            "rtgevc_backtransform", "rtgevc_resolve_opts", "rtgevc_strerror", "rtgevc_version")
 TIMED_NSTATS = 12
 
 
@@ -298,3 +302,42 @@ def tgevc_batched(S, T, select=None, normalize: bool = True, mb: int = 0, stream
     bs = BatchSolver([x.shape[0] for x in S], mb=mb, normalize=normalize, device=S[0].device, band=band)
     Z, sc, info = bs.outputs()
     return bs.run(S, T, Z, sc, info, select=select, stream=stream)
+
+
+class BackTransformer:
+    """Back-transformation X = V Z (rtgevc_backtransform) for one order m, holding its
+    workspace (allocated once by torch)."""
+
+    def __init__(self, m: int, mb: int = 0, normalize: bool = True, device="cuda"):
+        import torch
+        self.m = int(m)
+        self.opts = make_opts(mb, normalize)
+        self.nbytes = int(load().rtgevc_backtransform_workspace_size(self.m, ctypes.byref(self.opts)))
+        self.work = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
+        self.device = device
+
+    def run(self, S, V, Z, scales=None, X=None, xscales=None, info=None, stream=None) -> Result:
+        """Returns Result(X, xscales, info); X may be Z (in place)."""
+        import torch
+        m = self.m
+        if X is None:
+            X = colmajor_empty(m, self.device)
+        if xscales is None:
+            xscales = torch.empty(max(m, 1), dtype=torch.int32, device=self.device)
+        if info is None:
+            info = torch.zeros(1, dtype=torch.int32, device=self.device)
+        rc = load().rtgevc_backtransform(m, S.data_ptr(), _ld(S, m), V.data_ptr(), _ld(V, m),
+                                         Z.data_ptr(), _ld(Z, m),
+                                         scales.data_ptr() if scales is not None else None,
+                                         X.data_ptr(), _ld(X, m), xscales.data_ptr(), info.data_ptr(),
+                                         self.work.data_ptr(), self.nbytes, ctypes.byref(self.opts),
+                                         _stream_ptr(stream))
+        _check(rc, "rtgevc_backtransform")
+        return Result(X, xscales[:m], info)
+
+
+def backtransform(S, V, Z, scales=None, X=None, normalize: bool = True, mb: int = 0, stream=None) -> Result:
+    """Eigenvectors X = V Z of the original pencil (A, B) = (Q S V^T, Q T V^T) from the
+    Schur-form eigenvectors (Z, scales) returned by tgevc."""
+    return BackTransformer(S.shape[0], mb=mb, normalize=normalize, device=S.device).run(
+        S, V, Z, scales, X=X, stream=stream)

@@ -132,3 +132,38 @@ def test_batched_workspace_and_argument_errors():
     assert call(nbytes=100) == -13
     bad = rt.make_opts(mb=100)
     assert call(opts=bad) == -14
+
+
+def test_backtransform_workspace_and_argument_errors():
+    """Workspace sizes grow with m and with the tile; invalid arguments are rejected on
+    the host (fake device addresses: nothing is launched)."""
+    L = rt.load()
+    o64, o128 = rt.make_opts(mb=64), rt.make_opts(mb=128)
+    ws = lambda m, o: L.rtgevc_backtransform_workspace_size(m, ctypes.byref(o))
+    assert ws(-1, o64) == 0 and ws(0, o64) > 0
+    assert ws(100, o64) < ws(1000, o64) < ws(4000, o64)
+    assert ws(1000, o64) >= 1000 * 1000 * 4    # packed Z: about half of Z's doubles
+    p = 1 << 20                                  # aligned fake address, never dereferenced
+    m, nb = 100, ws(100, o64)
+    call = lambda **k: L.rtgevc_backtransform(
+        k.get("m", m), k.get("S", p), k.get("lds", m), k.get("V", p), k.get("ldv", m), k.get("Z", 2 * p),
+        k.get("ldz", m), None, k.get("X", 3 * p), k.get("ldx", m), k.get("xs", p), None,
+        k.get("work", p), k.get("nb", nb), ctypes.byref(k.get("o", o64)), None)
+    assert call(m=-1) == -1
+    assert call(S=None) == -2
+    assert call(lds=m - 1) == -3
+    assert call(V=None) == -4
+    assert call(ldv=0) == -5
+    assert call(Z=None) == -6
+    assert call(ldz=m - 1) == -7
+    assert call(X=None) == -9
+    assert call(X=p) == -9                       # X overlapping V
+    assert call(X=2 * p, ldx=m + 1, ldz=m) == -10   # in place with another leading dimension
+    assert call(ldx=1) == -10
+    assert call(xs=None) == -11
+    assert call(work=p + 8) == -13
+    assert call(nb=nb - 1) == -14
+    bad = rt.make_opts(mb=96)
+    assert call(o=bad) == -15
+    assert call(m=0) == 0
+    assert "argument 4" in rt.strerror(-4)
