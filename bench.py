@@ -143,6 +143,49 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_back(args, m, Sd, Zf, scales, blk):
+    """The back-transformation X = V Z of the FP64 eigenvectors with a seeded dense V (the
+    contraction does not depend on V being orthogonal), timed with events on the stream it
+    runs on.  Algorithmic flops: 2 m per stored entry of the quasi-triangular Z."""
+    import numpy as np
+    import torch
+    from paper_2003_04776_amd import rtgevc as rt
+    g = torch.Generator(device="cuda")
+    g.manual_seed(args.seed + 1)
+    V = torch.randn((m, m), dtype=torch.float64, device="cuda", generator=g).t()   # column-major view
+    V.mul_(1.0 / np.sqrt(m))
+    X = rt.colmajor_empty(m)
+    xs = torch.empty(m, dtype=torch.int32, device="cuda")
+    binfo = torch.zeros(1, dtype=torch.int32, device="cuda")
+    bt = rt.BackTransformer(m, mb=args.mb if args.mb in (64, 128) else 0)
+    for _ in range(max(args.warmup, 1)):
+        bt.run(Sd, V, Zf, scales, X=X, xscales=xs, info=binfo)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        bt.run(Sd, V, Zf, scales, X=X, xscales=xs, info=binfo)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / max(args.steps, 1)
+    npairs = int((np.asarray(blk) == 1).sum())
+    flops = 2.0 * m * (m * (m + 1) / 2.0 + npairs)
+    ach = flops / (ms * 1e-3) / 1e12
+    log(f"[bench] back-transformation: {ms:.1f} ms per call, {ach:.2f} TFLOP/s")
+    res = {
+        "what": "X = V Z, the eigenvectors of (Q S V^T, Q T V^T); dense seeded V, normalised output",
+        "mb": 128 if (args.mb == 128 or (args.mb not in (64, 128) and m >= 2048)) else 64,
+        "ms_per_call": round(ms, 3),
+        "flops_per_call": flops,
+        "roofline": {"kernel": "whole call (back_gemm_kernel on FP64 MFMA 16x16x4 plus scan, pack and "
+                               "normalisation passes)", "bound": "mfma", "achieved": round(ach, 3),
+                     "peak": FP64_MFMA_PEAK, "unit": "TFLOP/s", "frac": round(ach / FP64_MFMA_PEAK, 4)},
+        "info": int(binfo.item()),
+    }
+    del V, X, bt
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +200,8 @@ def main():
                     help="0: FP64 tile updates; 1: mixed (int8 matrix cores on split operands)")
     ap.add_argument("--no-compare-mixed", dest="compare_mixed", action="store_false",
                     help="skip the mixed-precision run that follows the FP64 one")
+    ap.add_argument("--no-back", dest="back", action="store_false",
+                    help="skip the back-transformation X = V Z timed after the eigenvectors")
     ap.add_argument("--seed", type=int, default=400)
     ap.add_argument("--kind", default="normal", choices=("normal", "stress"))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -268,9 +313,9 @@ def main():
         "phases_ms": {k: round(st0[k], 3) for k in ("pre_ms", "solve_ms", "update_ms", "consolidate_ms", "total_ms")},
         "info": info_v,
     }
+    Zf = Z.clone()
     if args.compare_mixed and args.precision == 0 and args.schedule != 2:
         # the mixed-precision mode on the same inputs: speed-up and agreement with the FP64 run
-        Zf = Z.clone()
         mixed = rt.Solver(m, mb=args.mb, normalize=True, band=args.band, precision=1)
         for w in range(args.warmup):
             mixed.run_timed(Sd, Td, Z, scales, info)
@@ -293,7 +338,10 @@ def main():
             "info": int(info.item()),
         }
         log(f"[bench] mixed: {mwall:.1f} ms/step, speed-up {ms_per_step / mwall:.3f}")
-        del mixed, Zf
+        del mixed
+    if args.back:
+        out["backtransform"] = bench_back(args, m, Sd, Zf, scales, blk)
+    del Zf
     if rank == 0 and not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a column sample")
         out["cpu_baseline"] = cpu_baseline(S, T, blk, m, args.cpu_seconds)

@@ -127,10 +127,10 @@ int rtgevc_eigvals(int64_t m, const double *S, int64_t lds, const double *T, int
                    void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream);
 
 /* Back-transformation to the eigenvectors of the original pencil (the step after the
- * path).  If (A, B) = (Q S V^T, Q T V^T) is the generalized Schur decomposition the method
- * starts from (Section 2: Q, V orthogonal, (S, T) the real Schur pencil given to rtgevc),
- * then S z = lambda T z gives A (V z) = lambda B (V z): the eigenvectors of (A, B) are
- * X = V Z.  For every column c:
+ * path).  With the real Schur decomposition S = U^T A V, T = U^T B V of Section 1 (U, V
+ * orthogonal, (S, T) the real Schur pencil given to rtgevc), S z = lambda T z gives
+ * A (V z) = lambda B (V z): the eigenvectors of (A, B) are X = V Z (Section 1 writes U z;
+ * V z is the vector that satisfies the equation).  For every column c:
  *     2^xscales[c] X[:, c] = V (2^scales[c] Z[:, c]),
  * with Z, scales the output of rtgevc() (Z upper quasi-triangular: the entries below its
  * first sub-diagonal, and the sub-diagonal entries of columns that do not start a complex

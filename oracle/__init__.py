@@ -136,9 +136,10 @@ def tgevc(S: np.ndarray, T: np.ndarray, select=None, normalize: bool = True,
 def backtransform(V: np.ndarray, Z: np.ndarray, scales, blk, normalize: bool = True):
     """Eigenvectors of the original pencil from those of its Schur form.
 
-    If (A, B) = (Q S V^T, Q T V^T) with Q, V orthogonal (the generalized Schur
-    decomposition the paper starts from, Section 2), then S z = lambda T z gives
-    A (V z) = lambda B (V z): the eigenvector of (A, B) is x = V z.  Column c of the
+    With the real Schur decomposition S = U^T A V, T = U^T B V of Section 1 (U, V
+    orthogonal), S z = lambda T z gives A (V z) = U S z = lambda U T z = lambda B (V z):
+    the eigenvector of (A, B) is x = V z.  (Section 1 writes U z; the defining equation
+    holds for V z, and the pins below check that one.)  Column c of the
     result represents 2^xs[c] X[:, c] = V (2^scales[c] Z[:, c]); a complex pair
     (blk[p] == 1) is z = Z[:, p] + i Z[:, p+1] and shares one exponent.  Each column (or
     pair) is brought to a maximum magnitude in [1/2, 1) by a power of two before the

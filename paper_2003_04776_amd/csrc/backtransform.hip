@@ -1,7 +1,8 @@
 // Back-transformation: the eigenvectors of the original pencil from those of its Schur
-// form.  If (A, B) = (Q S V^T, Q T V^T) with Q, V orthogonal (the generalized Schur
-// decomposition the method starts from, Section 2), S z = lambda T z gives
-// A (V z) = lambda B (V z), so the eigenvectors of (A, B) are X = V Z.
+// form.  With the real Schur decomposition S = U^T A V, T = U^T B V of the introduction
+// (Section 1; U, V orthogonal), S z = lambda T z gives A (V z) = U S z = lambda U T z =
+// lambda B (V z), so the eigenvectors of (A, B) are X = V Z (the introduction writes U z;
+// it is V z that satisfies the equation).
 //
 // Z (the output of the eigenvector solve) is upper quasi-triangular: column c has
 // non-zeros in rows 0 .. c, and row c + 1 too when c is the first column of a complex
