@@ -173,7 +173,7 @@ def bench_back(args, m, Sd, Zf, scales, blk):
     ach = flops / (ms * 1e-3) / 1e12
     log(f"[bench] back-transformation: {ms:.1f} ms per call, {ach:.2f} TFLOP/s")
     res = {
-        "what": "X = V Z, the eigenvectors of (Q S V^T, Q T V^T); dense seeded V, normalised output",
+        "what": "X = V Z, the eigenvectors of (U S V^T, U T V^T); dense seeded V, normalised output",
         "mb": 128 if (args.mb == 128 or (args.mb not in (64, 128) and m >= 2048)) else 64,
         "ms_per_call": round(ms, 3),
         "flops_per_call": flops,

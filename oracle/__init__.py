@@ -168,3 +168,29 @@ def backtransform(V: np.ndarray, Z: np.ndarray, scales, blk, normalize: bool = T
                     xs[k] = int(scales[cols[0]]) + e
         c += len(cols)
     return X, xs
+
+
+def tgevc_left(S: np.ndarray, T: np.ndarray, select=None, normalize: bool = True,
+               precision: str = "double", threads: int | None = None):
+    """Left eigenvectors u of the Schur pencil: u^H (beta S - alpha T) = 0.
+
+    With J the exchange matrix, (S', T') = (J S^T J, J T^T J) is again a real Schur pencil
+    (upper quasi-triangular S', upper triangular T'; the block at (p, p+1) moves to
+    (m-2-p, m-1-p)), and u^H (beta S - alpha T) = 0 holds iff (beta S' - conj(alpha) T')
+    (J conj(u)) = 0 -- so u is J times the conjugate of a right eigenvector of (S', T'),
+    computed by the right-eigenvector oracle.  For a complex pair (p, p+1) of S, column p
+    holds Re u and column p+1 Im u of the left eigenvector for alpha_im[p] > 0.  The
+    robustness bounds of the right solve on (S', T') are those of the left solve on (S, T)
+    (its infinity norms are the 1-norms of S and T).  Returns (Y, scales, info) like tgevc."""
+    m = S.shape[0]
+    Sf = np.array(S.T[::-1, ::-1], order="F")   # (copies with positive strides)
+    Tf = np.array(T.T[::-1, ::-1], order="F")
+    sel = None if select is None else np.ascontiguousarray(np.asarray(select, dtype=np.int32)[::-1])
+    Zf, scf, info = tgevc(Sf, Tf, select=sel, normalize=normalize, precision=precision, threads=threads)
+    Y = np.array(Zf[::-1, ::-1], order="F")
+    scales = np.ascontiguousarray(scf[::-1])
+    kind, _ = blocks(S)
+    for p in np.flatnonzero(kind == 1):
+        re, im = Y[:, p + 1].copy(), Y[:, p].copy()
+        Y[:, p], Y[:, p + 1] = re, -im
+    return Y, scales, info
