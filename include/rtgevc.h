@@ -126,6 +126,23 @@ int rtgevc_eigvals(int64_t m, const double *S, int64_t lds, const double *T, int
                    double *alpha_re, double *alpha_im, double *beta, int32_t *info,
                    void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream);
 
+/* Left eigenvectors of the Schur pencil: u^H (beta S - alpha T) = 0 for every selected
+ * eigenvalue, with the same robustness (power-of-two scale exponents, no overflow).  They are
+ * the right eigenvectors of the flipped transposed pencil (J S^T J, J T^T J), J the exchange
+ * matrix, reversed and conjugated, so the library forms that pencil in the workspace and
+ * runs the right-eigenvector path on it; its bounds are then the 1-norm bounds of a left
+ * solve on (S, T).  Arguments, options, select, info and return codes as for rtgevc();
+ * the output Y, ldy takes the place of Z, ldz:
+ *   Y      column c is the left eigenvector of eigenvalue c (2^scales[c] Y[:, c]); for a
+ *          complex pair (p, p+1), u = Y[:, p] + i Y[:, p+1] is the left eigenvector for
+ *          alpha_im[p] > 0.  With normalisation, max_i |u_i| (|Re| + |Im| for a pair) = 1.
+ *   work   at least rtgevc_left_workspace_size(m, opts) bytes: rtgevc's workspace plus
+ *          16 m^2 + 4 m bytes for the flipped pencil. */
+size_t rtgevc_left_workspace_size(int64_t m, const rtgevc_opts *opts);
+int rtgevc_left(int64_t m, const double *S, int64_t lds, const double *T, int64_t ldt,
+                const int32_t *select, double *Y, int64_t ldy, int32_t *scales, int32_t *info,
+                void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream);
+
 /* Back-transformation to the eigenvectors of the original pencil (the step after the
  * path).  With the real Schur decomposition S = U^T A V, T = U^T B V of Section 1 (U, V
  * orthogonal, (S, T) the real Schur pencil given to rtgevc), S z = lambda T z gives

@@ -32,6 +32,9 @@ void launch_update_batched(const PencilDesc* D, int n, int mb, int max_tiles, in
 void launch_consolidate_batched(const PencilDesc* D, int n, int64_t max_m, hipStream_t s);
 void launch_eigvals_out(const PencilDesc& P, double* are, double* aim, double* bet, hipStream_t s);
 void launch_backtransform(const BackDesc& B, hipStream_t s);
+void launch_left_flip(int64_t m, const double* A, int64_t lda, double* B, hipStream_t s);
+void launch_left_select(int64_t m, const int32_t* sel, int32_t* out, hipStream_t s);
+void launch_left_finish(int64_t m, const int8_t* blkp, double* Y, int64_t ldy, int32_t* scales, hipStream_t s);
 hipError_t launch_walk(const PencilDesc& P, const WalkDesc& W, hipStream_t s);
 }  // namespace rgev
 
@@ -393,6 +396,37 @@ size_t back_carve(BackDesc& B, char* base, int64_t m, int mb) {
   return c.off;
 }
 
+// The right-eigenvector path on one stream (rtgevc after its argument checks); *out gets
+// the pencil descriptor (its block structure stays valid in the workspace).
+hipError_t enqueue_right(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt,
+                         const int32_t* select, double* Z, int64_t ldz, int32_t* scales, int32_t* info,
+                         void* work, const rtgevc_opts* opts, hipStream_t s, PencilDesc* out) {
+  if (resolve_schedule(m, opts) == 2) {
+    WalkDesc W;
+    PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts, &W);
+    *out = P;
+    launch_preprocess(P, s);
+    hipError_t err = launch_walk(P, W, s);
+    launch_consolidate(P, s);
+    return err == hipSuccess ? hipGetLastError() : err;
+  }
+  PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts);
+  *out = P;
+  std::lock_guard<std::mutex> lock(g_aux_mu);
+  Aux* ax = nullptr;
+  hipError_t err = get_aux(&ax);
+  if (err != hipSuccess) return err;
+  launch_preprocess(P, s);
+  err = enqueue_rows(P, P.Mmax, s, *ax, [](int, bool, hipStream_t) {});
+  launch_consolidate(P, s);
+  return err == hipSuccess ? hipGetLastError() : err;
+}
+
+// workspace of the left solve beyond the right solve's: S', T' (m^2 doubles each), select'
+size_t left_extra_bytes(int64_t m) {
+  return up((size_t)(2 * m * m) * sizeof(double) + (size_t)m * sizeof(int32_t));
+}
+
 }  // namespace
 
 extern "C" {
@@ -415,24 +449,38 @@ int rtgevc(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt
   if (m > 0 && !Z) return -7;
   if (ldz < (m > 1 ? m : 1)) return -8;
   if (m == 0) return 0;
+  PencilDesc P;
+  return hip_code(enqueue_right(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts,
+                                static_cast<hipStream_t>(stream), &P));
+}
+
+size_t rtgevc_left_workspace_size(int64_t m, const rtgevc_opts* opts) {
+  if (m < 0) return 0;
+  if (m == 0) return kAlign;
+  return rtgevc_workspace_size(m, opts) + left_extra_bytes(m);
+}
+
+int rtgevc_left(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt, const int32_t* select,
+                double* Y, int64_t ldy, int32_t* scales, int32_t* info, void* work, size_t work_bytes,
+                const rtgevc_opts* opts, void* stream) {
+  int rc = check_common(m, S, lds, T, ldt, work, work_bytes, opts, 11, 12, 13);
+  if (rc) return rc;
+  if (m > 0 && !Y) return -7;
+  if (ldy < (m > 1 ? m : 1)) return -8;
+  if (m == 0) return 0;
+  if (work_bytes < rtgevc_left_workspace_size(m, opts)) return -12;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (resolve_schedule(m, opts) == 2) {
-    WalkDesc W;
-    PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts, &W);
-    launch_preprocess(P, s);
-    hipError_t err = launch_walk(P, W, s);
-    launch_consolidate(P, s);
-    if (err == hipSuccess) err = hipGetLastError();
-    return hip_code(err);
-  }
-  PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts);
-  std::lock_guard<std::mutex> lock(g_aux_mu);
-  Aux* ax = nullptr;
-  hipError_t err = get_aux(&ax);
-  if (err != hipSuccess) return hip_code(err);
-  launch_preprocess(P, s);
-  err = enqueue_rows(P, P.Mmax, s, *ax, [](int, bool, hipStream_t) {});
-  launch_consolidate(P, s);
+  // (S', T', select') after the right solve's own workspace
+  char* extra = static_cast<char*>(work) + rtgevc_workspace_size(m, opts);
+  double* Sp = reinterpret_cast<double*>(extra);
+  double* Tp = Sp + m * m;
+  int32_t* selp = reinterpret_cast<int32_t*>(Tp + m * m);
+  launch_left_flip(m, S, lds, Sp, s);
+  launch_left_flip(m, T, ldt, Tp, s);
+  if (select) launch_left_select(m, select, selp, s);
+  PencilDesc P;
+  hipError_t err = enqueue_right(m, Sp, m, Tp, m, select ? selp : nullptr, Y, ldy, scales, info, work, opts, s, &P);
+  launch_left_finish(m, P.blk, Y, ldy, scales, s);
   if (err == hipSuccess) err = hipGetLastError();
   return hip_code(err);
 }

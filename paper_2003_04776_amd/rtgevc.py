@@ -65,6 +65,10 @@ def load():
     L.rtgevc_batched_workspace_size.argtypes = [ctypes.c_int32, vp, op]
     L.rtgevc_batched.restype = ctypes.c_int
     L.rtgevc_batched.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, op, vp]
+    L.rtgevc_left_workspace_size.restype = sz
+    L.rtgevc_left_workspace_size.argtypes = [i64, op]
+    L.rtgevc_left.restype = ctypes.c_int
+    L.rtgevc_left.argtypes = [i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, vp, sz, op, vp]
     L.rtgevc_backtransform_workspace_size.restype = sz
     L.rtgevc_backtransform_workspace_size.argtypes = [i64, op]
     L.rtgevc_backtransform.restype = ctypes.c_int
@@ -80,7 +84,8 @@ def load():
 
 
 EXPORTED = ("rtgevc_workspace_size", "rtgevc", "rtgevc_eigvals", "rtgevc_timed",
-            "rtgevc_batched_workspace_size", "rtgevc_batched", "rtgevc_backtransform_workspace_size",
+            "rtgevc_batched_workspace_size", "rtgevc_batched", "rtgevc_left_workspace_size", "rtgevc_left",
+            "rtgevc_backtransform_workspace_size",
             "rtgevc_backtransform", "rtgevc_resolve_opts", "rtgevc_strerror", "rtgevc_version")
 TIMED_NSTATS = 12
 
@@ -178,11 +183,13 @@ class Solver:
     allocation, made once by torch; the library itself allocates nothing)."""
 
     def __init__(self, m: int, mb: int = 0, normalize: bool = True, band: int = 0, device="cuda",
-                 schedule: int = 0, watchdog: int = 0, precision: int = 0):
+                 schedule: int = 0, watchdog: int = 0, precision: int = 0, left: bool = False):
         import torch
         self.m = int(m)
+        self.left = bool(left)
         self.opts = make_opts(mb, normalize, band, schedule, watchdog, precision)
-        self.nbytes = int(load().rtgevc_workspace_size(self.m, ctypes.byref(self.opts)))
+        size = load().rtgevc_left_workspace_size if self.left else load().rtgevc_workspace_size
+        self.nbytes = int(size(self.m, ctypes.byref(self.opts)))
         self.work = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
         self.device = device
 
@@ -202,12 +209,13 @@ class Solver:
             sel = torch.as_tensor(select, dtype=torch.int32, device=self.device).contiguous()
             if sel.shape != (m,):
                 raise ValueError("select must have length m")
-        rc = load().rtgevc(m, S.data_ptr(), lds, T.data_ptr(), ldt,
-                           sel.data_ptr() if sel is not None else None,
-                           Z.data_ptr(), ldz, scales.data_ptr(), info.data_ptr(),
-                           self.work.data_ptr(), self.nbytes, ctypes.byref(self.opts),
-                           _stream_ptr(stream))
-        _check(rc, "rtgevc")
+        fn = load().rtgevc_left if self.left else load().rtgevc
+        rc = fn(m, S.data_ptr(), lds, T.data_ptr(), ldt,
+                sel.data_ptr() if sel is not None else None,
+                Z.data_ptr(), ldz, scales.data_ptr(), info.data_ptr(),
+                self.work.data_ptr(), self.nbytes, ctypes.byref(self.opts),
+                _stream_ptr(stream))
+        _check(rc, "rtgevc_left" if self.left else "rtgevc")
         return Result(Z, scales[:m], info)
 
     def run_timed(self, S, T, Z, scales, info, stream=None):
@@ -236,6 +244,14 @@ class Solver:
                                    _stream_ptr(stream))
         _check(rc, "rtgevc_eigvals")
         return out[0][:m], out[1][:m], out[2][:m], info
+
+
+def tgevc_left(S, T, select=None, normalize: bool = True, mb: int = 0, band: int = 0, stream=None,
+               schedule: int = 0, precision: int = 0) -> Result:
+    """All (or the selected) left eigenvectors u of the Schur pencil, u^H (beta S - alpha T) = 0
+    (Result.Z holds them)."""
+    return Solver(S.shape[0], mb=mb, normalize=normalize, band=band, device=S.device,
+                  schedule=schedule, precision=precision, left=True).run(S, T, select, stream=stream)
 
 
 def tgevc(S, T, select=None, normalize: bool = True, mb: int = 0, band: int = 0, stream=None,

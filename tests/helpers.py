@@ -98,3 +98,27 @@ def residuals_torch(S, T, Z, ar, ai, be, kind):
     den = (nS + nT) * Z.abs().sum(dim=0)
     eta = R.abs().sum(dim=0) / torch.where(den > 0, den, torch.ones_like(den))
     return eta.cpu().numpy()
+
+
+def left_residuals(S, T, Y, ar, ai, be):
+    """eta_c = ||u^H (beta S - alpha T)||_1 / ((||S||_1 + ||T||_1) ||u||_1), complex pairs
+    (p, p+1) as u = Y_p + i Y_{p+1} with alpha = ar_p + i ai_p, (alpha, beta) scaled so that
+    max(beta, |Re alpha| + |Im alpha|) = 1."""
+    m = S.shape[0]
+    kind = block_kinds_from_S(S)
+    nS = np.abs(S).sum(axis=0).max() if m else 0.0
+    nT = np.abs(T).sum(axis=0).max() if m else 0.0
+    out = {}
+    c = 0
+    while c < m:
+        pair = kind[c] == 1
+        a = complex(ar[c], ai[c] if pair else 0.0)
+        b = float(be[c])
+        s = max(b, abs(a.real) + abs(a.imag))
+        a, b = a / s, b / s
+        u = Y[:, c] + (1j * Y[:, c + 1] if pair else 0.0)
+        r = np.conj(u) @ (b * S - a * T)
+        den = (nS + nT) * np.abs(u).sum()
+        out[c] = float(np.abs(r).sum() / den) if den > 0 else 0.0
+        c += 2 if pair else 1
+    return out
