@@ -143,6 +143,34 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_left(args, m, Sd, Td, F, ms_right):
+    """All left eigenvectors of the same pencil (rtgevc_left: the right path on the flipped
+    transposed pencil plus the flip and turn passes), timed with events around each call on
+    its stream."""
+    import torch
+    from paper_2003_04776_amd import rtgevc as rt
+    solver = rt.Solver(m, mb=args.mb, normalize=True, band=args.band, schedule=args.schedule, left=True)
+    Y = rt.colmajor_empty(m)
+    ls = torch.empty(m, dtype=torch.int32, device="cuda")
+    linfo = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for _ in range(max(args.warmup, 1)):
+        solver.run(Sd, Td, Z=Y, scales=ls, info=linfo)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        solver.run(Sd, Td, Z=Y, scales=ls, info=linfo)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / max(args.steps, 1)
+    log(f"[bench] left eigenvectors: {ms:.1f} ms per call")
+    res = {"what": "all left eigenvectors u^H (beta S - alpha T) = 0 of the same pencil, FP64, normalised",
+           "ms_per_call": round(ms, 3), "value": round(F / (ms * 1e-3) / 1e12, 4), "unit": "TFLOP/s",
+           "time_vs_right": round(ms / ms_right, 4), "info": int(linfo.item())}
+    del solver, Y
+    return res
+
+
 def bench_back(args, m, Sd, Zf, scales, blk):
     """The back-transformation X = V Z of the FP64 eigenvectors with a seeded dense V (the
     contraction does not depend on V being orthogonal), timed with events on the stream it
@@ -200,6 +228,8 @@ def main():
                     help="0: FP64 tile updates; 1: mixed (int8 matrix cores on split operands)")
     ap.add_argument("--no-compare-mixed", dest="compare_mixed", action="store_false",
                     help="skip the mixed-precision run that follows the FP64 one")
+    ap.add_argument("--no-left", dest="left", action="store_false",
+                    help="skip the left eigenvectors timed after the right ones")
     ap.add_argument("--no-back", dest="back", action="store_false",
                     help="skip the back-transformation X = V Z timed after the eigenvectors")
     ap.add_argument("--seed", type=int, default=400)
@@ -339,6 +369,8 @@ def main():
         }
         log(f"[bench] mixed: {mwall:.1f} ms/step, speed-up {ms_per_step / mwall:.3f}")
         del mixed
+    if args.left and args.precision == 0:
+        out["left"] = bench_left(args, m, Sd, Td, F, ms_per_step)
     if args.back:
         out["backtransform"] = bench_back(args, m, Sd, Zf, scales, blk)
     del Zf

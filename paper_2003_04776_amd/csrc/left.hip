@@ -7,7 +7,8 @@
 // 180 degrees (rows and columns reversed, the scales reversed), and for every complex pair
 // (p, p+1) of S the two columns swapped with the imaginary part negated.  The robust
 // bounds of the right solve on (S', T') are those of a left solve on (S, T): its
-// infinity norms of tiles of S' are the 1-norms of tiles of S.
+// infinity norms of tiles of S' are the 1-norms of tiles of S (the conclusion, Section 7,
+// names left eigenvectors with the 1-norm in place of the infinity norm as the extension).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
