@@ -168,3 +168,40 @@ def test_back_full_size_8192_sampled():
     assert ig == 0 and len(cols) > 30
     assert np.abs(Xg[:, cols] - Xo[:, cols]).max() <= 1e-12
     assert not Xg[:, ~Z.any(axis=0)].any()
+
+
+def test_back_graph_capture_replays():
+    """The back-transformation is a fixed sequence of kernel launches (no allocation, no
+    memset, no synchronisation): captured once, every replay, with eager work and
+    synchronisation in between, reproduces the eager result bit for bit."""
+    torch = _torch()
+    from paper_2003_04776_amd import rtgevc as rt
+    m = 700
+    S, T, _ = pencils.schur_pencil(m, 81)
+    Z, sc, _ = oracle.tgevc(S, T)
+    Sd, Vd, Zd = rt.colmajor_to_device(S), rt.colmajor_to_device(_dense(m, 82)), rt.colmajor_to_device(Z)
+    sd = torch.as_tensor(sc, device="cuda")
+    bt = rt.BackTransformer(m, mb=64)
+    X = rt.colmajor_empty(m)
+    xs = torch.empty(m, dtype=torch.int32, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _say("back graph: eager")
+    bt.run(Sd, Vd, Zd, sd, X=X, xscales=xs, info=info)
+    torch.cuda.synchronize()
+    ref = X.clone()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            bt.run(Sd, Vd, Zd, sd, X=X, xscales=xs, info=info, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        X.fill_(float("nan"))
+        xs.fill_(7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(X, ref) and not bool(xs.any()) and int(info.item()) == 0, rep
+        _say(f"   replay {rep}: identical")
