@@ -216,6 +216,13 @@ __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange&
     for (int b = 0; b < CB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
   // operands swapped: acc holds (A W)^T blocks, so a lane's four accumulator registers
   // are one C row of four columns and a wave's store covers whole lines
+  auto mma = [&](const double (&af)[RB], const double (&bf)[CB]) {
+#pragma unroll
+    for (int a = 0; a < RB; ++a)
+#pragma unroll
+      for (int q = 0; q < CB; ++q)
+        acc[a][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[q], af[a], acc[a][q], 0, 0, 0);
+  };
   auto use = [&](double (&af)[RB], double (&bf)[CB], const int (&sgl)[CB], bool live) {
     if (!live) {             // a step past the band's end: W = 0
 #pragma unroll
@@ -231,11 +238,7 @@ __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange&
         for (int q = 0; q < CB; ++q) bf[q] = ldexp(bf[q], sgl[q]);
       }
     }
-#pragma unroll
-    for (int a = 0; a < RB; ++a)
-#pragma unroll
-      for (int q = 0; q < CB; ++q)
-        acc[a][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[q], af[a], acc[a][q], 0, 0, 0);
+    mma(af, bf);
   };
 
   // NS register slots rotate through an unrolled loop: the loads of step t + NS - 1 are in
@@ -275,11 +278,28 @@ __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange&
       for (int q = 0; q < CB; ++q) sgl[u][q] = sg[src[u]][16 * (CB * wc + q) + li];
   }
 
-  for (int t0 = 0; t0 < nrun; t0 += NS) {
+  if (!fix_a && !sgbits) {
+    // The common case: no scaling of the fragments and no step past the end inside the
+    // loop (the last nst mod NS steps, already loaded, run after it), so the loop body is
+    // the loader, loads and matrix instructions.
+    int t0 = 0;
+    for (; t0 + NS <= nst; t0 += NS) {
 #pragma unroll
-    for (int u = 0; u < NS; ++u) {
-      load(af[(u + NS - 1) % NS], bf[(u + NS - 1) % NS], sgl[(u + NS - 1) % NS], src[(u + NS - 1) % NS]);
-      use(af[u], bf[u], sgl[u], t0 + u < nst);
+      for (int u = 0; u < NS; ++u) {
+        load(af[(u + NS - 1) % NS], bf[(u + NS - 1) % NS], sgl[(u + NS - 1) % NS], src[(u + NS - 1) % NS]);
+        mma(af[u], bf[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NS - 1; ++u)
+      if (t0 + u < nst) mma(af[u], bf[u]);
+  } else {
+    for (int t0 = 0; t0 < nrun; t0 += NS) {
+#pragma unroll
+      for (int u = 0; u < NS; ++u) {
+        load(af[(u + NS - 1) % NS], bf[(u + NS - 1) % NS], sgl[(u + NS - 1) % NS], src[(u + NS - 1) % NS]);
+        use(af[u], bf[u], sgl[u], t0 + u < nst);
+      }
     }
   }
 
