@@ -220,7 +220,9 @@ class Solver:
 
     def run_timed(self, S, T, Z, scales, info, stream=None):
         """rtgevc_timed: same work, HIP events around every launch; returns the stats
-        dict (synchronises the stream)."""
+        dict (synchronises the stream).  Right eigenvectors only."""
+        if self.left:
+            raise RtgevcError("run_timed times the right-eigenvector call; time rtgevc_left with events")
         m = self.m
         lds, ldt, ldz = _ld(S, m), _ld(T, m), _ld(Z, m)
         st = (ctypes.c_double * TIMED_NSTATS)()
