@@ -244,7 +244,7 @@ def main():
                          "(a kernel of known traffic, to calibrate memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for {args.gpus})",
+        print(f"bench.py runs on one GPU only: the library has no multi-GPU path (asked for {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched":
