@@ -205,3 +205,22 @@ def test_back_graph_capture_replays():
         torch.cuda.synchronize()
         assert torch.equal(X, ref) and not bool(xs.any()) and int(info.item()) == 0, rep
         _say(f"   replay {rep}: identical")
+
+
+def test_back_padded_leading_dimensions():
+    """S, V, Z and X with leading dimensions larger than m give the same result."""
+    torch = _torch()
+    from paper_2003_04776_amd import rtgevc as rt
+    m = 260
+    S, T, _ = pencils.schur_pencil(m, 91)
+    Z, sc, _ = oracle.tgevc(S, T)
+    V = _dense(m, 92)
+    _say("back padded leading dimensions")
+    X1, xs1, _ = gpu_back(S, V, Z, sc, mb=128)
+    Sd = rt.colmajor_to_device(S, ld=m + 3)
+    Vd = rt.colmajor_to_device(V, ld=m + 5)
+    Zd = rt.colmajor_to_device(Z, ld=m + 7)
+    X = rt.colmajor_empty(m, ld=m + 9)
+    res = rt.BackTransformer(m, mb=128).run(Sd, Vd, Zd, torch.as_tensor(sc, device="cuda"), X=X)
+    torch.cuda.synchronize()
+    assert np.array_equal(res.Z.cpu().numpy(), X1) and np.array_equal(res.scales.cpu().numpy(), xs1)
