@@ -36,7 +36,8 @@ __device__ __forceinline__ Cx cdivx(Cx x, Cx y) {
   complex_div(x.r, x.i, y.r, y.i, z.r, z.i);
   return z;
 }
-__device__ __forceinline__ Cx cscl(Cx x, int q) { return q ? Cx{ldexp(x.r, -q), ldexp(x.i, -q)} : x; }
+// (ldexp by 0 is the identity, so no select on q is needed)
+__device__ __forceinline__ Cx cscl(Cx x, int q) { return Cx{ldexp(x.r, -q), ldexp(x.i, -q)}; }
 
 // When a protection has to scale, the solves scale by 2^128 more than the least
 // exponent: any power of two that meets the bound represents the same vector, and the
