@@ -167,3 +167,28 @@ def test_backtransform_workspace_and_argument_errors():
     assert call(o=bad) == -15
     assert call(m=0) == 0
     assert "argument 4" in rt.strerror(-4)
+
+
+def test_left_workspace_and_argument_errors():
+    """The left call takes rtgevc's arguments (Y in place of Z) and a workspace larger by
+    the flipped pencil; invalid arguments are rejected on the host."""
+    L = rt.load()
+    o = rt.make_opts()
+    for m in (1, 10, 1000):
+        assert L.rtgevc_left_workspace_size(m, ctypes.byref(o)) >= rt.workspace_size(m) + 16 * m * m
+    m, p = 4, 1 << 20
+    nb = L.rtgevc_left_workspace_size(m, ctypes.byref(o))
+    call = lambda **k: L.rtgevc_left(k.get("m", m), k.get("S", p), k.get("lds", m), k.get("T", p), k.get("ldt", m),
+                                     None, k.get("Y", 2 * p), k.get("ldy", m), None, None, k.get("work", p),
+                                     k.get("nb", nb), ctypes.byref(k.get("o", o)), None)
+    assert call(m=-1) == -1
+    assert call(S=None) == -2
+    assert call(lds=m - 1) == -3
+    assert call(T=None) == -4
+    assert call(ldt=1) == -5
+    assert call(Y=None) == -7
+    assert call(ldy=1) == -8
+    assert call(work=p + 8) == -11
+    assert call(nb=rt.workspace_size(m)) == -12     # enough for rtgevc, not for the left call
+    assert call(o=rt.make_opts(mb=96)) == -13
+    assert call(m=0) == 0
