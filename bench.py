@@ -53,7 +53,8 @@ def log(*a):
 def cpu_baseline(S, T, blk, m, seconds):
     """The oracle (scalar robust substitution, one eigenvector at a time) on a sample of
     columns spread evenly over the pencil, on the host cores; rate in FP64-equivalent
-    TFLOP/s (2 p^2 flops for the eigenvector of column p)."""
+    TFLOP/s (2 p^2 flops for the eigenvector of column p).  Also returns the sampled
+    columns and the oracle's eigenvectors for them."""
     import numpy as np
 
     import oracle
@@ -77,11 +78,12 @@ def cpu_baseline(S, T, blk, m, seconds):
     idx = np.nonzero(on)[0]
     flops = float(np.sum(2.0 * (idx + 1.0) ** 2))
     t0 = time.perf_counter()
-    oracle.tgevc(S, T, select=sel, threads=threads)
+    Zo, _, _ = oracle.tgevc(S, T, select=sel, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(idx)} of {m} columns evenly spread over the pencil, {flops:.3e} "
-                      f"algorithmic flops in {dt:.1f} s; double-precision scalar robust substitution"}
+    res = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+           "sample": f"{len(idx)} of {m} columns evenly spread over the pencil, {flops:.3e} "
+                     f"algorithmic flops in {dt:.1f} s; double-precision scalar robust substitution"}
+    return res, idx, Zo[:, idx]
 
 
 def bench_batched(args):
@@ -373,10 +375,15 @@ def main():
         out["left"] = bench_left(args, m, Sd, Td, F, ms_per_step)
     if args.back:
         out["backtransform"] = bench_back(args, m, Sd, Zf, scales, blk)
-    del Zf
     if rank == 0 and not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a column sample")
-        out["cpu_baseline"] = cpu_baseline(S, T, blk, m, args.cpu_seconds)
+        out["cpu_baseline"], idx, Zo = cpu_baseline(S, T, blk, m, args.cpu_seconds)
+        if args.precision == 0:
+            # the FP64 result against the oracle on the same (normalised) columns
+            Zs = Zf[:, torch.from_numpy(idx).to(Zf.device)].cpu().numpy()
+            err = np.abs(Zs - Zo).max(axis=0)
+            out["oracle_check"] = {"columns": int(len(idx)), "max_abs_err": float(err.max()),
+                                   "columns_above_1e-10": int((err > 1e-10).sum())}
     if rank == 0:
         print(json.dumps(out), flush=True)
 
