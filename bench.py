@@ -145,6 +145,35 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def residual_max(Sd, Td, Z, ar, ai, be, kind):
+    """max_c ||S Z_c D_c - T Z_c B_c||_1 / ((||S||_1 + ||T||_1) ||Z_c||_1) on the GPU in FP64
+    (the eigen-equation of the Schur pencil column by column; a complex pair (p, p+1) in its
+    real form, (alpha, beta) scaled so that max(beta, |Re alpha| + |Im alpha|) = 1)."""
+    import numpy as np
+    import torch
+    dev = Z.device
+    m = Z.shape[0]
+    kind = np.asarray(kind)
+    p = np.where(kind == 2, np.arange(m) - 1, np.arange(m))
+    a, b, bt = ar[p].astype(float), np.abs(ai[p]).astype(float), be[p].astype(float)
+    s = np.maximum(bt, np.abs(a) + b)
+    s[s == 0] = 1.0
+    A, Bv, BT = (torch.from_numpy(v / s).to(dev) for v in (a, b, bt))
+    R = (Sd @ Z) * BT
+    TZ = Td @ Z
+    TZB = TZ * A
+    k1 = torch.from_numpy(np.nonzero(kind == 1)[0]).to(dev)
+    if k1.numel():
+        TZB[:, k1] = A[k1] * TZ[:, k1] - Bv[k1] * TZ[:, k1 + 1]
+        TZB[:, k1 + 1] = Bv[k1] * TZ[:, k1] + A[k1] * TZ[:, k1 + 1]
+    del TZ
+    R -= TZB
+    del TZB
+    den = (Sd.abs().sum(dim=0).max() + Td.abs().sum(dim=0).max()) * Z.abs().sum(dim=0)
+    eta = R.abs().sum(dim=0) / torch.where(den > 0, den, torch.ones_like(den))
+    return float(eta.max().item())
+
+
 def bench_left(args, m, Sd, Td, F, ms_right):
     """All left eigenvectors of the same pencil (rtgevc_left: the right path on the flipped
     transposed pencil plus the flip and turn passes), timed with events around each call on
@@ -230,6 +259,8 @@ def main():
                     help="0: FP64 tile updates; 1: mixed (int8 matrix cores on split operands)")
     ap.add_argument("--no-compare-mixed", dest="compare_mixed", action="store_false",
                     help="skip the mixed-precision run that follows the FP64 one")
+    ap.add_argument("--no-residual", dest="residual", action="store_false",
+                    help="skip the eigen-equation residuals of the FP64 and mixed results")
     ap.add_argument("--no-left", dest="left", action="store_false",
                     help="skip the left eigenvectors timed after the right ones")
     ap.add_argument("--no-back", dest="back", action="store_false",
@@ -371,6 +402,15 @@ def main():
         }
         log(f"[bench] mixed: {mwall:.1f} ms/step, speed-up {ms_per_step / mwall:.3f}")
         del mixed
+    if args.residual and args.precision == 0:
+        # the eigen-equation residual of the FP64 result and of the mixed one (same bound)
+        are, aim, bet, _ = solver.eigvals(Sd, Td)
+        ar, ai, be = (x.cpu().numpy() for x in (are, aim, bet))
+        res = {"bound": 64 * m * 2.0 ** -53, "fp64_max": residual_max(Sd, Td, Zf, ar, ai, be, blk)}
+        if "mixed" in out:
+            res["mixed_max"] = residual_max(Sd, Td, Z, ar, ai, be, blk)
+        out["residual"] = res
+        log(f"[bench] residuals: {res}")
     if args.left and args.precision == 0:
         out["left"] = bench_left(args, m, Sd, Td, F, ms_per_step)
     if args.back:
