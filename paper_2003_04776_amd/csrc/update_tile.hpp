@@ -39,7 +39,7 @@ namespace rgev {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 
-constexpr int kChunk = 16;   // K rows per LDS stage
+constexpr int kChunk = 16;   // source heights are padded to a multiple of kChunk rows
 
 // wave grid R x C per tile size and S, the register slots of the fragment pipeline
 template <int MB> struct UpdShape;
