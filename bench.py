@@ -345,7 +345,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "i8+f64" if args.precision == 1 else "f64",
         "data": "synthetic",
         "config": {
             "workload": f"all right eigenvectors of a real Schur pencil, m={m}, robust FP64 "
