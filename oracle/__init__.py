@@ -181,7 +181,8 @@ def tgevc_left(S: np.ndarray, T: np.ndarray, select=None, normalize: bool = True
     computed by the right-eigenvector oracle.  For a complex pair (p, p+1) of S, column p
     holds Re u and column p+1 Im u of the left eigenvector for alpha_im[p] > 0.  The
     robustness bounds of the right solve on (S', T') are those of the left solve on (S, T)
-    (its infinity norms are the 1-norms of S and T).  Returns (Y, scales, info) like tgevc."""
+    (its infinity norms are the 1-norms of S and T, as the conclusion, Section 7, asks of a
+    left solve).  Returns (Y, scales, info) like tgevc."""
     m = S.shape[0]
     Sf = np.array(S.T[::-1, ::-1], order="F")   # (copies with positive strides)
     Tf = np.array(T.T[::-1, ::-1], order="F")
