@@ -224,3 +224,27 @@ def test_back_padded_leading_dimensions():
     res = rt.BackTransformer(m, mb=128).run(Sd, Vd, Zd, torch.as_tensor(sc, device="cuda"), X=X)
     torch.cuda.synchronize()
     assert np.array_equal(res.Z.cpu().numpy(), X1) and np.array_equal(res.scales.cpu().numpy(), xs1)
+
+
+def test_back_null_scales_and_info():
+    """scales = NULL means all exponents zero and info = NULL uses the workspace's own
+    word: the same result as with both given (normalised Z has zero exponents)."""
+    torch = _torch()
+    import ctypes
+    from paper_2003_04776_amd import rtgevc as rt
+    m = 150
+    S, T, _ = pencils.schur_pencil(m, 95)
+    Z, sc, _ = oracle.tgevc(S, T)
+    V = _dense(m, 96)
+    _say("back null scales and info")
+    X1, xs1, _ = gpu_back(S, V, Z, sc, mb=64)
+    Sd, Vd, Zd = rt.colmajor_to_device(S), rt.colmajor_to_device(V), rt.colmajor_to_device(Z)
+    X = rt.colmajor_empty(m)
+    xs = torch.empty(m, dtype=torch.int32, device="cuda")
+    bt = rt.BackTransformer(m, mb=64)
+    rc = rt.load().rtgevc_backtransform(m, Sd.data_ptr(), m, Vd.data_ptr(), m, Zd.data_ptr(), m, None,
+                                        X.data_ptr(), m, xs.data_ptr(), None, bt.work.data_ptr(), bt.nbytes,
+                                        ctypes.byref(bt.opts), rt._stream_ptr(None))
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(X.cpu().numpy(), X1) and np.array_equal(xs.cpu().numpy(), xs1)

@@ -133,3 +133,23 @@ def test_left_full_size_8192_sampled():
     cols = [c for c in np.flatnonzero(Yo.any(axis=0)) if np.abs(Yo[:, c] - Yl[:, c]).max() <= WELL]
     assert len(cols) > 30
     assert np.abs(Yg[:, cols] - Yo[:, cols]).max() <= TOL
+
+
+def test_left_null_info_and_scales_output():
+    """info = NULL is accepted (the workspace keeps the flags); the scales output is written."""
+    torch = _torch()
+    import ctypes
+    from paper_2003_04776_amd import rtgevc as rt
+    m = 120
+    S, T, _ = pencils.schur_pencil(m, 97)
+    _say("left null info")
+    Y1, s1, _ = run_left(S, T, mb=32)
+    solver = rt.Solver(m, mb=32, left=True)
+    Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
+    Y = rt.colmajor_empty(m)
+    sc = torch.full((m,), 5, dtype=torch.int32, device="cuda")
+    rc = rt.load().rtgevc_left(m, Sd.data_ptr(), m, Td.data_ptr(), m, None, Y.data_ptr(), m, sc.data_ptr(), None,
+                               solver.work.data_ptr(), solver.nbytes, ctypes.byref(solver.opts), rt._stream_ptr(None))
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(Y.cpu().numpy(), Y1) and not bool(sc.any())
