@@ -18,6 +18,7 @@
 #include "rtgevc.h"
 #include "back.hpp"
 #include "layout.hpp"
+#include "schedule.hpp"
 #include "slices.hpp"
 
 namespace rgev {
@@ -262,60 +263,39 @@ hipError_t get_aux(Aux** out) {
   return hipSuccess;
 }
 
-// The blocked back-substitution for tile rows [0, rows), bottom band first (Algorithm 1
-// with the tasks grouped into bands of R tile rows, the rows [R b, R b + R - 1]):
-//   C(b)   on the caller's stream: the band's rows from the bottom up, each solve
-//          followed by the small update of the band rows above it;
-//   U1(b)  on the caller's stream: the band applied to the next band's rows;
-//   U2(b)  on the side stream: the band applied to every row above the next band.
-// C(b-1) only needs U1(b) and U2(b+1), so it overlaps U2(b) (look-ahead).  C(b) waits
-// for U2(b+2), which last wrote its rows and read the W slots it is about to reuse.
-// mark(kind, before, stream) brackets each launch (kind 1 = solve, 2 = update); rows at
-// or beyond the device's tile count M are no-ops in the kernels.
+// The blocked back-substitution for tile rows [0, rows): the band wavefront schedule
+// (schedule.hpp) enqueued on the caller's stream sa and the side stream.  mark(kind,
+// before, stream) brackets each launch (kind 1 = solve, 2 = update); rows at or beyond
+// the device's tile count M are no-ops in the kernels.
 template <class Mark>
 hipError_t enqueue_rows(const PencilDesc& P, int rows, hipStream_t sa, Aux& ax, Mark&& mark) {
-  const int R = P.band;
-  hipStream_t sb = ax.side;
   hipError_t err = hipSuccess;
-  auto chk = [&](hipError_t e) {
-    if (err == hipSuccess) err = e;
-  };
-  // the side stream starts after everything already queued on the caller's stream
-  chk(hipEventRecord(ax.evC, sa));
-  chk(hipStreamWaitEvent(sb, ax.evC, 0));
-  chk(hipEventRecord(ax.evU[0], sb));
-  chk(hipEventRecord(ax.evU[1], sb));
-  for (int b = (rows - 1) / R; b >= 0 && err == hipSuccess; --b) {
-    const int r_lo = R * b, r_hi = R * b + R - 1;
-    chk(hipStreamWaitEvent(sa, ax.evU[b & 1], 0));
-    for (int i = (r_hi < rows ? r_hi : rows - 1); i >= r_lo; --i) {
-      mark(1, true, sa);
-      launch_solve(P, i, sa);
-      mark(1, false, sa);
-      if (i > r_lo) {
-        mark(2, true, sa);
-        launch_update(P, r_lo, i, i, i, i, sa);
-        mark(2, false, sa);
-      }
+  struct Ops {
+    const PencilDesc& P;
+    hipStream_t st[2];
+    hipEvent_t ev[4];
+    Mark& mark;
+    hipError_t& err;
+    bool ok(hipError_t e) {
+      if (err == hipSuccess) err = e;
+      return err == hipSuccess;
     }
-    if (r_lo > 0) {
-      chk(hipEventRecord(ax.evC, sa));
-      const int nlo = r_lo > R ? r_lo - R : 0;
-      mark(2, true, sa);
-      launch_update(P, nlo, r_lo, r_lo, r_lo, r_hi, sa);
-      mark(2, false, sa);
-      if (nlo > 0) {
-        chk(hipStreamWaitEvent(sb, ax.evC, 0));
-        mark(2, true, sb);
-        launch_update(P, 0, nlo, r_lo, r_lo, r_hi, sb);
-        mark(2, false, sb);
-        chk(hipEventRecord(ax.evU[b & 1], sb));
-      }
+    bool solve(int i, int s) {
+      mark(1, true, st[s]);
+      launch_solve(P, i, st[s]);
+      mark(1, false, st[s]);
+      return err == hipSuccess;
     }
-  }
-  // join the side stream back into the caller's stream
-  chk(hipEventRecord(ax.evJ, sb));
-  chk(hipStreamWaitEvent(sa, ax.evJ, 0));
+    bool update(int k_lo, int k_hi, int j_lo, int s_lo, int s_hi, int s) {
+      mark(2, true, st[s]);
+      launch_update(P, k_lo, k_hi, j_lo, s_lo, s_hi, st[s]);
+      mark(2, false, st[s]);
+      return err == hipSuccess;
+    }
+    bool record(int e, int s) { return ok(hipEventRecord(ev[e], st[s])); }
+    bool wait(int s, int e) { return ok(hipStreamWaitEvent(st[s], ev[e], 0)); }
+  } ops{P, {sa, ax.side}, {ax.evC, ax.evJ, ax.evU[0], ax.evU[1]}, mark, err};
+  band_schedule(rows, P.band, ops);
   return err;
 }
 

@@ -1,0 +1,67 @@
+// Band wavefront schedule of Algorithm 1 (Section 3) for one pencil: the order in
+// which the tile solves and tile updates are enqueued on two streams, with the events
+// that order them.  Host code only, no HIP types: the operations are supplied by the
+// caller (Ops), so the same schedule drives the HIP launches and the host-side replay
+// that checks its ordering.
+//
+// Tile rows [0, rows) are grouped into bands of R rows, band b = rows [R b, R b + R - 1].
+// For each band from the bottom:
+//   C(b)   on the caller's stream A: the band's rows from the bottom up, each solve
+//          followed by the small update of the band rows above it;
+//   U1(b)  on A: the band applied to the next band's rows [R (b - 1), R b);
+//   U2(b)  on the side stream B: the band applied to every row above, [0, R (b - 1)).
+// Dependencies (every one is an event or stream order):
+//   U1(b)  needs U2(b + 1), which also read-modifies-writes rows of band b - 1 (the
+//          sources of a tile are applied in descending order, and a tile column's first
+//          update overwrites rather than accumulates), so the two must not overlap;
+//   C(b)   needs U2(b + 2), the last writer of its rows and the last reader of the W
+//          slots (two bands of them) it is about to overwrite: C(b) follows U1(b + 1)
+//          on A, which waited for U2(b + 2);
+//   U2(b)  needs C(b) (its sources), and stream order on B puts it after U2(b + 1).
+// C(b - 1) needs U1(b) and U2(b + 1) only, so it overlaps U2(b) (the look-ahead).
+#pragma once
+
+namespace rgev {
+
+enum SchedStream { kStreamA = 0, kStreamB = 1 };
+enum SchedEvent { kEvC = 0, kEvJ = 1, kEvU0 = 2, kEvU1 = 3 };
+
+// Ops:  solve(i, stream)                              solve tile row i (all columns j >= i)
+//       update(k_lo, k_hi, j_lo, s_lo, s_hi, stream)  sources [s_lo, s_hi] -> rows [k_lo, k_hi)
+//       record(event, stream), wait(stream, event)    event order between the streams
+// Each returns false on failure, which stops the enqueue.
+template <class Ops>
+bool band_schedule(int rows, int R, Ops& ops) {
+  bool ok = true;
+  auto chk = [&](bool b) { ok = ok && b; };
+  // the side stream starts after everything already queued on the caller's stream
+  chk(ops.record(kEvC, kStreamA));
+  chk(ops.wait(kStreamB, kEvC));
+  chk(ops.record(kEvU0, kStreamB));
+  chk(ops.record(kEvU1, kStreamB));
+  for (int b = (rows - 1) / R; b >= 0 && ok; --b) {
+    const int r_lo = R * b, r_hi = R * b + R - 1;
+    for (int i = (r_hi < rows ? r_hi : rows - 1); i >= r_lo && ok; --i) {
+      chk(ops.solve(i, kStreamA));
+      if (i > r_lo) chk(ops.update(r_lo, i, i, i, i, kStreamA));
+    }
+    if (r_lo > 0 && ok) {
+      chk(ops.record(kEvC, kStreamA));
+      const int nlo = r_lo > R ? r_lo - R : 0;
+      // U2(b + 1): evU[(b + 1) & 1] was last recorded after it
+      chk(ops.wait(kStreamA, ((b + 1) & 1) ? kEvU1 : kEvU0));
+      chk(ops.update(nlo, r_lo, r_lo, r_lo, r_hi, kStreamA));
+      if (nlo > 0) {
+        chk(ops.wait(kStreamB, kEvC));
+        chk(ops.update(0, nlo, r_lo, r_lo, r_hi, kStreamB));
+        chk(ops.record((b & 1) ? kEvU1 : kEvU0, kStreamB));
+      }
+    }
+  }
+  // join the side stream back into the caller's stream
+  chk(ops.record(kEvJ, kStreamB));
+  chk(ops.wait(kStreamA, kEvJ));
+  return ok;
+}
+
+}  // namespace rgev
