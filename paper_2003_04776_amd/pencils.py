@@ -32,12 +32,29 @@ Recipe (per pencil, seed ``seed``):
   block's column draws one more uniform u: u < 0.01 sets s = 0 (zero eigenvalue),
   0.01 <= u < 0.02 sets t = 0 (infinite eigenvalue) -- about 1 percent of each, as in the
   pencils of the paper's experiments (Section 6), so some eigenvalues repeat.
+* ``kind="general"``: 2x2 blocks in the general form of a real Schur pencil (Section 2
+  only asks for T upper triangular): T_b = [[t11, t12], [0, t22]] with t11, t22 ~ U[0.5, 2]
+  drawn separately and t12 ~ N(0, 1) in about half of the blocks (u < 1/2), else 0; and
+  S_b = T_b M with M = [[a, b], [c, a + e]], a ~ N(0, 1), b ~ U[0.5, 2], c = -U[0.5, 2],
+  e ~ U[-0.9, 0.9].  Then det(S_b - lambda T_b) = det(T_b) det(M - lambda I), and since
+  e^2 < 1 <= -4 b c the block's eigenvalues (those of M) are a complex pair.  Draw order
+  of the block's column: a, b, c, e, t11, t22, u, t12.  1x1 blocks and off-diagonal entries
+  as for "normal".
+* ``kind="general_stress"``: "general" with t11, t22 of 10**U[-12, -6], t12 the N(0, 1)
+  draw times min(t11, t22), M multiplied by f = 10**U[6, 12] (drawn last), so that the
+  eigenvalues spread over the same magnitudes as those of "stress", and every
+  off-diagonal entry multiplied by 1e100.
+
+``qz_pencil`` gives a third source of inputs: the real generalized Schur form
+(S, T) = (Q^T A Zq, Q^T B Zq) that LAPACK's QZ algorithm (through SciPy) computes for a
+seeded dense pencil (A, B) with N(0, 1) entries -- the pencils the method receives in
+practice (Section 1), with 2x2 blocks whose T part has t11 != t22.
 """
 from __future__ import annotations
 
 import numpy as np
 
-KINDS = ("normal", "stress", "zeroinf", "degenerate")
+KINDS = ("normal", "stress", "zeroinf", "degenerate", "general", "general_stress")
 
 
 def _stream(seed: int, j: int) -> np.random.Generator:
@@ -61,7 +78,7 @@ def block_starts(m: int, seed: int) -> np.ndarray:
 
 
 def _tdiag(rng: np.random.Generator, kind: str) -> float:
-    if kind == "stress":
+    if kind in ("stress", "general_stress"):
         return float(10.0 ** rng.uniform(-12.0, -6.0))
     return float(rng.uniform(0.5, 2.0))
 
@@ -70,7 +87,8 @@ def fill_columns(S: np.ndarray, T: np.ndarray, kind_arr: np.ndarray, seed: int,
                  j0: int, j1: int, kind: str = "normal") -> None:
     """Write columns [j0, j1) of S and T (arrays indexed [row, col], any strides)."""
     m = kind_arr.shape[0]
-    offscale = 1e100 if kind == "stress" else 1.0
+    offscale = 1e100 if kind in ("stress", "general_stress") else 1.0
+    general = kind in ("general", "general_stress")
     zero_at = inf_at = -1
     if kind == "zeroinf":
         ones = np.flatnonzero(kind_arr == 0)
@@ -82,6 +100,26 @@ def fill_columns(S: np.ndarray, T: np.ndarray, kind_arr: np.ndarray, seed: int,
         if kind_arr[j] == 0:
             S[j, j] = rng.standard_normal()
             T[j, j] = _tdiag(rng, kind)
+        elif kind_arr[j] == 1 and general:
+            a = rng.standard_normal()
+            b = rng.uniform(0.5, 2.0)
+            c = -rng.uniform(0.5, 2.0)
+            e = rng.uniform(-0.9, 0.9)
+            t11 = _tdiag(rng, kind)
+            t22 = _tdiag(rng, kind)
+            t12 = rng.standard_normal() if rng.random() < 0.5 else 0.0
+            if kind == "general_stress":
+                t12 *= min(t11, t22)
+                f = float(10.0 ** rng.uniform(6.0, 12.0))
+                a, b, c, e = a * f, b * f, c * f, e * f
+            # S_b = T_b M, M = [[a, b], [c, a + e]]
+            S[j, j] = t11 * a + t12 * c
+            S[j, j + 1] = t11 * b + t12 * (a + e)
+            S[j + 1, j] = t22 * c
+            S[j + 1, j + 1] = t22 * (a + e)
+            T[j, j] = t11
+            T[j, j + 1] = t12
+            T[j + 1, j + 1] = t22
         elif kind_arr[j] == 1:
             a = rng.standard_normal()
             b = rng.uniform(0.5, 2.0)
@@ -146,6 +184,37 @@ def schur_pencil(m: int, seed: int, kind: str = "normal", ld: int | None = None,
         with ThreadPoolExecutor(max_workers=int(threads)) as ex:
             list(ex.map(lambda r: fill_columns(S, T, kind_arr, seed, r[0], r[1], kind), ranges))
     return S, T, kind_arr
+
+
+def qz_pencil(m: int, seed: int):
+    """Real generalized Schur form of a seeded dense pencil.
+
+    A and B have N(0, 1) entries from the stream keyed by ``(seed, 0)`` (A first, column
+    by column); ``scipy.linalg.qz(A, B, output="real")`` gives A = Q S Zq^T and
+    B = Q T Zq^T with Q, Zq orthogonal.  Entries below S's first sub-diagonal and below
+    T's diagonal are set to exact zeros (LAPACK leaves them at zero or rounding level).
+    Returns (S, T, blockkind, A, B, Q, Zq), all column-major float64."""
+    import scipy.linalg
+    rng = _stream(seed, 0)
+    A = np.asfortranarray(rng.standard_normal((m, m)).T)
+    B = np.asfortranarray(rng.standard_normal((m, m)).T)
+    if m == 0:
+        e = np.zeros((0, 0), order="F")
+        return e, e.copy(), np.zeros(0, np.int8), A, B, e.copy(), e.copy()
+    S, T, Q, Zq = scipy.linalg.qz(A, B, output="real")
+    S = np.asfortranarray(np.triu(S, -1))
+    T = np.asfortranarray(np.triu(T))
+    kind = np.zeros(m, dtype=np.int8)
+    k = 0
+    while k < m:
+        if k + 1 < m and S[k + 1, k] != 0.0:
+            kind[k], kind[k + 1] = 1, 2
+            k += 2
+        else:
+            if k + 1 < m:
+                S[k + 1, k] = 0.0
+            k += 1
+    return S, T, kind, A, B, np.asfortranarray(Q), np.asfortranarray(Zq)
 
 
 def batch_sizes(count: int = 512, lo: int = 64, hi: int = 2048, seed: int = 3999) -> np.ndarray:
