@@ -117,6 +117,28 @@ int rtgevc(int64_t m, const double *S, int64_t lds, const double *T, int64_t ldt
            const int32_t *select, double *Z, int64_t ldz, int32_t *scales, int32_t *info,
            void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream);
 
+/* Allocation-free variant of rtgevc(), for callers that cannot allocate device memory or
+ * pass a workspace (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  The same computation and results as rtgevc() with the same options (the
+ * band schedule runs on the caller's stream alone, without the look-ahead side stream; the
+ * persistent walker as in rtgevc), but the workspace is a fixed device array inside the
+ * library of RTGEVC_NOALLOC_SCRATCH_BYTES bytes, one per GPU the library runs on, held until
+ * the process ends.  The call allocates and frees nothing, creates no stream or event and
+ * never synchronises; on its first call on a device it looks up that device's address of
+ * the array.
+ *   Arguments as for rtgevc() (argument numbers: 11 = opts, 12 = stream).
+ *   Returns RTGEVC_ERR_SCRATCH, with nothing enqueued, when rtgevc_workspace_size(m, opts)
+ *   exceeds RTGEVC_NOALLOC_SCRATCH_BYTES (with default options FP64 fits up to m = 4096).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (different
+ * streams, or host threads, without ordering between them) race and give wrong results;
+ * order them on one stream.  The array keeps the last call's contents; everything that must
+ * start at zero is cleared by the call's own pre-processing kernels. */
+#define RTGEVC_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define RTGEVC_ERR_SCRATCH (-2000)
+int rtgevc_noalloc(int64_t m, const double *S, int64_t lds, const double *T, int64_t ldt,
+                   const int32_t *select, double *Z, int64_t ldz, int32_t *scales, int32_t *info,
+                   const rtgevc_opts *opts, void *stream);
+
 /* Normalised eigenvalues of (S, T) (Section 2): for each column c, alpha = alpha_re[c]
  * + i alpha_im[c] and beta[c] >= 0, scaled by a power of two so that
  * max(beta, |Re alpha| + |Im alpha|) lies in (1/2, 1]; a complex pair in (p, p+1) has

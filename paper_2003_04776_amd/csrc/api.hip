@@ -402,6 +402,53 @@ hipError_t enqueue_right(int64_t m, const double* S, int64_t lds, const double* 
   return err == hipSuccess ? hipGetLastError() : err;
 }
 
+// ---- the entry point that allocates nothing ----
+// Its workspace is this file-scope device array instead of a caller's buffer.  Host code
+// never passes the array's name to a kernel (on the host the name is only a stand-in):
+// the device address is looked up once per device with hipGetSymbolAddress and kept.
+static __device__ __align__(256) char scratch[RTGEVC_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64];
+
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return err;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (err != hipSuccess) return err;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// The band schedule with every launch on one stream (no side stream, no events): the same
+// launches in the same order as the two-stream look-ahead, so the same eigenvectors.
+hipError_t enqueue_rows_one_stream(const PencilDesc& P, int rows, hipStream_t s) {
+  struct Ops {
+    const PencilDesc& P;
+    hipStream_t s;
+    bool solve(int i, int) {
+      launch_solve(P, i, s);
+      return true;
+    }
+    bool update(int k_lo, int k_hi, int j_lo, int s_lo, int s_hi, int) {
+      launch_update(P, k_lo, k_hi, j_lo, s_lo, s_hi, s);
+      return true;
+    }
+    bool record(int, int) { return true; }
+    bool wait(int, int) { return true; }
+  } ops{P, s};
+  band_schedule(rows, P.band, ops);
+  return hipGetLastError();
+}
+
 // workspace of the left solve beyond the right solve's: S', T' (m^2 doubles each), select'
 size_t left_extra_bytes(int64_t m) {
   return up((size_t)(2 * m * m) * sizeof(double) + (size_t)m * sizeof(int32_t));
@@ -432,6 +479,39 @@ int rtgevc(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt
   PencilDesc P;
   return hip_code(enqueue_right(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts,
                                 static_cast<hipStream_t>(stream), &P));
+}
+
+int rtgevc_noalloc(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt,
+                   const int32_t* select, double* Z, int64_t ldz, int32_t* scales, int32_t* info,
+                   const rtgevc_opts* opts, void* stream) {
+  if (m < 0) return -1;
+  if (m > 0 && !S) return -2;
+  if (lds < (m > 1 ? m : 1)) return -3;
+  if (m > 0 && !T) return -4;
+  if (ldt < (m > 1 ? m : 1)) return -5;
+  if (m > 0 && !Z) return -7;
+  if (ldz < (m > 1 ? m : 1)) return -8;
+  if (!opts_ok(opts)) return -11;
+  if (m == 0) return 0;
+  if (rtgevc_workspace_size(m, opts) > (size_t)RTGEVC_NOALLOC_SCRATCH_BYTES) return RTGEVC_ERR_SCRATCH;
+  void* work = nullptr;
+  hipError_t err = scratch_address(&work);
+  if (err != hipSuccess) return hip_code(err);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (resolve_schedule(m, opts) == 2) {
+    WalkDesc W;
+    PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts, &W);
+    launch_preprocess(P, s);
+    err = launch_walk(P, W, s);
+    launch_consolidate(P, s);
+  } else {
+    PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts);
+    launch_preprocess(P, s);
+    err = enqueue_rows_one_stream(P, P.Mmax, s);
+    launch_consolidate(P, s);
+  }
+  if (err == hipSuccess) err = hipGetLastError();
+  return hip_code(err);
 }
 
 size_t rtgevc_left_workspace_size(int64_t m, const rtgevc_opts* opts) {
@@ -757,6 +837,9 @@ const char* rtgevc_strerror(int code) {
       "argument 14 is invalid (workspace too small?)", "argument 15 is invalid (options or stats?)",
       "argument 16 is invalid"};
   if (code == 0) return "success";
+  if (code == RTGEVC_ERR_SCRATCH)
+    return "the workspace this order and these options need exceeds the fixed scratch of rtgevc_noalloc "
+           "(RTGEVC_NOALLOC_SCRATCH_BYTES); use rtgevc with a workspace";
   if (code <= -1000) return hipGetErrorString(static_cast<hipError_t>(-1000 - code));
   if (code < 0 && code >= -16) return kArg[-code];
   return "invalid argument";

@@ -56,6 +56,8 @@ def load():
     L.rtgevc_workspace_size.argtypes = [i64, op]
     L.rtgevc.restype = ctypes.c_int
     L.rtgevc.argtypes = [i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, vp, sz, op, vp]
+    L.rtgevc_noalloc.restype = ctypes.c_int
+    L.rtgevc_noalloc.argtypes = [i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, op, vp]
     L.rtgevc_eigvals.restype = ctypes.c_int
     L.rtgevc_eigvals.argtypes = [i64, vp, i64, vp, i64, vp, vp, vp, vp, vp, sz, op, vp]
     L.rtgevc_timed.restype = ctypes.c_int
@@ -86,7 +88,10 @@ def load():
 EXPORTED = ("rtgevc_workspace_size", "rtgevc", "rtgevc_eigvals", "rtgevc_timed",
             "rtgevc_batched_workspace_size", "rtgevc_batched", "rtgevc_left_workspace_size", "rtgevc_left",
             "rtgevc_backtransform_workspace_size",
-            "rtgevc_backtransform", "rtgevc_resolve_opts", "rtgevc_strerror", "rtgevc_version")
+            "rtgevc_backtransform", "rtgevc_resolve_opts", "rtgevc_strerror", "rtgevc_version",
+            "rtgevc_noalloc")
+NOALLOC_SCRATCH_BYTES = 64 << 20   # RTGEVC_NOALLOC_SCRATCH_BYTES
+ERR_SCRATCH = -2000                # RTGEVC_ERR_SCRATCH
 TIMED_NSTATS = 12
 
 
@@ -261,6 +266,35 @@ def tgevc(S, T, select=None, normalize: bool = True, mb: int = 0, band: int = 0,
     """All (or the selected) right eigenvectors of the Schur pencil (S, T)."""
     return Solver(S.shape[0], mb=mb, normalize=normalize, band=band, device=S.device,
                   schedule=schedule, precision=precision).run(S, T, select, stream=stream)
+
+
+def tgevc_noalloc(S, T, select=None, normalize: bool = True, mb: int = 0, band: int = 0, stream=None,
+                  schedule: int = 0, precision: int = 0, Z=None, scales=None, info=None) -> Result:
+    """rtgevc_noalloc: the same eigenvectors as tgevc, computed in the library's fixed device
+    scratch (no workspace; torch allocates only the outputs that are not passed in)."""
+    import torch
+    m = int(S.shape[0])
+    dev = S.device
+    lds, ldt = _ld(S, m), _ld(T, m)
+    if Z is None:
+        Z = colmajor_empty(m, dev)
+    ldz = _ld(Z, m)
+    if scales is None:
+        scales = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=dev)
+    sel = None
+    if select is not None:
+        sel = torch.as_tensor(select, dtype=torch.int32, device=dev).contiguous()
+        if sel.shape != (m,):
+            raise ValueError("select must have length m")
+    o = make_opts(mb, normalize, band, schedule, 0, precision)
+    rc = load().rtgevc_noalloc(m, S.data_ptr(), lds, T.data_ptr(), ldt,
+                               sel.data_ptr() if sel is not None else None,
+                               Z.data_ptr(), ldz, scales.data_ptr(), info.data_ptr(),
+                               ctypes.byref(o), _stream_ptr(stream))
+    _check(rc, "rtgevc_noalloc")
+    return Result(Z, scales[:m], info)
 
 
 def _i64_array(vals):

@@ -192,3 +192,31 @@ def test_left_workspace_and_argument_errors():
     assert call(nb=rt.workspace_size(m)) == -12     # enough for rtgevc, not for the left call
     assert call(o=rt.make_opts(mb=96)) == -13
     assert call(m=0) == 0
+
+
+def test_noalloc_argument_errors_and_scratch_limit():
+    """rtgevc_noalloc rejects invalid arguments and orders whose workspace exceeds the
+    fixed scratch before touching the GPU (fake non-null pointers: nothing is read)."""
+    lib = rt.load()
+    o = rt.make_opts()
+
+    def call(m=4, S=1, lds=4, T=1, ldt=4, Z=1, ldz=4, opts=o):
+        return lib.rtgevc_noalloc(m, S, lds, T, ldt, None, Z, ldz, None, None, ctypes.byref(opts), None)
+
+    assert call(m=-1) == -1
+    assert call(S=None) == -2
+    assert call(lds=3) == -3
+    assert call(T=None) == -4
+    assert call(ldt=3) == -5
+    assert call(Z=None) == -7
+    assert call(ldz=3) == -8
+    assert call(opts=rt.make_opts(mb=48)) == -11
+    assert call(m=0, S=None, T=None, Z=None, lds=1, ldt=1, ldz=1) == 0
+    # the largest FP64 order with default options that fits, and the first that does not
+    assert rt.workspace_size(4096) <= rt.NOALLOC_SCRATCH_BYTES < rt.workspace_size(8192)
+    big = 8192
+    assert call(m=big, lds=big, ldt=big, ldz=big) == rt.ERR_SCRATCH
+    assert "scratch" in rt.strerror(rt.ERR_SCRATCH)
+    mixed = rt.make_opts(precision=1)
+    assert rt.workspace_size(4096, precision=1) > rt.NOALLOC_SCRATCH_BYTES
+    assert call(m=4096, lds=4096, ldt=4096, ldz=4096, opts=mixed) == rt.ERR_SCRATCH
