@@ -251,7 +251,7 @@ int rtgevc_batched(int32_t count, const int64_t *m, const double *const *S, cons
                    void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream);
 
 /* The tile size and band a call with these options would use for order m (batched != 0:
- * as a pencil of rtgevc_batched, whose band is always 1).  The automatic choices come
+ * as a pencil of rtgevc_batched: its band is opts->band, or 2 when that is 0).  The automatic choices come
  * from a table compiled into the library, written by an autotuning sweep on the GPU
  * (performance parameters only: every choice computes the same eigenvectors).
  * out receives mb, band and normalize (reserved fields zero).  Returns 0, -1 (m < 0),

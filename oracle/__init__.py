@@ -176,7 +176,7 @@ def tgevc_left(S: np.ndarray, T: np.ndarray, select=None, normalize: bool = True
 
     With J the exchange matrix, (S', T') = (J S^T J, J T^T J) is again a real Schur pencil
     (upper quasi-triangular S', upper triangular T'; the block at (p, p+1) moves to
-    (m-2-p, m-1-p)), and u^H (beta S - alpha T) = 0 holds iff (beta S' - conj(alpha) T')
+    (m-2-p, m-1-p)), and u^H (beta S - alpha T) = 0 holds iff (beta S' - alpha T')
     (J conj(u)) = 0 -- so u is J times the conjugate of a right eigenvector of (S', T'),
     computed by the right-eigenvector oracle.  For a complex pair (p, p+1) of S, column p
     holds Re u and column p+1 Im u of the left eigenvector for alpha_im[p] > 0.  The

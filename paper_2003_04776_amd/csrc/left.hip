@@ -2,7 +2,7 @@
 // eigenvector path on the flipped transposed pencil.  With J the exchange matrix,
 // (S', T') = (J S^T J, J T^T J) is again a real Schur pencil (its 2 x 2 block at
 // (m-2-p, m-1-p) comes from the block of S at (p, p+1)), and u^H (beta S - alpha T) = 0
-// iff (beta S' - conj(alpha) T') (J conj(u)) = 0.  So u = conj(J z') with z' the right
+// iff (beta S' - alpha T') (J conj(u)) = 0.  So u = conj(J z') with z' the right
 // eigenvector of (S', T') for the same eigenvalue: the right solve's output Y' turned by
 // 180 degrees (rows and columns reversed, the scales reversed), and for every complex pair
 // (p, p+1) of S the two columns swapped with the imaginary part negated.  The robust
