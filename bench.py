@@ -266,7 +266,7 @@ def main():
     ap.add_argument("--no-back", dest="back", action="store_false",
                     help="skip the back-transformation X = V Z timed after the eigenvectors")
     ap.add_argument("--seed", type=int, default=400)
-    ap.add_argument("--kind", default="normal", choices=("normal", "stress", "zeroinf", "degenerate"))
+    ap.add_argument("--kind", default="normal", choices=("normal", "stress", "zeroinf", "degenerate", "general", "unbalanced"))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="single", choices=("single", "batched"),

@@ -55,6 +55,8 @@ extern "C" {
 #define RTGEVC_INFO_INDEFINITE     8   /* alpha = beta = 0 in a 1x1 block: e_p returned      */
 #define RTGEVC_INFO_PERTURBED     16   /* a pivot below smin was replaced (assumption 3)     */
 #define RTGEVC_INFO_SELECT_CLOSED 32   /* select was closed under complex conjugation        */
+#define RTGEVC_INFO_REFINE        64   /* mixed precision: a column's backward-error estimate
+                                          is above the threshold after the last sweep         */
 #define RTGEVC_INFO_WATCHDOG     128   /* a dependency wait gave up (results invalid)        */
 #define RTGEVC_INFO_PRESCALED    256   /* S and T were scaled by a common power of two       */
 
@@ -91,7 +93,18 @@ typedef struct rtgevc_opts {
                             per source).  Solves, bounds, scale factors and consolidation
                             stay FP64.  Needs more workspace (slices of every tile pair).
                             Not with schedule 2.                                          */
-  int32_t reserved[2];/* must be zero                                                  */
+  int32_t max_refine; /* mixed precision only: at most this many refinement sweeps against
+                         an FP64 residual (0 = default, 3; -1 = none; else 1..3).  A sweep
+                         estimates for every column still under refinement the componentwise
+                         backward error ||r||_1 / ||beta |S||z| + |alpha||T||z| ||_1 of
+                         r = (beta S - alpha T) z (Section 2) with a 16-row Cauchy sketch
+                         (O(m^2) work), flags the columns above the threshold, forms r in
+                         FP64 for them, solves (beta S - alpha T) d = r with the blocked robust
+                         solver (d = 0 at the tip) and replaces z by z - d (normalising again).
+                         A last estimate sets RTGEVC_INFO_REFINE for columns still above the
+                         threshold.  Needs 8 m^2 more bytes of workspace.                 */
+  int32_t refine_bits;/* threshold of the flag: 2^-refine_bits (1..100); 0 = the residual
+                         bound 64 m 2^-53.                                              */
 } rtgevc_opts;
 
 /* Bytes of device workspace rtgevc() needs for order m with these options
@@ -214,8 +227,9 @@ int rtgevc_backtransform(int64_t m, const double *S, int64_t lds, const double *
  *   [5..8] number of launches of each of those four classes
  *   [9] algorithmic flops of the tile updates, sum over k < r <= j of 4 h_k h_r h_j
  *   [10] number of tiles M;  [11] tile size mb
+ *   [12] device time of the refinement sweeps (mixed precision), ms;  [13] sweeps
  * Returns 0, a negative argument code as rtgevc() (-15: stats), or -1000 - hipError. */
-#define RTGEVC_TIMED_NSTATS 12
+#define RTGEVC_TIMED_NSTATS 14
 int rtgevc_timed(int64_t m, const double *S, int64_t lds, const double *T, int64_t ldt,
                  const int32_t *select, double *Z, int64_t ldz, int32_t *scales, int32_t *info,
                  void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream,
@@ -254,7 +268,8 @@ int rtgevc_batched(int32_t count, const int64_t *m, const double *const *S, cons
  * as a pencil of rtgevc_batched: its band is opts->band, or 2 when that is 0).  The automatic choices come
  * from a table compiled into the library, written by an autotuning sweep on the GPU
  * (performance parameters only: every choice computes the same eigenvectors).
- * out receives mb, band and normalize (reserved fields zero).  Returns 0, -1 (m < 0),
+ * out receives mb, band, schedule, normalize, precision and the refinement sweeps in max_refine
+ * (-1 when none run) and refine_bits as given.  Returns 0, -1 (m < 0),
  * -3 (invalid opts) or -4 (out is NULL).  Host only; touches no GPU. */
 int rtgevc_resolve_opts(int64_t m, int32_t batched, const rtgevc_opts *opts, rtgevc_opts *out);
 

@@ -41,9 +41,10 @@ def lib():
         L = ctypes.CDLL(_SO)
         i64, i32p, dp = ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
         for suf in ("_d", "_ld"):
-            f = getattr(L, "oracle_tgevc" + suf)
-            f.restype = ctypes.c_int
-            f.argtypes = [i64, dp, i64, dp, i64, i32p, dp, i64, i32p, ctypes.c_int, ctypes.c_int]
+            for name in ("oracle_tgevc", "oracle_tgevc_left"):
+                f = getattr(L, name + suf)
+                f.restype = ctypes.c_int
+                f.argtypes = [i64, dp, i64, dp, i64, i32p, dp, i64, i32p, ctypes.c_int, ctypes.c_int]
             f = getattr(L, "oracle_eigvals" + suf)
             f.restype = ctypes.c_int
             f.argtypes = [i64, dp, i64, dp, i64, dp, dp, dp]
@@ -112,9 +113,7 @@ def eigvals(S: np.ndarray, T: np.ndarray, precision: str = "double"):
     return ar[:m], ai[:m], be[:m], int(info)
 
 
-def tgevc(S: np.ndarray, T: np.ndarray, select=None, normalize: bool = True,
-          precision: str = "double", threads: int | None = None):
-    """All (or the selected) right eigenvectors.  Returns (Z, scales, info)."""
+def _call_tgevc(name, S, T, select, normalize, precision, threads):
     m = S.shape[0]
     if threads is None:
         threads = os.cpu_count() or 1
@@ -125,12 +124,18 @@ def tgevc(S: np.ndarray, T: np.ndarray, select=None, normalize: bool = True,
         sel = np.ascontiguousarray(np.asarray(select, dtype=np.int32))
         if sel.shape != (m,):
             raise ValueError("select must have length m")
-    f = lib().oracle_tgevc_d if precision == "double" else lib().oracle_tgevc_ld
+    f = getattr(lib(), name + ("_d" if precision == "double" else "_ld"))
     i32p = ctypes.POINTER(ctypes.c_int32)
     info = f(m, _dp(S), _ld_of(S), _dp(T), _ld_of(T),
              sel.ctypes.data_as(i32p) if sel is not None else None,
              _dp(Z), max(m, 1), scales.ctypes.data_as(i32p), int(bool(normalize)), int(threads))
     return Z, scales[:m], int(info)
+
+
+def tgevc(S: np.ndarray, T: np.ndarray, select=None, normalize: bool = True,
+          precision: str = "double", threads: int | None = None):
+    """All (or the selected) right eigenvectors.  Returns (Z, scales, info)."""
+    return _call_tgevc("oracle_tgevc", S, T, select, normalize, precision, threads)
 
 
 def backtransform(V: np.ndarray, Z: np.ndarray, scales, blk, normalize: bool = True):
@@ -174,15 +179,22 @@ def tgevc_left(S: np.ndarray, T: np.ndarray, select=None, normalize: bool = True
                precision: str = "double", threads: int | None = None):
     """Left eigenvectors u of the Schur pencil: u^H (beta S - alpha T) = 0.
 
-    With J the exchange matrix, (S', T') = (J S^T J, J T^T J) is again a real Schur pencil
-    (upper quasi-triangular S', upper triangular T'; the block at (p, p+1) moves to
-    (m-2-p, m-1-p)), and u^H (beta S - alpha T) = 0 holds iff (beta S' - alpha T')
-    (J conj(u)) = 0 -- so u is J times the conjugate of a right eigenvector of (S', T'),
-    computed by the right-eigenvector oracle.  For a complex pair (p, p+1) of S, column p
-    holds Re u and column p+1 Im u of the left eigenvector for alpha_im[p] > 0.  The
-    robustness bounds of the right solve on (S', T') are those of the left solve on (S, T)
-    (its infinity norms are the 1-norms of S and T, as the conclusion, Section 7, asks of a
-    left solve).  Returns (Y, scales, info) like tgevc."""
+    Computed directly (oracle_impl.h, oracle_tgevc_left): with w = conj(u), w^T C = 0 for
+    C = beta S - alpha T is a forward substitution from the eigenvalue's own block down,
+    each block row's update protected with its 1-norm (the conclusion, Section 7, names
+    left eigenvectors as the same computation with the 1-norm).  Phase: u_p = 1 at the
+    first row of the eigenvalue's block.  For a complex pair (p, p+1), column p holds Re u
+    and column p+1 Im u of the left eigenvector for alpha_im[p] > 0.  Returns
+    (Y, scales, info) like tgevc."""
+    return _call_tgevc("oracle_tgevc_left", S, T, select, normalize, precision, threads)
+
+
+def tgevc_left_flip(S: np.ndarray, T: np.ndarray, select=None, normalize: bool = True,
+                    precision: str = "double", threads: int | None = None):
+    """The left eigenvectors by a second route, for cross-checking tgevc_left: with J the
+    exchange matrix, (S', T') = (J S^T J, J T^T J) is again a real Schur pencil, and
+    u^H (beta S - alpha T) = 0 holds iff (beta S' - alpha T') (J conj(u)) = 0, so u is J times
+    the conjugate of a right eigenvector of (S', T') (the right oracle).  Same layout."""
     m = S.shape[0]
     Sf = np.array(S.T[::-1, ::-1], order="F")   # (copies with positive strides)
     Tf = np.array(T.T[::-1, ::-1], order="F")

@@ -249,11 +249,11 @@ static R FN(block_smin)(const FN(pencil_t) *P, int64_t r0, int nb, R a, R b, R b
 }
 
 /* Solve the 1x1 or 2x2 system C w = y in rows r0..r0+nb-1 of the working vector,
- * where C = beta S_qq - alpha T_qq, writing w over y.  Every division and update
- * is protected; the scaling exponents are added to *k and applied to the whole
- * working vector (length n).  Returns info bits. */
-static int FN(diag_solve)(const FN(pencil_t) *P, int64_t r0, int nb, R a, R b, R be,
-                          int cplx, R *wr, R *wi, int64_t n, int64_t *k)
+ * where C = beta S_qq - alpha T_qq (trans = 1: C^T w = y, for the left eigenvectors),
+ * writing w over y.  Every division and update is protected; the scaling exponents are
+ * added to *k and applied to the whole working vector (length n).  Returns info bits. */
+static int FN(diag_solve_t)(const FN(pencil_t) *P, int64_t r0, int nb, R a, R b, R be,
+                            int cplx, R *wr, R *wi, int64_t n, int64_t *k, int trans)
 {
 #define SS(i, j) ((R)P->S[(i) + (j) * P->lds])
 #define TT(i, j) ((R)P->T[(i) + (j) * P->ldt])
@@ -282,8 +282,9 @@ static int FN(diag_solve)(const FN(pencil_t) *P, int64_t r0, int nb, R a, R b, R
     R cr[2][2], ci[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) {
-            R s = SS(r0 + i, r0 + j);
-            R t = (i > j) ? 0 : TT(r0 + i, r0 + j);
+            int ii = trans ? j : i, jj = trans ? i : j;   /* entry (i, j) of C or of C^T */
+            R s = SS(r0 + ii, r0 + jj);
+            R t = (ii > jj) ? 0 : TT(r0 + ii, r0 + jj);
             cr[i][j] = be * s - a * t;
             ci[i][j] = cplx ? -b * t : 0;
         }
@@ -359,6 +360,12 @@ static int FN(diag_solve)(const FN(pencil_t) *P, int64_t r0, int nb, R a, R b, R
     return info;
 #undef SS
 #undef TT
+}
+
+static int FN(diag_solve)(const FN(pencil_t) *P, int64_t r0, int nb, R a, R b, R be,
+                          int cplx, R *wr, R *wi, int64_t n, int64_t *k)
+{
+    return FN(diag_solve_t)(P, r0, nb, a, b, be, cplx, wr, wi, n, k, 0);
 }
 
 /* y[0:r0] -= (beta S[0:r0, cols] - alpha T[0:r0, cols]) w[cols], cols = r0..r0+nb-1,
@@ -526,6 +533,172 @@ int FN(oracle_tgevc)(int64_t m, const double *S, int64_t lds, const double *T, i
                 scales[p] = (int32_t)k;
                 if (cplx) scales[p + 1] = (int32_t)k;
             }
+        }
+        free(wr);
+        free(wi);
+    }
+    info |= tinfo;
+    if (select)
+        for (int64_t c = 0; c + 1 < m; ++c)
+            if (blk[c] == 1 && ((select[c] != 0) != (select[c + 1] != 0))) info |= 32;
+    free(starts);
+    free(blk);
+    return info;
+}
+
+/* ------------------------------------------- left eigenvectors (Section 7) -- */
+
+/* The left eigenvector u of eigenvalue (alpha, beta): u^H (beta S - alpha T) = 0.  With
+ * w = conj(u) this is w^T C = 0, C = beta S - alpha T: a forward substitution over the
+ * blocks from the eigenvalue's own block down, row-oriented where the right vectors are
+ * column-oriented.  After block q is solved, the columns after it take the update
+ *     y[cols after q] -= C[rows of q, cols after q]^T w_q,
+ * whose protection needs the 1-norm of that block row (its largest column sum): the
+ * conclusion's remark that left eigenvectors are the same computation with the 1-norm in
+ * place of the infinity norm.  Diagonal blocks are solved transposed, C_qq^T w_q = y_q. */
+
+/* y[r0+nb : n) -= C[r0 .. r0+nb-1, r0+nb : n)^T w[r0 .. r0+nb-1], protected by
+ * ProtectUpdate with the exact 1-norm of the block row. */
+static void FN(update_below)(const FN(pencil_t) *P, int64_t r0, int nb, R a, R b, R be,
+                             int cplx, R *wr, R *wi, int64_t n, int64_t *k)
+{
+    int64_t c0 = r0 + nb;
+    if (c0 >= n) return;
+    const double *S = P->S, *T = P->T;
+    int64_t lds = P->lds, ldt = P->ldt;
+    R aabs = FABS(a) + FABS(b);
+    R cn = 0;                     /* max over the columns after the block of its column sum */
+    for (int64_t c = c0; c < n; ++c) {
+        R s = 0;
+        for (int l = 0; l < nb; ++l)
+            s += be * FABS((R)S[(r0 + l) + c * lds]) + aabs * FABS((R)T[(r0 + l) + c * ldt]);
+        if (s > cn) cn = s;
+    }
+    R wn = 0, yn = 0;
+    for (int l = 0; l < nb; ++l) {
+        R v = FN(cabs1)(wr[r0 + l], cplx ? wi[r0 + l] : 0);
+        if (v > wn) wn = v;
+    }
+    for (int64_t c = c0; c < n; ++c) {
+        R v = FN(cabs1)(wr[c], cplx ? wi[c] : 0);
+        if (v > yn) yn = v;
+    }
+    int q = FN(oracle_pu)(cn, wn, yn);
+    if (q) { FN(scale_all)(wr, wi, n, q, cplx); *k += q; }
+    for (int l = 0; l < nb; ++l) {
+        int64_t r = r0 + l;
+        R xr = wr[r], xi = cplx ? wi[r] : 0;
+        R ur = be * xr, ui = be * xi;                                  /* beta w */
+        R vr = a * xr - b * xi, vi = b * xr + a * xi;                  /* alpha w */
+        for (int64_t c = c0; c < n; ++c) {
+            R s = (R)S[r + c * lds], t = (R)T[r + c * ldt];
+            wr[c] -= s * ur - t * vr;
+            if (cplx) wi[c] -= s * ui - t * vi;
+        }
+    }
+}
+
+/* w = conj(u) for the block starting at p; w[p .. m) holds the mantissa, *k the exponent.
+ * Phase: w_p = 1 (for a pair, w_{p+1} from the first column of the singular block). */
+static int FN(left_eigvec)(const FN(pencil_t) *P, int64_t p, R *wr, R *wi, int64_t *kout)
+{
+    const double *S = P->S, *T = P->T;
+    int64_t lds = P->lds, ldt = P->ldt, m = P->m;
+    const int8_t *blk = P->blk;
+    int info = 0;
+    R a, b, be;
+    info |= FN(block_eig)(p, blk[p], S, lds, T, ldt, &a, &b, &be);
+    int cplx = (blk[p] == 1);
+    int nbp = cplx ? 2 : 1;
+    int64_t k = 0;
+    for (int64_t i = 0; i < m; ++i) { wr[i] = 0; wi[i] = 0; }
+    if (info & 8) {
+        wr[p] = 1;
+        *kout = 0;
+        return info;
+    }
+    if (!cplx) {
+        wr[p] = 1;
+    } else {
+        /* first column of M = beta S_b - alpha T_b: w_p M11 + w_{p+1} M21 = 0, w_p = 1 */
+        R m21 = be * (R)S[p + 1 + p * lds];
+        R m11r = be * (R)S[p + p * lds] - a * (R)T[p + p * ldt];
+        R m11i = -b * (R)T[p + p * ldt];
+        R nr = -m11r, ni = -m11i;
+        R smin = FN(block_smin)(P, p, 2, a, b, be);
+        if (FABS(m21) < smin) { m21 = smin; info |= 16; }
+        int q = FN(oracle_pd)(FN(cabs1)(nr, ni), FABS(m21));
+        R one = 1;
+        if (q) { one = LDEXP(one, -q); nr = LDEXP(nr, -q); ni = LDEXP(ni, -q); k += q; }
+        wr[p] = one; wi[p] = 0;
+        wr[p + 1] = nr / m21; wi[p + 1] = ni / m21;
+    }
+    FN(update_below)(P, p, nbp, a, b, be, cplx, wr, wi, m, &k);
+    int64_t r = p + nbp;
+    while (r < m) {
+        int nb = (blk[r] == 1) ? 2 : 1;
+        info |= FN(diag_solve_t)(P, r, nb, a, b, be, cplx, wr, wi, m, &k, 1);
+        FN(update_below)(P, r, nb, a, b, be, cplx, wr, wi, m, &k);
+        r += nb;
+    }
+    *kout = k;
+    return info;
+}
+
+/* All selected left eigenvectors, in the layout of oracle_tgevc: column c of a real
+ * eigenvalue holds u; for a pair (p, p+1), column p holds Re u and column p+1 Im u of the
+ * left eigenvector of the eigenvalue with positive imaginary part (u = conj(w)).
+ * normalize = 1: u / max_i (|Re u_i| + |Im u_i|), scales 0; else mantissa and exponent. */
+int FN(oracle_tgevc_left)(int64_t m, const double *S, int64_t lds, const double *T, int64_t ldt,
+                          const int32_t *select, double *Z, int64_t ldz, int32_t *scales,
+                          int normalize, int nthreads)
+{
+    if (m <= 0) return 0;
+    int8_t *blk = (int8_t *)malloc((size_t)m);
+    int info = FN(oracle_blocks)(m, S, lds, blk);
+    FN(pencil_t) P;
+    P.m = m; P.S = S; P.T = T; P.lds = lds; P.ldt = ldt; P.blk = blk;
+    int64_t *starts = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    int64_t nstart = 0;
+    for (int64_t c = 0; c < m; ++c) {
+        if (blk[c] == 2) continue;
+        int want = 1;
+        if (select) {
+            want = select[c] != 0;
+            if (blk[c] == 1 && select[c + 1] != 0) want = 1;
+        }
+        if (want) starts[nstart++] = c;
+    }
+    for (int64_t c = 0; c < m; ++c) {
+        for (int64_t i = 0; i < m; ++i) Z[i + c * ldz] = 0;
+        scales[c] = 0;
+    }
+    int tinfo = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1) reduction(| : tinfo)
+    {
+        R *wr = (R *)malloc(sizeof(R) * (size_t)(m + 2));
+        R *wi = (R *)malloc(sizeof(R) * (size_t)(m + 2));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t s = 0; s < nstart; ++s) {
+            int64_t p = starts[s];
+            int64_t k = 0;
+            tinfo |= FN(left_eigvec)(&P, p, wr, wi, &k);
+            int cplx = blk[p] == 1;
+            R nrm = 1;
+            if (normalize) {
+                nrm = 0;
+                for (int64_t i = p; i < m; ++i) {
+                    R v = FABS(wr[i]) + (cplx ? FABS(wi[i]) : 0);
+                    if (v > nrm) nrm = v;
+                }
+                if (nrm == 0) nrm = 1;
+            }
+            for (int64_t i = p; i < m; ++i) {
+                Z[i + p * ldz] = (double)(wr[i] / nrm);
+                if (cplx) Z[i + (p + 1) * ldz] = (double)(-wi[i] / nrm);   /* u = conj(w) */
+            }
+            scales[p] = normalize ? 0 : (int32_t)k;
+            if (cplx) scales[p + 1] = scales[p];
         }
         free(wr);
         free(wi);

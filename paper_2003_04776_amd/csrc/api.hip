@@ -37,6 +37,10 @@ void launch_left_flip(int64_t m, const double* A, int64_t lda, double* B, hipStr
 void launch_left_select(int64_t m, const int32_t* sel, int32_t* out, hipStream_t s);
 void launch_left_finish(int64_t m, const int8_t* blkp, double* Y, int64_t ldy, int32_t* scales, hipStream_t s);
 hipError_t launch_walk(const PencilDesc& P, const WalkDesc& W, hipStream_t s);
+void launch_refine_setup(const PencilDesc& P, const RefineDesc& R, hipStream_t s);
+void launch_refine_estimate(const PencilDesc& P, const RefineDesc& R, int pass, bool final_pass, hipStream_t s);
+void launch_refine_residual(const PencilDesc& P, const RefineDesc& R, hipStream_t s);
+void launch_refine_apply(const PencilDesc& P, const RefineDesc& R, hipStream_t s);
 }  // namespace rgev
 
 using namespace rgev;
@@ -85,9 +89,22 @@ bool opts_ok(const rtgevc_opts* o) {
   if (o->watchdog < 0) return false;
   if (o->precision < 0 || o->precision > 1) return false;
   if (o->precision == 1 && o->schedule == 2) return false;   // the walker runs FP64 updates
-  for (int i = 0; i < 2; ++i)
-    if (o->reserved[i] != 0) return false;
+  if (o->max_refine < -1 || o->max_refine > 3) return false;
+  if (o->refine_bits < 0 || o->refine_bits > 100) return false;
   return true;
+}
+
+// refinement sweeps of a call: mixed precision only; max_refine 0 = 3, -1 = none
+int resolve_sweeps(const rtgevc_opts* o) {
+  if (!o || o->precision != 1) return 0;
+  if (o->max_refine < 0) return 0;
+  return o->max_refine == 0 ? 3 : o->max_refine;
+}
+
+// flag threshold: 2^-refine_bits, or by default the residual bound 64 m 2^-53
+double resolve_tau(int64_t m, const rtgevc_opts* o) {
+  if (o && o->refine_bits > 0) return ldexp(1.0, -o->refine_bits);
+  return 64.0 * (double)m * 1.1102230246251565e-16;
 }
 
 int resolve_precision(const rtgevc_opts* o) { return (o && o->precision == 1) ? 1 : 0; }
@@ -113,7 +130,7 @@ struct Carve {
 // Lays out the workspace; with base == nullptr it only measures.  W keeps 2 band source
 // rows (band wavefront) or, with walk != nullptr, every source row (persistent walker).
 __host__ __device__ size_t carve(PencilDesc& P, char* base, int64_t m, int mb, int band, WalkDesc* walk = nullptr,
-                                 int precision = 0) {
+                                 int precision = 0, RefineDesc* ref = nullptr) {
   const int Mmax = tile_bound(m, mb);
   const int wslots = walk ? Mmax : 2 * band;
   Carve c;
@@ -144,8 +161,24 @@ __host__ __device__ size_t carve(PencilDesc& P, char* base, int64_t m, int mb, i
     P.Aexp = c.take<int32_t>(base, pairs * mb);
     P.Wslc = c.take<int4>(base, (size_t)wslots * Mmax * kSlices * slice_packets(mb));
     P.Wexp = c.take<int32_t>(base, (size_t)wslots * m);
+    P.stmax = c.take<unsigned long long>(base, (size_t)2 * Mmax);
     P.exps_next = c.take<int32_t>(base, (size_t)Mmax * m);
     P.norms_next = c.take<unsigned long long>(base, (size_t)Mmax * m);
+  }
+  if (ref) {
+    ref->G = c.take<double>(base, (size_t)m * kSketch);
+    ref->GS = c.take<double>(base, (size_t)m * kSketch);
+    ref->GT = c.take<double>(base, (size_t)m * kSketch);
+    ref->cS = c.take<double>(base, m);
+    ref->cT = c.take<double>(base, m);
+    ref->PS = c.take<double>(base, (size_t)m * kSketch);
+    ref->PT = c.take<double>(base, (size_t)m * kSketch);
+    ref->dS = c.take<double>(base, m);
+    ref->dT = c.take<double>(base, m);
+    ref->zexp = c.take<int32_t>(base, m);
+    ref->rf = c.take<int8_t>(base, m);
+    ref->tflag = c.take<int32_t>(base, Mmax);
+    ref->Zc = c.take<double>(base, (size_t)m * m);
   }
   if (walk) {
     walk->cnt = c.take<int32_t>(base, (size_t)Mmax * Mmax);
@@ -337,7 +370,7 @@ int check_common(int64_t m, const double* S, int64_t lds, const double* T, int64
 
 PencilDesc make_desc(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt,
                      const int32_t* select, double* Z, int64_t ldz, int32_t* scales, int32_t* info,
-                     void* work, const rtgevc_opts* opts, WalkDesc* walk = nullptr) {
+                     void* work, const rtgevc_opts* opts, WalkDesc* walk = nullptr, RefineDesc* ref = nullptr) {
   PencilDesc P;
   memset(&P, 0, sizeof(P));
   P.m = m;
@@ -349,7 +382,9 @@ PencilDesc make_desc(int64_t m, const double* S, int64_t lds, const double* T, i
   P.Z = Z;
   P.scales = scales;
   P.select = select;
-  carve(P, static_cast<char*>(work), m, resolve_mb(m, opts), resolve_band(m, opts), walk, resolve_precision(opts));
+  carve(P, static_cast<char*>(work), m, resolve_mb(m, opts), resolve_band(m, opts), walk, resolve_precision(opts),
+        resolve_sweeps(opts) > 0 ? ref : nullptr);
+  if (ref) ref->tau = resolve_tau(m, opts);
   P.info = info ? info : &P.ctrl->info_local;
   P.normalize = opts ? opts->normalize : 1;
   if (walk) walk->spin_limit = (opts && opts->watchdog > 0) ? opts->watchdog : kDefaultSpinLimit;
@@ -376,11 +411,59 @@ size_t back_carve(BackDesc& B, char* base, int64_t m, int mb) {
   return c.off;
 }
 
-// The right-eigenvector path on one stream (rtgevc after its argument checks); *out gets
-// the pencil descriptor (its block structure stays valid in the workspace).
+// The band schedule with every launch on one stream (no side stream, no events): the same
+// launches in the same order as the two-stream look-ahead, so the same eigenvectors.
+hipError_t enqueue_rows_one_stream(const PencilDesc& P, int rows, hipStream_t s) {
+  struct Ops {
+    const PencilDesc& P;
+    hipStream_t s;
+    bool solve(int i, int) {
+      launch_solve(P, i, s);
+      return true;
+    }
+    bool update(int k_lo, int k_hi, int j_lo, int s_lo, int s_hi, int) {
+      launch_update(P, k_lo, k_hi, j_lo, s_lo, s_hi, s);
+      return true;
+    }
+    bool record(int, int) { return true; }
+    bool wait(int, int) { return true; }
+  } ops{P, s};
+  band_schedule(rows, P.band, ops);
+  return hipGetLastError();
+}
+
+// Refinement sweeps of a mixed-precision result (refine.hip): estimate and flag, FP64
+// residual of the flagged columns, correction solve through the blocked solver in
+// correction mode (rows(C) enqueues it), z <- z - d; a last estimate reports the columns
+// still above the threshold (info bit 64).
+template <class Rows>
+hipError_t enqueue_refine(const PencilDesc& P, const RefineDesc& R, int sweeps, hipStream_t s, Rows&& rows) {
+  launch_refine_setup(P, R, s);
+  PencilDesc C = P;
+  C.Z = R.Zc;
+  C.ldz = P.m;
+  C.sel = R.rf;
+  C.rhs = 1;
+  C.tflag = R.tflag;
+  C.scales = nullptr;
+  hipError_t err = hipSuccess;
+  for (int sw = 0; sw < sweeps && err == hipSuccess; ++sw) {
+    launch_refine_estimate(P, R, sw, false, s);
+    launch_refine_residual(P, R, s);
+    err = rows(C);
+    launch_refine_apply(P, R, s);
+  }
+  launch_refine_estimate(P, R, sweeps, true, s);
+  return err == hipSuccess ? hipGetLastError() : err;
+}
+
+// The right-eigenvector path (rtgevc after its argument checks); *out gets the pencil
+// descriptor (its block structure stays valid in the workspace).  one_stream: the band
+// schedule without the side stream (no stream or event is created).
 hipError_t enqueue_right(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt,
                          const int32_t* select, double* Z, int64_t ldz, int32_t* scales, int32_t* info,
-                         void* work, const rtgevc_opts* opts, hipStream_t s, PencilDesc* out) {
+                         void* work, const rtgevc_opts* opts, hipStream_t s, PencilDesc* out,
+                         bool one_stream = false) {
   if (resolve_schedule(m, opts) == 2) {
     WalkDesc W;
     PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts, &W);
@@ -390,8 +473,18 @@ hipError_t enqueue_right(int64_t m, const double* S, int64_t lds, const double* 
     launch_consolidate(P, s);
     return err == hipSuccess ? hipGetLastError() : err;
   }
-  PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts);
+  RefineDesc R;
+  PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts, nullptr, &R);
   *out = P;
+  const int sweeps = resolve_sweeps(opts);
+  if (one_stream) {
+    launch_preprocess(P, s);
+    hipError_t err = enqueue_rows_one_stream(P, P.Mmax, s);
+    launch_consolidate(P, s);
+    if (err == hipSuccess && sweeps > 0)
+      err = enqueue_refine(P, R, sweeps, s, [&](const PencilDesc& C) { return enqueue_rows_one_stream(C, C.Mmax, s); });
+    return err == hipSuccess ? hipGetLastError() : err;
+  }
   std::lock_guard<std::mutex> lock(g_aux_mu);
   Aux* ax = nullptr;
   hipError_t err = get_aux(&ax);
@@ -399,6 +492,10 @@ hipError_t enqueue_right(int64_t m, const double* S, int64_t lds, const double* 
   launch_preprocess(P, s);
   err = enqueue_rows(P, P.Mmax, s, *ax, [](int, bool, hipStream_t) {});
   launch_consolidate(P, s);
+  if (err == hipSuccess && sweeps > 0)
+    err = enqueue_refine(P, R, sweeps, s, [&](const PencilDesc& C) {
+      return enqueue_rows(C, C.Mmax, s, *ax, [](int, bool, hipStream_t) {});
+    });
   return err == hipSuccess ? hipGetLastError() : err;
 }
 
@@ -428,26 +525,6 @@ hipError_t scratch_address(void** out) {
   return hipSuccess;
 }
 
-// The band schedule with every launch on one stream (no side stream, no events): the same
-// launches in the same order as the two-stream look-ahead, so the same eigenvectors.
-hipError_t enqueue_rows_one_stream(const PencilDesc& P, int rows, hipStream_t s) {
-  struct Ops {
-    const PencilDesc& P;
-    hipStream_t s;
-    bool solve(int i, int) {
-      launch_solve(P, i, s);
-      return true;
-    }
-    bool update(int k_lo, int k_hi, int j_lo, int s_lo, int s_hi, int) {
-      launch_update(P, k_lo, k_hi, j_lo, s_lo, s_hi, s);
-      return true;
-    }
-    bool record(int, int) { return true; }
-    bool wait(int, int) { return true; }
-  } ops{P, s};
-  band_schedule(rows, P.band, ops);
-  return hipGetLastError();
-}
 
 // workspace of the left solve beyond the right solve's: S', T' (m^2 doubles each), select'
 size_t left_extra_bytes(int64_t m) {
@@ -464,8 +541,10 @@ size_t rtgevc_workspace_size(int64_t m, const rtgevc_opts* opts) {
   PencilDesc P;
   memset(&P, 0, sizeof(P));
   WalkDesc W;
+  RefineDesc R;
   return carve(P, nullptr, m, resolve_mb(m, opts), resolve_band(m, opts),
-               resolve_schedule(m, opts) == 2 ? &W : nullptr, resolve_precision(opts));
+               resolve_schedule(m, opts) == 2 ? &W : nullptr, resolve_precision(opts),
+               resolve_sweeps(opts) > 0 ? &R : nullptr);
 }
 
 int rtgevc(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt, const int32_t* select,
@@ -497,21 +576,9 @@ int rtgevc_noalloc(int64_t m, const double* S, int64_t lds, const double* T, int
   void* work = nullptr;
   hipError_t err = scratch_address(&work);
   if (err != hipSuccess) return hip_code(err);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  if (resolve_schedule(m, opts) == 2) {
-    WalkDesc W;
-    PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts, &W);
-    launch_preprocess(P, s);
-    err = launch_walk(P, W, s);
-    launch_consolidate(P, s);
-  } else {
-    PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts);
-    launch_preprocess(P, s);
-    err = enqueue_rows_one_stream(P, P.Mmax, s);
-    launch_consolidate(P, s);
-  }
-  if (err == hipSuccess) err = hipGetLastError();
-  return hip_code(err);
+  PencilDesc P;
+  return hip_code(enqueue_right(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts,
+                                static_cast<hipStream_t>(stream), &P, /*one_stream=*/true));
 }
 
 size_t rtgevc_left_workspace_size(int64_t m, const rtgevc_opts* opts) {
@@ -623,7 +690,10 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool walker = resolve_schedule(m, opts) == 2;
   WalkDesc W;
-  PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts, walker ? &W : nullptr);
+  RefineDesc R;
+  PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts, walker ? &W : nullptr,
+                           walker ? nullptr : &R);
+  const int sweeps = walker ? 0 : resolve_sweeps(opts);
   // events bracket every launch on the stream it runs on
   const int nev = 2 * (3 * P.Mmax + 8);
   std::lock_guard<std::mutex> lock(g_event_mu);
@@ -672,6 +742,16 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
   launch_consolidate(P, s);
   mark();
   spans[nsp++] = Span{3, c0, c0 + 1};
+  if (err == hipSuccess && sweeps > 0) {
+    // the refinement is one span (its correction solves' launches are not marked)
+    const int f0 = used;
+    mark();
+    err = enqueue_refine(P, R, sweeps, s, [&](const PencilDesc& C) {
+      return enqueue_rows(C, M, s, *ax, [](int, bool, hipStream_t) {});
+    });
+    mark();
+    spans[nsp++] = Span{4, f0, f0 + 1};
+  }
   if (err == hipSuccess) err = hipGetLastError();
   if (err == hipSuccess) err = hipStreamSynchronize(s);
   int32_t* edges = new int32_t[M + 1];
@@ -682,9 +762,14 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
     stats[0] = ms;
     for (int i = 0; i < nsp && err == hipSuccess; ++i) {
       err = hipEventElapsedTime(&ms, ev[spans[i].e0], ev[spans[i].e1]);
+      if (spans[i].cls == 4) {
+        stats[12] += ms;
+        continue;
+      }
       stats[1 + spans[i].cls] += ms;
       stats[5 + spans[i].cls] += 1.0;
     }
+    stats[13] = sweeps;
     // algorithmic flops of the tile updates: sum over k < r <= j of 2 h_k (2 h_r) h_j
     double fl = 0.0;
     for (int r = M - 1; r >= 1; --r) {
@@ -822,6 +907,9 @@ int rtgevc_resolve_opts(int64_t m, int32_t batched, const rtgevc_opts* opts, rtg
     out->schedule = resolve_schedule(m, opts);
   }
   out->precision = opts ? opts->precision : 0;
+  const int sweeps = batched ? 0 : resolve_sweeps(opts);
+  out->max_refine = sweeps > 0 ? sweeps : -1;
+  out->refine_bits = opts ? opts->refine_bits : 0;
   return 0;
 }
 

@@ -66,15 +66,22 @@ struct PencilDesc {
   Ctrl* ctrl;
   // mixed precision (split operands for the int8 matrix instruction, see slices.hpp)
   int4* Aslc;         // slices of every super-diagonal tile pair [S_kr | T_kr]
-  int32_t* Aexp;      // [pair][MB] row exponents of those tiles
+  int32_t* Aexp;      // [pair][MB] row exponents of those tiles (S half; T half + D_r)
   int4* Wslc;         // slices of W per source-row slot and tile column
-  int32_t* Wexp;      // [slot][m] column exponents of W
+  int32_t* Wexp;      // [slot][m] column exponents of W (X D half; -X B half - D_r)
+  unsigned long long* stmax;   // [2][Mmax] largest |S| and |T| (bits, >= 0) in the columns of
+                               // tile r above its diagonal tile: D_r from their exponents
   // the new segment exponents and norms of a mixed-precision update launch whose tiles are
   // split over several workgroups (row groups): norms combined by an atomic maximum on the
   // bits of the non-negative doubles, published into exps/norms (and cleared) once the
   // launch is done, so that no workgroup reads a segment another one has already rewritten
   int32_t* exps_next;            // [Mmax * m]
   unsigned long long* norms_next; // [Mmax * m], zero between launches
+  // refinement of the mixed-precision result: in correction mode (rhs = 1) the tile rows of
+  // Z hold a right-hand side (the residual) instead of starting at zero, the tip block's
+  // correction is zero, and only tile columns j with tflag[j] != 0 are solved and updated
+  int32_t* tflag;     // [Mmax], read in correction mode only
+  int32_t rhs;
   int32_t mb;
   int32_t Mmax;
   int32_t normalize;
@@ -84,6 +91,31 @@ struct PencilDesc {
 };
 
 constexpr int kMaxBand = 8;
+
+// Refinement of the mixed-precision result against an FP64 residual.  A sketch with
+// kSketch Cauchy rows G estimates the 1-norm of each column's residual r = (beta S - alpha T) z
+// (the median of |g_t . r| over the rows is a consistent estimate of ||r||_1 for Cauchy g);
+// the column is flagged when that estimate exceeds tau times the exact
+// || beta |S| |z| + |alpha| |T| |z| ||_1 (a componentwise backward error, at the level of u for an
+// FP64 substitution); flagged columns get r in FP64 and a correction solve.
+constexpr int kSketch = 16;
+
+struct RefineDesc {
+  double* G;          // [m][kSketch] sketch rows, row-major by matrix row
+  double* GS;         // [m][kSketch] sk * psc * (G S)^T: entry (j, t) = sum_i G(i, t) S(i, j)
+  double* GT;         // [m][kSketch] the same for T
+  double* cS;         // [m] sk * psc * column sums of |S| (and |T|)
+  double* cT;
+  double* PS;         // [m][kSketch] projections G S z'_c, G T z'_c of each column of Z
+  double* PT;
+  double* dS;         // [m] cS . |z'_c| and cT . |z'_c|
+  double* dT;
+  int32_t* zexp;      // [m] z'_c = 2^-zexp[c] z_c (common to the two columns of a pair)
+  int8_t* rf;         // [m] flagged by the latest pass
+  int32_t* tflag;     // [Mmax] tile column holds a flagged column
+  double* Zc;         // [m * m] residual in, correction out (leading dimension m)
+  double tau;         // flag threshold on the backward-error estimate
+};
 
 // Work list and dependency counters of the persistent walker (schedule 2).
 struct WalkDesc {

@@ -19,6 +19,8 @@ __device__ __forceinline__ void pre_reset_body(const PencilDesc& P) {
     P.ctrl->numax_bits = 0;
     P.ctrl->psc = 1.0;
   }
+  if (P.precision == 1 && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < 2 * P.Mmax; i += blockDim.x) P.stmax[i] = 0ull;
 }
 
 __device__ __forceinline__ void pre_structure_body(const PencilDesc& P) {
@@ -160,6 +162,7 @@ __device__ __forceinline__ void pre_norms_body(const PencilDesc& P) {
     const int nrg = (hk + 63) / 64 * 64;   // rows padded to whole waves
     const int groups = kNormThreads / 64;
     double best = 0.0;
+    double smx = 0.0, tmx = 0.0;   // largest |S| and |T| of the pair (mixed precision: D_r)
     int nonfinite = 0;
     // each thread owns rows i = tid % 64 + 64 * u and columns l = group, group + groups, ...
     const int lane = threadIdx.x % 64, grp = threadIdx.x / 64;
@@ -171,6 +174,8 @@ __device__ __forceinline__ void pre_norms_body(const PencilDesc& P) {
           const double sv = S[(k0 + i) + (int64_t)(c0 + l) * lds];
           const double tv = T[(k0 + i) + (int64_t)(c0 + l) * ldt];
           s += fabs(sv) * sc + fabs(tv) * sc;
+          smx = fmax(smx, fabs(sv) * sc);
+          tmx = fmax(tmx, fabs(tv) * sc);
           nonfinite |= !(isfinite(sv) && isfinite(tv));
         }
       }
@@ -184,6 +189,16 @@ __device__ __forceinline__ void pre_norms_body(const PencilDesc& P) {
       __syncthreads();
     }
     if (nonfinite) atomicOr(&bad, 1);
+    if (P.precision == 1) {
+      for (int off = 32; off > 0; off >>= 1) {
+        smx = fmax(smx, __shfl_xor(smx, off));
+        tmx = fmax(tmx, __shfl_xor(tmx, off));
+      }
+      if (lane == 0) {
+        if (isfinite(smx)) atomicMax(&P.stmax[r], (unsigned long long)__double_as_longlong(smx));
+        if (isfinite(tmx)) atomicMax(&P.stmax[P.Mmax + r], (unsigned long long)__double_as_longlong(tmx));
+      }
+    }
     // reduce best over the first wave
     if (grp == 0) {
       for (int off = 32; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off));
@@ -279,7 +294,7 @@ template <int MB>
 __device__ __forceinline__ void pre_slices_tile(const PencilDesc& P, int k, int r) {
   constexpr int HK = slice_half_k(MB), KS = slice_ksteps(MB), RBN = MB / 16;
   __shared__ int rowexp[MB];
-  __shared__ double rowmax[kSliceThreads / MB > 0 ? kSliceThreads / MB : 1][MB];
+  __shared__ double rowmax[2][kSliceThreads / MB > 0 ? kSliceThreads / MB : 1][MB];
   const int k0 = P.edges[k], hk = P.edges[k + 1] - k0;
   const int c0 = P.edges[r], hc = P.edges[r + 1] - c0;
   const double psc = P.ctrl->psc;
@@ -290,17 +305,25 @@ __device__ __forceinline__ void pre_slices_tile(const PencilDesc& P, int k, int 
   const int tid = threadIdx.x;
   if (tid < G * MB) {
     const int i = tid % MB, g = tid / MB;
-    double mx = 0.0;
+    double mxs = 0.0, mxt = 0.0;
     if (i < hk)
-      for (int l = g; l < hc; l += G)
-        mx = fmax(mx, fmax(fabs(P.S[(k0 + i) + (int64_t)(c0 + l) * lds]), fabs(P.T[(k0 + i) + (int64_t)(c0 + l) * ldt])));
-    rowmax[g][i] = psc * mx;
+      for (int l = g; l < hc; l += G) {
+        mxs = fmax(mxs, fabs(P.S[(k0 + i) + (int64_t)(c0 + l) * lds]));
+        mxt = fmax(mxt, fabs(P.T[(k0 + i) + (int64_t)(c0 + l) * ldt]));
+      }
+    rowmax[0][g][i] = psc * mxs;
+    rowmax[1][g][i] = psc * mxt;
   }
   __syncthreads();
+  // the S half of row i is scaled by 2^a_i, its T half by 2^(a_i + D_r)
+  const int D = half_offset(P.stmax, P.Mmax, r);
   if (tid < MB) {
-    double mx = rowmax[0][tid];
-    for (int g = 1; g < G; ++g) mx = fmax(mx, rowmax[g][tid]);
-    const int e = slice_exponent(mx);
+    double ms = rowmax[0][0][tid], mt = rowmax[1][0][tid];
+    for (int g = 1; g < G; ++g) {
+      ms = fmax(ms, rowmax[0][g][tid]);
+      mt = fmax(mt, rowmax[1][g][tid]);
+    }
+    const int e = slice_exponent2(ms, mt, D);
     rowexp[tid] = e;
     P.Aexp[pair * MB + tid] = e;
   }
@@ -311,7 +334,8 @@ __device__ __forceinline__ void pre_slices_tile(const PencilDesc& P, int k, int 
   for (int64_t pk = tid; pk < npk; pk += kSliceThreads) {
     const int l = (int)(pk % 64), rb = (int)((pk / 64) % RBN), ks = (int)(pk / (64 * RBN));
     const int i = 16 * rb + l % 16;
-    const int e = rowexp[i];
+    // a K step of 64 lies in one half (HK is a multiple of 64)
+    const int e = rowexp[i] + (64 * ks >= HK ? D : 0);
     double y[16];
 #pragma unroll
     for (int b = 0; b < 16; ++b) {

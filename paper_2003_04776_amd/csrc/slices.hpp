@@ -2,14 +2,22 @@
 // scale and kSlices signed 7-bit slices, so products of slices are exact in the int8
 // matrix instruction's int32 accumulators.
 //
-// For a row (of [S_kr | T_kr]) or a column (of W) with largest magnitude below 2^e, every
+// The two halves of a row of [S_kr | T_kr] (S part, T part) and of a column of
+// W = [X D ; -X B] are scaled apart by 2^D_r, one offset per source tile row r: the S half of
+// row i by 2^a_i, its T half by 2^(a_i + D_r), the X D half of column c by 2^b_c and its
+// -X B half by 2^(b_c - D_r), so both halves' products carry the one exponent a_i + b_c and
+// are folded together.  D_r is the exponent of |T| minus that of |S| in the columns of tile
+// r; with a_i and b_c the least exponents that cover both halves, a pencil whose T is far
+// smaller (or larger) than its S loses no bits in either half (with one scale per row and
+// column it would lose their ratio in both operands of the same products).
+// For a row (or column) scaled by 2^e so that its entries are below one, every
 // entry x gives y = x 2^-e in (-1, 1) and
 //     y = sum_{p=1..7} a_p 2^(-7p) + rho,   a_p in [-127, 127] integers,  |rho| < 2^-49,
 // each a_p the integer part of the running remainder times 2^7 (exact in FP64).  A product
 // of two split operands is then 2^(e + f) sum_{p,q} 2^(-7(p+q)) sum_k a_p[i,k] w_q[k,c];
 // the pairs with p + q <= 8 are kept (the rest weigh below 2^-63 of the product), and the
 // pairs of one level L = p + q are summed exactly in int32 (|sum| <= 7 K 127^2 < 2^31 for
-// K <= 256).  The error is at most about 2 K 2^-49 max|A_i| max|W_c|.
+// K <= 256).  The error is at most about 2 K 2^-49 2^(a_i + b_c) per source.
 //
 // Fragment layout (matches the 16x16x64 int8 matrix instruction): a 16-byte packet per lane
 // holds 16 consecutive K values of one row (A) or one column (W); lane l of a 64-lane
@@ -20,6 +28,7 @@
 // kHalfK(MB) = MB rounded up to 64.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <limits.h>
 #include <stdint.h>
 
 namespace rgev {
@@ -64,6 +73,30 @@ __device__ __forceinline__ int slice_exponent(double vmax) {
   int e = 0;
   if (vmax > 0.0) frexp(vmax, &e);
   return e;
+}
+
+// The same for an operand of two halves scaled apart by 2^d (the second half's entries are
+// taken in units of 2^(e + d)): the least e with |first| < 2^e and |second| < 2^(e + d).
+__device__ __forceinline__ int slice_exponent2(double max_first, double max_second, int d) {
+  int e1 = INT_MIN / 2, e2 = INT_MIN / 2;
+  if (max_first > 0.0) frexp(max_first, &e1);
+  if (max_second > 0.0) {
+    frexp(max_second, &e2);
+    e2 -= d;
+  }
+  const int e = e1 > e2 ? e1 : e2;
+  return e == INT_MIN / 2 ? 0 : e;
+}
+
+// D_r from the largest |S| and |T| of the columns of tile r (as bits of non-negative doubles)
+__device__ __forceinline__ int half_offset(const unsigned long long* stmax, int mmax, int r) {
+  const double s = __longlong_as_double((long long)stmax[r]);
+  const double t = __longlong_as_double((long long)stmax[mmax + r]);
+  if (!(s > 0.0) || !(t > 0.0)) return 0;
+  int es, et;
+  frexp(s, &es);
+  frexp(t, &et);
+  return et - es;
 }
 
 }  // namespace rgev

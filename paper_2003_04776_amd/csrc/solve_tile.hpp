@@ -165,7 +165,7 @@ struct SolveSmem {
   int fcol[BW];                // scale exponent still owed by the rows above the group
   int ecol[BW];                // exponent of the second column of a pair
   int colG[BW];
-  int wexp[BW];                // mixed precision: column exponent of W
+  int wexp[BW];                // mixed precision: column exponent of W (X D half)
   int8_t tblk[MB];
   int8_t colKind[BW];
 };
@@ -197,6 +197,7 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
   __syncthreads();   // a previous solve in this workgroup is done with the shared memory
   const int M = P.ctrl->M;
   if (r < 0 || r >= M || j >= M) return;
+  if (P.rhs && !P.tflag[j]) return;   // correction mode: no column of tile j is refined
   const int64_t m = P.m;
   const int r0 = P.edges[r], hr = P.edges[r + 1] - r0;
   const int c0 = P.edges[j], hj = P.edges[j + 1] - c0;
@@ -249,7 +250,8 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
   }
   for (int idx = lc; idx < MB * LDY; idx += NTOT) Y[idx] = 0.0;
   __syncthreads();
-  if (!tip) {
+  if (!tip || P.rhs) {
+    // (in correction mode the tip tile too starts from the right-hand side held in Z)
     // thread lc reads row lc of every column (coalesced down the columns), 16 loads in flight
     if (lc < hr) {
       const double* zrow = P.Z + (r0 + lc) + (int64_t)(c0 + lo) * ldz;
@@ -355,7 +357,9 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
       if (work) {
         int qs = 0;
         if (tip && q0 == pc) {
-          if (nb == 1) {
+          if (P.rhs) {
+            // correction mode: the correction is zero at the tip (z0 = z1 = 0)
+          } else if (nb == 1) {
             z0 = cx(1.0, 0.0);
           } else {
             // second row of the singular block beta S_b - alpha T_b gives z_p for z_{p+1} = 1
@@ -591,11 +595,16 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
       if (kd == 1) return -(colA[n] * x - colB[n] * xp);
       return -(colB[n] * xp + colA[n] * x);
     };
+    // the X D half of column c is scaled by 2^b_c, its -X B half by 2^(b_c - D_r)
+    const int D = half_offset(P.stmax, P.Mmax, r);
     if (colthr) {
-      double mx = 0.0;
+      double mxu = 0.0, mxl = 0.0;
       if (inrange)
-        for (int i = 0; i < hr; ++i) mx = fmax(mx, fmax(fabs(wval(i, false, lc)), fabs(wval(i, true, lc))));
-      const int f = slice_exponent(ldexp(mx, -colG[lc]));
+        for (int i = 0; i < hr; ++i) {
+          mxu = fmax(mxu, fabs(wval(i, false, lc)));
+          mxl = fmax(mxl, fabs(wval(i, true, lc)));
+        }
+      const int f = slice_exponent2(ldexp(mxu, -colG[lc]), ldexp(mxl, -colG[lc]), -D);
       wexp[lc] = f;
       if (own) P.Wexp[(int64_t)(r % P.wslots) * m + c] = f;
     }
@@ -614,7 +623,7 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
       if (nt < own_lo || (nt >= own_hi && !(last && nt >= hj))) continue;
       const bool nok = nt < own_hi;
       const int n = nok ? nt - lo : 0;        // held column
-      const int sh = nok ? colG[n] + wexp[n] : 0;
+      const int sh = nok ? colG[n] + wexp[n] - (64 * ks >= HK ? D : 0) : 0;   // (a K step lies in one half)
       double y[16];
 #pragma unroll
       for (int b = 0; b < 16; ++b) {

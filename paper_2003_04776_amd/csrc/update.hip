@@ -22,6 +22,7 @@ void update_kernel(PencilDesc P, UpdRange U) {
   const int k = U.k_lo + 8 * (blk % nbk) + (w64 % 8);
   const int j = U.j_lo + 8 * (blk / nbk) + (w64 / 8);
   if (k >= U.k_hi || j >= M) return;
+  if (P.rhs && !P.tflag[j]) return;   // correction mode: no column of tile j is refined
   __shared__ UpdSmem<MB, UpdShape<MB>::R> sm;
   update_tile<MB, UpdShape<MB>::R, UpdShape<MB>::C>(P, U, k, j, sm);
 }

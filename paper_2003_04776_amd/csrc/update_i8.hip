@@ -75,7 +75,7 @@ __device__ __forceinline__ void update_i8_tile(const PencilDesc& P, const UpdRan
   if (g0 >= hj) return;
   const int s_end = min(min(U.s_hi, M - 1), j);
   const int ns = s_end - U.s_lo + 1;
-  const bool first = (j <= U.s_hi);
+  const bool first = (j <= U.s_hi) && !P.rhs;   // (correction mode: Y starts as the right-hand side)
   const int tid = threadIdx.x;
   const int lane = tid % 64, li = lane % 16, lk = lane / 16;
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
@@ -273,6 +273,7 @@ void update_i8_kernel(PencilDesc P, UpdRange U) {
   const int k = U.k_lo + 8 * (blk % nbk) + (w64 % 8);
   const int j = U.j_lo + 8 * (blk / nbk) + (w64 / 8);
   if (k >= U.k_hi || j >= M) return;
+  if (P.rhs && !P.tflag[j]) return;   // correction mode: no column of tile j is refined
   update_i8_tile<MB>(P, U, k, j, cg, rg);
 }
 
@@ -286,6 +287,7 @@ __global__ void publish_kernel(PencilDesc P, UpdRange U) {
   const int64_t m = P.m;
   for (int64_t c = P.edges[U.j_lo] + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < m;
        c += (int64_t)gridDim.x * blockDim.x) {
+    if (P.rhs && !P.tflag[P.tileof[c]]) continue;   // (tile column skipped by the launch)
     const int64_t e = (int64_t)k * m + c;
     P.norms[e] = __longlong_as_double((long long)P.norms_next[e]);
     P.exps[e] = P.exps_next[e];

@@ -139,7 +139,8 @@ __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange&
   // band, makes this the first update of (k, j): Y is still zero)
   const int s_end = min(min(U.s_hi, M - 1), j);
   const int ns = s_end - U.s_lo + 1;
-  const bool first = (j <= U.s_hi);
+  // (in correction mode Y starts as the right-hand side, so every update accumulates)
+  const bool first = (j <= U.s_hi) && !P.rhs;
   int cs[kMaxBand + 1];     // cumulative K chunks per source
   int es[kMaxBand + 1];     // first row of each source tile (and the end of the last)
   int ev[kMaxBand + 1];     // (edges past the band from clamped addresses, discarded: these

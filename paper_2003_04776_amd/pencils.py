@@ -45,6 +45,10 @@ Recipe (per pencil, seed ``seed``):
   eigenvalues spread over the same magnitudes as those of "stress", and every
   off-diagonal entry multiplied by 1e100.
 
+* ``kind="unbalanced"``: the "normal" pencil with T multiplied by 2^-40 (exact): the same
+  eigenvectors, eigenvalues 2^40 times larger, and the entries of T far below those of S in
+  every row of [S | T].
+
 ``qz_pencil`` gives a third source of inputs: the real generalized Schur form
 (S, T) = (Q^T A Zq, Q^T B Zq) that LAPACK's QZ algorithm (through SciPy) computes for a
 seeded dense pencil (A, B) with N(0, 1) entries -- the pencils the method receives in
@@ -54,7 +58,7 @@ from __future__ import annotations
 
 import numpy as np
 
-KINDS = ("normal", "stress", "zeroinf", "degenerate", "general", "general_stress")
+KINDS = ("normal", "stress", "zeroinf", "degenerate", "general", "general_stress", "unbalanced")
 
 
 def _stream(seed: int, j: int) -> np.random.Generator:
@@ -154,6 +158,8 @@ def fill_columns(S: np.ndarray, T: np.ndarray, kind_arr: np.ndarray, seed: int,
                     S[j, j] = 0.0
                 elif u < 0.02:
                     T[j, j] = 0.0
+        if kind == "unbalanced":
+            T[: j + 1, j] *= 2.0 ** -40
     del m
 
 

@@ -25,6 +25,7 @@ INFO_REAL_PAIR = 4
 INFO_INDEFINITE = 8
 INFO_PERTURBED = 16
 INFO_SELECT_CLOSED = 32
+INFO_REFINE = 64
 INFO_WATCHDOG = 128
 INFO_PRESCALED = 256
 
@@ -36,7 +37,7 @@ class RtgevcError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("mb", ctypes.c_int32), ("normalize", ctypes.c_int32), ("band", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("watchdog", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("max_refine", ctypes.c_int32), ("refine_bits", ctypes.c_int32)]
 
 
 _lib = None
@@ -92,7 +93,7 @@ EXPORTED = ("rtgevc_workspace_size", "rtgevc", "rtgevc_eigvals", "rtgevc_timed",
             "rtgevc_noalloc")
 NOALLOC_SCRATCH_BYTES = 64 << 20   # RTGEVC_NOALLOC_SCRATCH_BYTES
 ERR_SCRATCH = -2000                # RTGEVC_ERR_SCRATCH
-TIMED_NSTATS = 12
+TIMED_NSTATS = 14
 
 
 SCHEDULE_BANDS = 1     # band wavefront with look-ahead (default)
@@ -104,8 +105,10 @@ PRECISION_MIXED = 1    # tile-update contraction on the int8 matrix cores from s
 
 
 def make_opts(mb: int = 0, normalize: bool = True, band: int = 0, schedule: int = 0, watchdog: int = 0,
-              precision: int = 0) -> Opts:
+              precision: int = 0, max_refine: int = 0, refine_bits: int = 0) -> Opts:
     o = Opts()
+    o.max_refine = int(max_refine)
+    o.refine_bits = int(refine_bits)
     o.precision = int(precision)
     o.mb = int(mb)
     o.normalize = 1 if normalize else 0
@@ -116,8 +119,8 @@ def make_opts(mb: int = 0, normalize: bool = True, band: int = 0, schedule: int 
 
 
 def workspace_size(m: int, mb: int = 0, normalize: bool = True, band: int = 0, schedule: int = 0,
-                   precision: int = 0) -> int:
-    o = make_opts(mb, normalize, band, schedule, 0, precision)
+                   precision: int = 0, max_refine: int = 0, refine_bits: int = 0) -> int:
+    o = make_opts(mb, normalize, band, schedule, 0, precision, max_refine, refine_bits)
     return int(load().rtgevc_workspace_size(int(m), ctypes.byref(o)))
 
 
@@ -188,11 +191,12 @@ class Solver:
     allocation, made once by torch; the library itself allocates nothing)."""
 
     def __init__(self, m: int, mb: int = 0, normalize: bool = True, band: int = 0, device="cuda",
-                 schedule: int = 0, watchdog: int = 0, precision: int = 0, left: bool = False):
+                 schedule: int = 0, watchdog: int = 0, precision: int = 0, left: bool = False,
+                 max_refine: int = 0, refine_bits: int = 0):
         import torch
         self.m = int(m)
         self.left = bool(left)
-        self.opts = make_opts(mb, normalize, band, schedule, watchdog, precision)
+        self.opts = make_opts(mb, normalize, band, schedule, watchdog, precision, max_refine, refine_bits)
         size = load().rtgevc_left_workspace_size if self.left else load().rtgevc_workspace_size
         self.nbytes = int(size(self.m, ctypes.byref(self.opts)))
         self.work = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
@@ -236,7 +240,7 @@ class Solver:
                                  ctypes.byref(self.opts), _stream_ptr(stream), st, TIMED_NSTATS)
         _check(rc, "rtgevc_timed")
         keys = ("total_ms", "pre_ms", "solve_ms", "update_ms", "consolidate_ms", "n_pre", "n_solve",
-                "n_update", "n_consolidate", "update_flops", "M", "mb")
+                "n_update", "n_consolidate", "update_flops", "M", "mb", "refine_ms", "sweeps")
         return dict(zip(keys, list(st)))
 
     def eigvals(self, S, T, stream=None):
@@ -254,22 +258,25 @@ class Solver:
 
 
 def tgevc_left(S, T, select=None, normalize: bool = True, mb: int = 0, band: int = 0, stream=None,
-               schedule: int = 0, precision: int = 0) -> Result:
+               schedule: int = 0, precision: int = 0, max_refine: int = 0, refine_bits: int = 0) -> Result:
     """All (or the selected) left eigenvectors u of the Schur pencil, u^H (beta S - alpha T) = 0
     (Result.Z holds them)."""
     return Solver(S.shape[0], mb=mb, normalize=normalize, band=band, device=S.device,
-                  schedule=schedule, precision=precision, left=True).run(S, T, select, stream=stream)
+                  schedule=schedule, precision=precision, left=True, max_refine=max_refine,
+                  refine_bits=refine_bits).run(S, T, select, stream=stream)
 
 
 def tgevc(S, T, select=None, normalize: bool = True, mb: int = 0, band: int = 0, stream=None,
-          schedule: int = 0, precision: int = 0) -> Result:
+          schedule: int = 0, precision: int = 0, max_refine: int = 0, refine_bits: int = 0) -> Result:
     """All (or the selected) right eigenvectors of the Schur pencil (S, T)."""
     return Solver(S.shape[0], mb=mb, normalize=normalize, band=band, device=S.device,
-                  schedule=schedule, precision=precision).run(S, T, select, stream=stream)
+                  schedule=schedule, precision=precision, max_refine=max_refine,
+                  refine_bits=refine_bits).run(S, T, select, stream=stream)
 
 
 def tgevc_noalloc(S, T, select=None, normalize: bool = True, mb: int = 0, band: int = 0, stream=None,
-                  schedule: int = 0, precision: int = 0, Z=None, scales=None, info=None) -> Result:
+                  schedule: int = 0, precision: int = 0, Z=None, scales=None, info=None,
+                  max_refine: int = 0, refine_bits: int = 0) -> Result:
     """rtgevc_noalloc: the same eigenvectors as tgevc, computed in the library's fixed device
     scratch (no workspace; torch allocates only the outputs that are not passed in)."""
     import torch
@@ -288,7 +295,7 @@ def tgevc_noalloc(S, T, select=None, normalize: bool = True, mb: int = 0, band: 
         sel = torch.as_tensor(select, dtype=torch.int32, device=dev).contiguous()
         if sel.shape != (m,):
             raise ValueError("select must have length m")
-    o = make_opts(mb, normalize, band, schedule, 0, precision)
+    o = make_opts(mb, normalize, band, schedule, 0, precision, max_refine, refine_bits)
     rc = load().rtgevc_noalloc(m, S.data_ptr(), lds, T.data_ptr(), ldt,
                                sel.data_ptr() if sel is not None else None,
                                Z.data_ptr(), ldz, scales.data_ptr(), info.data_ptr(),

@@ -66,9 +66,10 @@ def test_argument_errors_before_any_gpu_work():
     assert _call(nbytes=16) == -12
     bad = rt.make_opts(mb=48)
     assert _call(opts=bad) == -13
-    bad = rt.make_opts()
-    bad.reserved[1] = 1
-    assert _call(opts=bad) == -13
+    assert _call(opts=rt.make_opts(precision=1, max_refine=4)) == -13
+    assert _call(opts=rt.make_opts(precision=1, max_refine=-2)) == -13
+    assert _call(opts=rt.make_opts(precision=1, refine_bits=101)) == -13
+    assert _call(opts=rt.make_opts(refine_bits=-1)) == -13
     assert _call(opts=rt.make_opts(schedule=3)) == -13
     assert _call(opts=rt.make_opts(watchdog=-1)) == -13
     assert _call(opts=rt.make_opts(precision=2)) == -13

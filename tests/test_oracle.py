@@ -423,3 +423,25 @@ def test_generator_structure():
     # a column regenerates alone and threads do not change the result
     S2, T2, _ = pencils.schur_pencil(400, 45, threads=4)
     assert np.array_equal(S, S2) and np.array_equal(T, T2)
+
+
+@pytest.mark.parametrize("m,seed,kind", [(300, 3, "normal"), (300, 203, "stress"), (300, 73, "general"),
+                                         (300, 74, "general_stress"), (1500, 4, "normal")])
+def test_componentwise_backward_error_at_unit_roundoff(m, seed, kind):
+    """The oracle is a scalar substitution, backward stable column by column, so its
+    componentwise backward error ||(beta S - alpha T) z||_1 / ||beta |S||z| + |alpha||T||z| ||_1
+    stays at a few units of roundoff whatever the pencil's scaling (1e100 off-diagonals in
+    the stress pencils) and order.  A dropped term, a wrong sign or a transposed operand in the
+    substitution moves it to O(1).  (The refinement of the mixed-precision mode flags columns
+    by this measure.)"""
+    from helpers import backward_errors
+    S, T, blk = pencils.schur_pencil(m, seed, kind)
+    Z, _, _ = oracle.tgevc(S, T)
+    ar, ai, be, _ = oracle.eigvals(S, T)
+    om = np.array(list(backward_errors(S, T, Z, ar, ai, be).values()))
+    assert om.max() <= 8 * U, om.max()
+    # the measure does see a perturbation at the 1e-12 level (relative to each column)
+    rng = np.random.default_rng(seed)
+    Zp = Z * (1.0 + 1e-12 * rng.standard_normal(Z.shape))
+    om_p = np.array(list(backward_errors(S, T, Zp, ar, ai, be).values()))
+    assert np.median(om_p) > 1e3 * np.median(om)

@@ -181,3 +181,24 @@ def test_qz_end_to_end_against_lapack():
     assert _match_scipy(A, B, X, blk, ar, ai, be, w, V) < 1e-9
     eta = residuals(A, B, X, ar, ai, be, kind=blk)
     assert max(eta.values()) <= 64 * m * U
+
+
+@pytest.mark.parametrize("m,seed", [(200, 81), (700, 82)])
+def test_unbalanced_pencil_same_eigenvectors(m, seed):
+    """The "unbalanced" pencil is (S, 2^-40 T) of the normal pencil (S, T): the eigenvalue
+    pairs become (alpha, 2^40 beta) up to the normalisation and the eigenvectors are the same.
+    With exact power-of-two scaling every step of the substitution is scaled exactly, so the
+    oracle returns the same normalised vectors bit for bit."""
+    S, T, _ = pencils.schur_pencil(m, seed)
+    Su, Tu, _ = pencils.schur_pencil(m, seed, kind="unbalanced")
+    assert np.array_equal(S, Su) and np.array_equal(Tu, T * 2.0 ** -40)
+    Z, _, i0 = oracle.tgevc(S, T)
+    Zu, _, i1 = oracle.tgevc(Su, Tu)
+    assert i0 == i1 == 0
+    assert np.array_equal(Z, Zu)
+    ar, ai, be, _ = oracle.eigvals(S, T)
+    aru, aiu, beu, _ = oracle.eigvals(Su, Tu)
+    # lambda_u = 2^40 lambda: alpha_u / beta_u = 2^40 alpha / beta
+    fin = be > 0
+    np.testing.assert_allclose(aru[fin] / beu[fin], 2.0 ** 40 * ar[fin] / be[fin], rtol=1e-14)
+    np.testing.assert_allclose(aiu[fin] / beu[fin], 2.0 ** 40 * ai[fin] / be[fin], rtol=1e-14)

@@ -7,6 +7,8 @@ import numpy as np
 import pytest
 import scipy.linalg
 
+import mpmath
+
 import oracle
 from helpers import block_kinds_from_S, left_residuals
 from paper_2003_04776_amd import pencils
@@ -25,11 +27,15 @@ def test_left_vectors_solve_the_equation(m, seed, kind):
     assert max(eta.values()) <= 64 * max(m, 1) * U, max(eta.values())
 
 
-def test_left_matches_lapack():
+@pytest.mark.parametrize("m,seed,kind", [(30, 11, "normal"), (64, 12, "normal"), (120, 13, "general"),
+                                         (160, 14, "normal")])
+def test_left_matches_lapack(m, seed, kind):
     """Each left eigenvector is parallel (complex cosine 1 to 1e-9) to LAPACK's left
-    eigenvector of the same eigenvalue (the right eigenvectors would not be)."""
-    m = 30
-    S, T, _ = pencils.schur_pencil(m, 11)
+    eigenvector of the same eigenvalue (the right eigenvectors would not be).  (LAPACK's QZ
+    is normwise backward stable, so on the overflow-stress pencils, with 1e100
+    off-diagonals, its eigenvalues near 1e6 carry no digits; those are pinned against the
+    80-digit substitution below.)"""
+    S, T, _ = pencils.schur_pencil(m, seed, kind=kind)
     kind = block_kinds_from_S(S)
     Y, _, _ = oracle.tgevc_left(S, T)
     ar, ai, be, _ = oracle.eigvals(S, T)
@@ -82,3 +88,90 @@ def test_left_selection_and_unnormalised():
         t = sum(np.abs(Yu[:, k]) for k in cols).max()
         assert np.allclose(Yu[:, c] / t, Yn[:, c], rtol=0, atol=8 * U)
     assert su.max() > 100
+
+
+@pytest.mark.parametrize("m,seed,kind", [(1, 31, "normal"), (2, 32, "normal"), (90, 33, "normal"),
+                                         (300, 34, "general"), (250, 35, "stress"), (200, 36, "zeroinf")])
+def test_left_direct_equals_flipped_pencil(m, seed, kind):
+    """The direct forward substitution and the right-eigenvector oracle on the flipped
+    transposed pencil (J S^T J, J T^T J) (a second route with other rounding) agree."""
+    S, T, _ = pencils.schur_pencil(m, seed, kind=kind)
+    Y, _, i1 = oracle.tgevc_left(S, T)
+    Yf, _, i2 = oracle.tgevc_left_flip(S, T)
+    assert i1 == i2
+    assert np.abs(Y - Yf).max() <= 1e-11
+
+
+def test_left_closed_form_pair():
+    """A single complex pair: S = [[a, b], [c, a]], T = t I; the left eigenvector of the
+    eigenvalue with positive imaginary part is u = (1, conj(-(beta a - alpha t) / (beta c)))
+    before normalisation, the phase fixed by u_0 = 1."""
+    a_, b_, c_, t_ = 0.3, 1.5, -0.7, 1.25
+    S = np.asfortranarray([[a_, b_], [c_, a_]])
+    T = np.asfortranarray([[t_, 0.0], [0.0, t_]])
+    Y, _, info = oracle.tgevc_left(S, T)
+    assert info == 0
+    lam = complex(a_, np.sqrt(-b_ * c_)) / t_
+    u = np.array([1.0, np.conj(-(a_ - lam * t_) / c_)])
+    u = u / max(abs(u[0].real) + abs(u[0].imag), abs(u[1].real) + abs(u[1].imag))
+    got = Y[:, 0] + 1j * Y[:, 1]
+    assert np.allclose(got, u, rtol=0, atol=8 * U)
+    assert abs(np.conj(got) @ (S - lam * T)).max() <= 8 * U
+
+
+def _mp_left(S, T, p, kind, dps=80):
+    """Independent reference: w = conj(u) with w^T M = 0 for M = S - lambda T (a 1x1 block:
+    t_pp S - s_pp T, a multiple that stays defined for an infinite eigenvalue), by forward
+    substitution over the blocks after p in 80-digit arithmetic with unbounded exponents and
+    no scaling; lambda of a pair from mpmath's eigensolver of T_b^-1 S_b (Im > 0); phase
+    w_p = 1; 2x2 blocks by mpmath's LU on the transposed 2x2 system."""
+    mpmath.mp.dps = dps
+    m = S.shape[0]
+    nb = 2 if kind[p] == 1 else 1
+    Sm = mpmath.matrix([[mpmath.mpf(float(S[i, j])) for j in range(m)] for i in range(m)])
+    Tm = mpmath.matrix([[mpmath.mpf(float(T[i, j])) if i <= j else 0 for j in range(m)] for i in range(m)])
+    for i in range(m):
+        for j in range(m):
+            if i > j + 1 or (i == j + 1 and kind[j] != 1):
+                Sm[i, j] = 0
+    if nb == 1:
+        M = Tm[p, p] * Sm - Sm[p, p] * Tm
+    else:
+        ev = mpmath.eig(mpmath.inverse(Tm[p:p + 2, p:p + 2]) * Sm[p:p + 2, p:p + 2], left=False, right=False)
+        lam = [e for e in ev if mpmath.im(e) > 0][0]
+        M = Sm - lam * Tm
+    w = [mpmath.mpc(0)] * m
+    w[p] = mpmath.mpc(1)
+    if nb == 2:
+        w[p + 1] = -M[p, p] / M[p + 1, p]
+    q = p + nb
+    while q < m:
+        cols = [q, q + 1] if kind[q] == 1 else [q]
+        rhs = [-mpmath.fsum(w[i] * M[i, c] for i in range(q)) for c in cols]
+        if len(cols) == 1:
+            w[q] = rhs[0] / M[q, q]
+        else:
+            A = mpmath.matrix([[M[r, c] for r in cols] for c in cols])   # M_qq^T
+            sol = mpmath.lu_solve(A, mpmath.matrix(rhs))
+            w[q], w[q + 1] = sol[0], sol[1]
+        q += len(cols)
+    return [mpmath.conj(v) for v in w]
+
+
+@pytest.mark.parametrize("kind,seed,m", [("normal", 41, 12), ("stress", 42, 12), ("stress", 43, 9),
+                                         ("general_stress", 44, 10), ("zeroinf", 45, 11)])
+def test_tiny_left_against_high_precision(kind, seed, m):
+    S, T, _ = pencils.schur_pencil(m, seed, kind)
+    blk = block_kinds_from_S(S)
+    Y, _, info = oracle.tgevc_left(S, T)
+    assert info == 0
+    for p in range(m):
+        if blk[p] == 2:
+            continue
+        u = _mp_left(S, T, p, blk)
+        nrm = max(abs(mpmath.re(v)) + abs(mpmath.im(v)) for v in u)
+        x = np.array([float(mpmath.re(v) / nrm) for v in u])
+        y = np.array([float(mpmath.im(v) / nrm) for v in u])
+        assert np.max(np.abs(Y[:, p] - x)) <= 1e-13, (p, Y[:, p], x)
+        if blk[p] == 1:
+            assert np.max(np.abs(Y[:, p + 1] - y)) <= 1e-13

@@ -66,6 +66,7 @@ def _oracle_check(S, T, Z):
     ("normal", 900, dict(precision=1)),
     ("general", 400, dict(schedule=2)),
     ("normal", 37, dict(mb=32)),
+    ("normal", 600, dict(precision=1, refine_bits=50)),
 ])
 def test_noalloc_equals_rtgevc(case):
     kind, m, kw = case
