@@ -82,8 +82,73 @@ def cpu_baseline(S, T, blk, m, seconds):
     dt = time.perf_counter() - t0
     res = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
            "sample": f"{len(idx)} of {m} columns evenly spread over the pencil, {flops:.3e} "
-                     f"algorithmic flops in {dt:.1f} s; double-precision scalar robust substitution"}
+                     f"algorithmic flops in {dt:.1f} s; double-precision scalar robust substitution",
+           "one_core_value": rate1 / 1e12,
+           "one_core_sample": f"the eigenvector of column {p} alone on one thread ({t1:.2f} s)",
+           "host_cpu": cpu_model(), "host_cores_total": os.cpu_count()}
     return res, idx, Zo[:, idx]
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def time_calls(fn, steps, warmup):
+    """Median and mean device time (ms) of fn() from HIP events recorded on the current
+    stream around each call (fn enqueues on that stream), after warmup calls."""
+    import numpy as np
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts)), float(np.mean(ts))
+
+
+def backward_error_stats(Sd, Td, Z, ar, ai, be, kind):
+    """Componentwise backward error of every eigenvector on the GPU in FP64:
+    omega_c = ||(beta S - alpha T) z||_1 / ||beta |S||z| + |alpha||T||z| ||_1 (pairs once, with
+    |Re| + |Im|); an FP64 substitution keeps it at a few units of roundoff.  Returns
+    median, p99 and max."""
+    import numpy as np
+    import torch
+    dev = Z.device
+    m = Z.shape[0]
+    kind = np.asarray(kind)
+    first = np.nonzero(kind != 2)[0]
+    pair = kind[first] == 1
+    a = torch.from_numpy(ar[first]).to(dev)
+    b = torch.from_numpy(np.where(pair, ai[first], 0.0)).to(dev)
+    bt = torch.from_numpy(be[first]).to(dev)
+    fi = torch.from_numpy(first).to(dev)
+    nx = torch.from_numpy(np.where(pair, first + 1, first)).to(dev)
+    pm = torch.from_numpy(pair).to(dev)
+    SZ = Sd @ Z
+    TZ = Td @ Z
+    rx = bt * SZ[:, fi] - a * TZ[:, fi] + b * TZ[:, nx]
+    ry = torch.where(pm, bt * SZ[:, nx] - b * TZ[:, fi] - a * TZ[:, nx], torch.zeros_like(rx))
+    num = rx.abs().sum(dim=0) + ry.abs().sum(dim=0)
+    del SZ, TZ, rx, ry
+    aZ = Z.abs()
+    az = aZ[:, fi] + torch.where(pm, aZ[:, nx], torch.zeros_like(aZ[:, fi]))
+    del aZ
+    den = bt * (Sd.abs() @ az).sum(dim=0) + (a.abs() + b.abs()) * (Td.abs() @ az).sum(dim=0)
+    om = (num / torch.where(den > 0, den, torch.ones_like(den))).cpu().numpy()
+    return {"median": float(np.median(om)), "p99": float(np.quantile(om, 0.99)), "max": float(om.max())}
 
 
 def bench_batched(args):
@@ -312,28 +377,43 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy probe: {n * 8} bytes read and {n * 8} bytes written")
         del src, dst
-    for w in range(args.warmup):
-        st = solver.run_timed(Sd, Td, Z, scales, info)
-        log(f"[bench] warmup {w}: {st['total_ms']:.1f} ms device")
+
+    # ---- the headline: the product call rtgevc, HIP events around each call on its stream ----
+    def call():
+        solver.run(Sd, Td, Z=Z, scales=scales, info=info)
+
+    for _ in range(args.warmup):
+        call()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = []
+    dev_ms = []
     for k in range(args.steps):
-        stats.append(solver.run_timed(Sd, Td, Z, scales, info))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        call()
+        e1.record()
+        e1.synchronize()
+        dev_ms.append(e0.elapsed_time(e1))
+        log(f"[bench] step {k}: {dev_ms[-1]:.1f} ms (rtgevc, device events)")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall / max(args.steps, 1) * 1e3
-    for k, st in enumerate(stats):
-        log(f"[bench] step {k}: device {st['total_ms']:.1f} ms (pre {st['pre_ms']:.2f}, solve {st['solve_ms']:.1f}, "
-            f"update {st['update_ms']:.1f}, consolidate {st['consolidate_ms']:.2f})")
     info_v = int(info.item())
     F = 2.0 * m ** 3 / 3.0
     value = F / (ms_per_step * 1e-3) / 1e12
+
+    # ---- phase split and the update kernel's roofline: rtgevc_timed (events around every launch) ----
+    stats = [solver.run_timed(Sd, Td, Z, scales, info) for _ in range(2)]
+    for k, st in enumerate(stats):
+        log(f"[bench] timed {k}: device {st['total_ms']:.1f} ms (pre {st['pre_ms']:.2f}, solve {st['solve_ms']:.1f}, "
+            f"update {st['update_ms']:.1f}, consolidate {st['consolidate_ms']:.2f}, refine {st['refine_ms']:.2f})")
     upd_flops = sum(s["update_flops"] for s in stats)
     upd_ms = sum(s["update_ms"] for s in stats)
     upd_launches = sum(s["n_update"] for s in stats)
     achieved = upd_flops / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else 0.0
     st0 = stats[-1]
+    res_mb, res_band, res_sched = rt.resolve_opts(m, mb=args.mb, band=args.band, schedule=args.schedule,
+                                                  precision=args.precision, with_schedule=True)
     out = {
         "metric": METRIC,
         "value": round(value, 4),
@@ -350,14 +430,16 @@ def main():
         "config": {
             "workload": f"all right eigenvectors of a real Schur pencil, m={m}, robust FP64 "
                         f"(power-of-two scale exponents), normalised output",
-            "m": m, "mb": int(st0["mb"]), "band": rt.resolve_opts(m, mb=args.mb, band=args.band)[1],
-            "schedule": "persistent walker" if args.schedule == 2 else "band wavefront", "tiles": int(st0["M"]),
-            "seed": args.seed,
-            "generator": args.kind, "flops_per_step": F,
+            "m": m, "mb": res_mb, "band": res_band,
+            "schedule": "persistent walker" if res_sched == 2 else "band wavefront", "tiles": int(st0["M"]),
+            "seed": args.seed, "generator": args.kind, "flops_per_step": F,
+            "timed_call": "rtgevc (the product entry point), HIP events around each call; ms_per_step is the "
+                          "host wall clock over the timed calls",
         },
+        "device_ms_median": round(float(np.median(dev_ms)), 3),
         "roofline": {
             "kernel": ("walker_kernel (whole task graph: tile updates on FP64 MFMA 16x16x4 and solves; "
-                       "update flops over the walker's time)") if args.schedule == 2 else
+                       "update flops over the walker's time)") if res_sched == 2 else
                       "update_kernel (robust tile update, FP64 MFMA 16x16x4)",
             "bound": "mfma",
             "achieved": round(achieved, 3),
@@ -365,65 +447,100 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(achieved / FP64_MFMA_PEAK, 4),
             "traffic": (TRAFFIC["bytes_per_launch"]
-                        if (m, int(st0["mb"]), rt.resolve_opts(m, mb=args.mb, band=args.band)[1],
-                            2 if args.schedule == 2 else 1) == TRAFFIC["workload"]
+                        if (m, res_mb, res_band, res_sched) == TRAFFIC["workload"]
+                        and args.precision == 0
                         and update_sources_hash() == TRAFFIC["sources_sha256_16"] else None),
             "traffic_unit": "bytes per launch (HBM read + write)",
             "launches": int(upd_launches),
             "avg_launch_ms": round(upd_ms / max(upd_launches, 1), 4),
             "flops_per_launch": upd_flops / max(upd_launches, 1),
+            "measured_with": "rtgevc_timed (HIP events on the stream of every launch), 2 calls",
         },
-        "phases_ms": {k: round(st0[k], 3) for k in ("pre_ms", "solve_ms", "update_ms", "consolidate_ms", "total_ms")},
+        "phases_ms": {k: round(st0[k], 3) for k in ("pre_ms", "solve_ms", "update_ms", "consolidate_ms",
+                                                     "refine_ms", "total_ms")},
         "info": info_v,
     }
     Zf = Z.clone()
+    Zm = None
     if args.compare_mixed and args.precision == 0 and args.schedule != 2:
-        # the mixed-precision mode on the same inputs: speed-up and agreement with the FP64 run
+        # the mixed-precision mode on the same inputs, with its default refinement (one sweep;
+        # columns flagged by the backward-error sketch) and without refinement
         mixed = rt.Solver(m, mb=args.mb, normalize=True, band=args.band, precision=1)
-        for w in range(args.warmup):
-            mixed.run_timed(Sd, Td, Z, scales, info)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        mst = [mixed.run_timed(Sd, Td, Z, scales, info) for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        mwall = (time.perf_counter() - t0) / max(args.steps, 1) * 1e3
-        mflops = sum(x["update_flops"] for x in mst)
-        mupd = sum(x["update_ms"] for x in mst)
-        mmb, mband = rt.resolve_opts(m, mb=args.mb, band=args.band, precision=1)
-        out["mixed"] = {
-            "precision": "tile-update contraction on int8 matrix cores, operands split into 7 x 7-bit slices",
-            "mb": mmb, "band": mband,
-            "ms_per_step": round(mwall, 3),
-            "value": round(F / (mwall * 1e-3) / 1e12, 4),
-            "speedup_vs_fp64": round(ms_per_step / mwall, 4),
-            "update_achieved_fp64_equiv_tflops": round(mflops / (mupd * 1e-3) / 1e12, 3) if mupd > 0 else None,
-            "max_abs_diff_vs_fp64": float((Z - Zf).abs().max().item()),
-            "info": int(info.item()),
-        }
-        log(f"[bench] mixed: {mwall:.1f} ms/step, speed-up {ms_per_step / mwall:.3f}")
+        Zm = rt.colmajor_empty(m)
+        minfo = torch.zeros(1, dtype=torch.int32, device="cuda")
+        mms, _ = time_calls(lambda: mixed.run(Sd, Td, Z=Zm, scales=scales, info=minfo), args.steps, args.warmup)
+        m_info = int(minfo.item())
+        mst = mixed.run_timed(Sd, Td, Zm, scales, minfo)
         del mixed
+        noref = rt.Solver(m, mb=args.mb, normalize=True, band=args.band, precision=1, max_refine=-1)
+        Zn = rt.colmajor_empty(m)
+        nms, _ = time_calls(lambda: noref.run(Sd, Td, Z=Zn, scales=scales, info=minfo), args.steps, args.warmup)
+        nst = noref.run_timed(Sd, Td, Zn, scales, minfo)
+        same = bool(torch.equal(Zn, Zm))
+        del noref, Zn
+        mmb, mband = rt.resolve_opts(m, mb=args.mb, band=args.band, precision=1)
+        fp64_ms = float(np.median(dev_ms))
+        out["mixed"] = {
+            "precision": "tile-update contraction on int8 matrix cores, operands split into 7 x 7-bit slices "
+                         "(S/T halves scaled apart per source tile row); FP64 solves, bounds, residual",
+            "mb": mmb, "band": mband,
+            "ms_per_call": round(mms, 3),
+            "value": round(F / (mms * 1e-3) / 1e12, 4),
+            "speedup_vs_fp64": round(fp64_ms / mms, 4),
+            "refinement": {"max_sweeps": 1, "threshold": "componentwise backward error 64 m 2^-53",
+                           "refine_ms": round(mst["refine_ms"], 3),
+                           "info_bit_64": bool(m_info & 64),
+                           "result_equals_unrefined": same,
+                           "ms_per_call_without_refinement": round(nms, 3),
+                           "speedup_vs_fp64_without_refinement": round(fp64_ms / nms, 4)},
+            "update_achieved_fp64_equiv_tflops": round(mst["update_flops"] / (mst["update_ms"] * 1e-3) / 1e12, 3)
+            if mst["update_ms"] > 0 else None,
+            "max_abs_diff_vs_fp64": float((Zm - Zf).abs().max().item()),
+            "info": m_info,
+        }
+        log(f"[bench] mixed: {mms:.1f} ms/call (without refinement {nms:.1f}), speed-up {fp64_ms / mms:.3f}")
     if args.residual and args.precision == 0:
-        # the eigen-equation residual of the FP64 result and of the mixed one (same bound)
+        # the eigen-equation residual and the componentwise backward error of the FP64 result
+        # and of the mixed one
         are, aim, bet, _ = solver.eigvals(Sd, Td)
         ar, ai, be = (x.cpu().numpy() for x in (are, aim, bet))
-        res = {"bound": 64 * m * 2.0 ** -53, "fp64_max": residual_max(Sd, Td, Zf, ar, ai, be, blk)}
-        if "mixed" in out:
-            res["mixed_max"] = residual_max(Sd, Td, Z, ar, ai, be, blk)
+        res = {"bound": 64 * m * 2.0 ** -53, "fp64_max": residual_max(Sd, Td, Zf, ar, ai, be, blk),
+               "fp64_backward_error": backward_error_stats(Sd, Td, Zf, ar, ai, be, blk)}
+        if Zm is not None:
+            res["mixed_max"] = residual_max(Sd, Td, Zm, ar, ai, be, blk)
+            res["mixed_backward_error"] = backward_error_stats(Sd, Td, Zm, ar, ai, be, blk)
         out["residual"] = res
         log(f"[bench] residuals: {res}")
+    del solver
     if args.left and args.precision == 0:
-        out["left"] = bench_left(args, m, Sd, Td, F, ms_per_step)
+        out["left"] = bench_left(args, m, Sd, Td, F, float(np.median(dev_ms)))
     if args.back:
         out["backtransform"] = bench_back(args, m, Sd, Zf, scales, blk)
     if rank == 0 and not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a column sample")
         out["cpu_baseline"], idx, Zo = cpu_baseline(S, T, blk, m, args.cpu_seconds)
         if args.precision == 0:
-            # the FP64 result against the oracle on the same (normalised) columns
-            Zs = Zf[:, torch.from_numpy(idx).to(Zf.device)].cpu().numpy()
-            err = np.abs(Zs - Zo).max(axis=0)
-            out["oracle_check"] = {"columns": int(len(idx)), "max_abs_err": float(err.max()),
-                                   "columns_above_1e-10": int((err > 1e-10).sum())}
+            # e_c = max_i |Z_gpu - Z_oracle| per column on the sample (normalised columns)
+            ti = torch.from_numpy(idx).to(Zf.device)
+            chk = {}
+            for name, ZZ in (("fp64", Zf), ("mixed", Zm)):
+                if ZZ is None:
+                    continue
+                err = np.abs(ZZ[:, ti].cpu().numpy() - Zo).max(axis=0)
+                chk[name] = {"columns": int(len(idx)), "median": float(np.median(err)),
+                             "p99": float(np.quantile(err, 0.99)), "max": float(err.max()),
+                             "columns_above_1e-10": int((err > 1e-10).sum())}
+            if Zm is not None:
+                # the columns where the mixed result differs most from the FP64 one, against the oracle
+                import oracle
+                d = (Zm - Zf).abs().amax(dim=0)
+                top = torch.topk(d, 8).indices.cpu().numpy()
+                sel = np.zeros(m, dtype=np.int32)
+                sel[top] = 1
+                Zt, _, _ = oracle.tgevc(S, T, select=sel, threads=16)
+                et = np.abs(Zm[:, torch.from_numpy(top).to(Zm.device)].cpu().numpy() - Zt[:, top]).max(axis=0)
+                chk["mixed_worst_vs_fp64"] = {"columns": [int(c) for c in top], "max": float(et.max())}
+            out["oracle_check"] = chk
     if rank == 0:
         print(json.dumps(out), flush=True)
 

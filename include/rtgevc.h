@@ -94,13 +94,17 @@ typedef struct rtgevc_opts {
                             stay FP64.  Needs more workspace (slices of every tile pair).
                             Not with schedule 2.                                          */
   int32_t max_refine; /* mixed precision only: at most this many refinement sweeps against
-                         an FP64 residual (0 = default, 3; -1 = none; else 1..3).  A sweep
+                         an FP64 residual (0 = default, 1; -1 = none; else 1..3).  A sweep
                          estimates for every column still under refinement the componentwise
                          backward error ||r||_1 / ||beta |S||z| + |alpha||T||z| ||_1 of
                          r = (beta S - alpha T) z (Section 2) with a 16-row Cauchy sketch
                          (O(m^2) work), flags the columns above the threshold, forms r in
                          FP64 for them, solves (beta S - alpha T) d = r with the blocked robust
-                         solver (d = 0 at the tip) and replaces z by z - d (normalising again).
+                         solver (d = 0 at the tip) and replaces z by z - d.  The sweeps run
+                         before the consolidation, on the tile segments with their own
+                         exponents, so eigenvectors spanning more than the double range
+                         are refined at full precision; columns whose entries underflow
+                         inside a tile (overflow-stress pencils) are not refined.
                          A last estimate sets RTGEVC_INFO_REFINE for columns still above the
                          threshold.  Needs 8 m^2 more bytes of workspace.                 */
   int32_t refine_bits;/* threshold of the flag: 2^-refine_bits (1..100); 0 = the residual

@@ -94,11 +94,11 @@ bool opts_ok(const rtgevc_opts* o) {
   return true;
 }
 
-// refinement sweeps of a call: mixed precision only; max_refine 0 = 3, -1 = none
+// refinement sweeps of a call: mixed precision only; max_refine 0 = 1, -1 = none
 int resolve_sweeps(const rtgevc_opts* o) {
   if (!o || o->precision != 1) return 0;
   if (o->max_refine < 0) return 0;
-  return o->max_refine == 0 ? 3 : o->max_refine;
+  return o->max_refine == 0 ? 1 : o->max_refine;
 }
 
 // flag threshold: 2^-refine_bits, or by default the residual bound 64 m 2^-53
@@ -177,8 +177,12 @@ __host__ __device__ size_t carve(PencilDesc& P, char* base, int64_t m, int mb, i
     ref->dT = c.take<double>(base, m);
     ref->zexp = c.take<int32_t>(base, m);
     ref->rf = c.take<int8_t>(base, m);
+    ref->fits = c.take<int8_t>(base, m);
     ref->tflag = c.take<int32_t>(base, Mmax);
+    ref->part = c.take<double>(base, (size_t)((m + 1023) / 1024) * m * (2 * kSketch + 2));
     ref->Zc = c.take<double>(base, (size_t)m * m);
+    ref->cexps = c.take<int32_t>(base, (size_t)Mmax * m);
+    ref->cnorms = c.take<double>(base, (size_t)Mmax * m);
   }
   if (walk) {
     walk->cnt = c.take<int32_t>(base, (size_t)Mmax * Mmax);
@@ -442,6 +446,8 @@ hipError_t enqueue_refine(const PencilDesc& P, const RefineDesc& R, int sweeps, 
   PencilDesc C = P;
   C.Z = R.Zc;
   C.ldz = P.m;
+  C.exps = R.cexps;
+  C.norms = R.cnorms;
   C.sel = R.rf;
   C.rhs = 1;
   C.tflag = R.tflag;
@@ -480,9 +486,9 @@ hipError_t enqueue_right(int64_t m, const double* S, int64_t lds, const double* 
   if (one_stream) {
     launch_preprocess(P, s);
     hipError_t err = enqueue_rows_one_stream(P, P.Mmax, s);
-    launch_consolidate(P, s);
     if (err == hipSuccess && sweeps > 0)
       err = enqueue_refine(P, R, sweeps, s, [&](const PencilDesc& C) { return enqueue_rows_one_stream(C, C.Mmax, s); });
+    launch_consolidate(P, s);
     return err == hipSuccess ? hipGetLastError() : err;
   }
   std::lock_guard<std::mutex> lock(g_aux_mu);
@@ -491,11 +497,11 @@ hipError_t enqueue_right(int64_t m, const double* S, int64_t lds, const double* 
   if (err != hipSuccess) return err;
   launch_preprocess(P, s);
   err = enqueue_rows(P, P.Mmax, s, *ax, [](int, bool, hipStream_t) {});
-  launch_consolidate(P, s);
   if (err == hipSuccess && sweeps > 0)
     err = enqueue_refine(P, R, sweeps, s, [&](const PencilDesc& C) {
       return enqueue_rows(C, C.Mmax, s, *ax, [](int, bool, hipStream_t) {});
     });
+  launch_consolidate(P, s);
   return err == hipSuccess ? hipGetLastError() : err;
 }
 
@@ -737,11 +743,6 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
     });
     if (err == hipSuccess) err = e;
   }
-  const int c0 = used;
-  mark();
-  launch_consolidate(P, s);
-  mark();
-  spans[nsp++] = Span{3, c0, c0 + 1};
   if (err == hipSuccess && sweeps > 0) {
     // the refinement is one span (its correction solves' launches are not marked)
     const int f0 = used;
@@ -752,6 +753,11 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
     mark();
     spans[nsp++] = Span{4, f0, f0 + 1};
   }
+  const int c0 = used;
+  mark();
+  launch_consolidate(P, s);
+  mark();
+  spans[nsp++] = Span{3, c0, c0 + 1};
   if (err == hipSuccess) err = hipGetLastError();
   if (err == hipSuccess) err = hipStreamSynchronize(s);
   int32_t* edges = new int32_t[M + 1];

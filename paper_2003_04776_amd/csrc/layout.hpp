@@ -99,6 +99,8 @@ constexpr int kMaxBand = 8;
 // || beta |S| |z| + |alpha| |T| |z| ||_1 (a componentwise backward error, at the level of u for an
 // FP64 substitution); flagged columns get r in FP64 and a correction solve.
 constexpr int kSketch = 16;
+// workgroups of a correction-mode launch (they stride over the tiles of the launch)
+constexpr int kRhsGrid = 1536;
 
 struct RefineDesc {
   double* G;          // [m][kSketch] sketch rows, row-major by matrix row
@@ -112,8 +114,12 @@ struct RefineDesc {
   double* dT;
   int32_t* zexp;      // [m] z'_c = 2^-zexp[c] z_c (common to the two columns of a pair)
   int8_t* rf;         // [m] flagged by the latest pass
+  int8_t* fits;       // [m] every entry within the range a refinement can handle (pass 0)
   int32_t* tflag;     // [Mmax] tile column holds a flagged column
+  double* part;       // [ceil(m / 1024) * m * (2 kSketch + 2)] partial sums per row chunk
   double* Zc;         // [m * m] residual in, correction out (leading dimension m)
+  int32_t* cexps;     // [Mmax * m] segment exponents and norms of Zc (the correction solve's)
+  double* cnorms;
   double tau;         // flag threshold on the backward-error estimate
 };
 

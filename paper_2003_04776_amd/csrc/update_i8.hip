@@ -265,6 +265,21 @@ void update_i8_kernel(PencilDesc P, UpdRange U) {
   if (U.j_lo >= M || U.k_hi <= U.k_lo || U.s_lo >= M) return;
   const int nk = U.k_hi - U.k_lo, nj = M - U.j_lo;
   const int nbk = (nk + 7) / 8, nbj = (nj + 7) / 8;
+  if (P.rhs) {
+    // correction mode: a bounded grid walks the target tiles and skips the tile columns that
+    // hold no refined column (so an empty sweep dispatches few workgroups)
+    const int total = nbk * nbj * 64 * NCG * NRG;
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+      const int cg = u % NCG, rg = (u / NCG) % NRG, t = u / (NCG * NRG);
+      const int blk = t / 64, w64 = t % 64;
+      const int k = U.k_lo + 8 * (blk % nbk) + (w64 % 8);
+      const int j = U.j_lo + 8 * (blk / nbk) + (w64 / 8);
+      if (k >= U.k_hi || j >= M || !P.tflag[j]) continue;
+      __syncthreads();   // the previous tile's shared memory is free
+      update_i8_tile<MB>(P, U, k, j, cg, rg);
+    }
+    return;
+  }
   const int per = (int)(gridDim.x / 8);
   const int idx = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   const int cg = idx % NCG, rg = (idx / NCG) % NRG, t = idx / (NCG * NRG);
@@ -273,7 +288,6 @@ void update_i8_kernel(PencilDesc P, UpdRange U) {
   const int k = U.k_lo + 8 * (blk % nbk) + (w64 % 8);
   const int j = U.j_lo + 8 * (blk / nbk) + (w64 / 8);
   if (k >= U.k_hi || j >= M) return;
-  if (P.rhs && !P.tflag[j]) return;   // correction mode: no column of tile j is refined
   update_i8_tile<MB>(P, U, k, j, cg, rg);
 }
 
@@ -299,7 +313,8 @@ template <int MB>
 static void launch_i8(const PencilDesc& P, const UpdRange& U, hipStream_t s) {
   constexpr int NCG = I8Shape<MB>::NCG, NRG = I8Shape<MB>::NRG;
   const int64_t nbk = (U.k_hi - U.k_lo + 7) / 8, nbj = (P.Mmax - U.j_lo + 7) / 8;
-  update_i8_kernel<MB><<<(unsigned)(nbk * nbj * 64 * NCG * NRG), 64 * I8Shape<MB>::NW, 0, s>>>(P, U);
+  const int64_t grid = nbk * nbj * 64 * NCG * NRG;
+  update_i8_kernel<MB><<<(unsigned)(P.rhs ? std::min<int64_t>(grid, kRhsGrid) : grid), 64 * I8Shape<MB>::NW, 0, s>>>(P, U);
   if (NRG > 1) publish_kernel<<<dim3(16, (unsigned)(U.k_hi - U.k_lo)), 256, 0, s>>>(P, U);
 }
 
