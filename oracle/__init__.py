@@ -41,13 +41,14 @@ def lib():
         L = ctypes.CDLL(_SO)
         i64, i32p, dp = ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
         for suf in ("_d", "_ld"):
-            for name in ("oracle_tgevc", "oracle_tgevc_left"):
+            for name in ("oracle_tgevc", "oracle_tgevc_left", "oracle_ctgevc"):
                 f = getattr(L, name + suf)
                 f.restype = ctypes.c_int
                 f.argtypes = [i64, dp, i64, dp, i64, i32p, dp, i64, i32p, ctypes.c_int, ctypes.c_int]
-            f = getattr(L, "oracle_eigvals" + suf)
-            f.restype = ctypes.c_int
-            f.argtypes = [i64, dp, i64, dp, i64, dp, dp, dp]
+            for name in ("oracle_eigvals", "oracle_ceigvals"):
+                f = getattr(L, name + suf)
+                f.restype = ctypes.c_int
+                f.argtypes = [i64, dp, i64, dp, i64, dp, dp, dp]
             f = getattr(L, "oracle_blocks" + suf)
             f.restype = ctypes.c_int
             f.argtypes = [i64, dp, i64, ctypes.POINTER(ctypes.c_int8)]
@@ -207,3 +208,45 @@ def tgevc_left_flip(S: np.ndarray, T: np.ndarray, select=None, normalize: bool =
         re, im = Y[:, p + 1].copy(), Y[:, p].copy()
         Y[:, p], Y[:, p + 1] = re, -im
     return Y, scales, info
+
+
+def _cld_of(A: np.ndarray) -> int:
+    if A.dtype != np.complex128 or A.ndim != 2 or A.strides[0] != 16:
+        raise ValueError("expected a column-major complex128 matrix")
+    return A.strides[1] // 16 if A.shape[1] > 1 else max(A.shape[0], 1)
+
+
+def _cdp(A):
+    return A.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def ctgevc(S: np.ndarray, T: np.ndarray, select=None, normalize: bool = True,
+           precision: str = "double", threads: int | None = None):
+    """Right eigenvectors of a complex upper-triangular pencil (S, T) (oracle_ctgevc in
+    oracle_impl.h: complex scalar robust back-substitution, z_k = 1 at the eigenvalue's own
+    row).  Returns (Z complex128 column-major, scales, info)."""
+    m = S.shape[0]
+    if threads is None:
+        threads = os.cpu_count() or 1
+    Z = np.zeros((m, m), dtype=np.complex128, order="F")
+    scales = np.zeros(max(m, 1), dtype=np.int32)
+    sel = None
+    if select is not None:
+        sel = np.ascontiguousarray(np.asarray(select, dtype=np.int32))
+        if sel.shape != (m,):
+            raise ValueError("select must have length m")
+    f = getattr(lib(), "oracle_ctgevc" + ("_d" if precision == "double" else "_ld"))
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    info = f(m, _cdp(S), _cld_of(S), _cdp(T), _cld_of(T),
+             sel.ctypes.data_as(i32p) if sel is not None else None,
+             _cdp(Z), max(m, 1), scales.ctypes.data_as(i32p), int(bool(normalize)), int(threads))
+    return Z, scales[:m], int(info)
+
+
+def ceigvals(S: np.ndarray, T: np.ndarray, precision: str = "double"):
+    """Normalised (alpha, beta) of the complex pencil: alpha complex, beta real >= 0."""
+    m = S.shape[0]
+    ar, ai, be = (np.zeros(max(m, 1)) for _ in range(3))
+    f = getattr(lib(), "oracle_ceigvals" + ("_d" if precision == "double" else "_ld"))
+    info = f(m, _cdp(S), _cld_of(S), _cdp(T), _cld_of(T), _dp(ar), _dp(ai), _dp(be))
+    return (ar + 1j * ai)[:m], be[:m], int(info)

@@ -711,3 +711,170 @@ int FN(oracle_tgevc_left)(int64_t m, const double *S, int64_t lds, const double 
     free(blk);
     return info;
 }
+
+/* --------------------------- complex-arithmetic pencils (Section 7, future work) -- */
+
+/* S and T complex upper triangular of order m, stored interleaved (real, imaginary) and
+ * column-major with leading dimensions counted in complex entries; there are no 2x2 blocks.
+ * Eigenvalue k is lambda = s_kk / t_kk, kept as (alpha, beta) with beta = |t_kk| real >= 0
+ * and alpha = s_kk conj(t_kk) / |t_kk| (t_kk = 0: beta = 0 and alpha = |s_kk|; both zero:
+ * indefinite, info bit 8), scaled by a power of two so that max(beta, |alpha|_1) lies in
+ * (1/2, 1].  Its eigenvector solves (beta S - alpha T) z = 0 with z_k = 1 and z_i = 0 for
+ * i > k, by the same scalar robust back-substitution as the real case with 1x1 blocks only:
+ * complex divisions protected by ProtectDivision, column updates by ProtectUpdate, pivots
+ * below smin = max(u (beta |s_jj| + |alpha| |t_jj|), tiny) perturbed (info bit 16), complex
+ * magnitudes |Re| + |Im|. */
+
+#define CRE(A, ld, i, j) ((R)(A)[2 * ((i) + (j) * (int64_t)(ld))])
+#define CIM(A, ld, i, j) ((R)(A)[2 * ((i) + (j) * (int64_t)(ld)) + 1])
+
+/* |x + iy| without overflow */
+static R FN(cmod)(R x, R y)
+{
+    R ax = FABS(x), ay = FABS(y);
+    R mx = ax > ay ? ax : ay;
+    if (mx == 0) return 0;
+    R rx = ax / mx, ry = ay / mx;
+    return mx * SQRT(rx * rx + ry * ry);
+}
+
+static int FN(ceig)(const double *S, int64_t lds, const double *T, int64_t ldt, int64_t k,
+                    R *ar, R *ai, R *be)
+{
+    R sr = CRE(S, lds, k, k), si = CIM(S, lds, k, k);
+    R tr = CRE(T, ldt, k, k), ti = CIM(T, ldt, k, k);
+    R at = FN(cmod)(tr, ti);
+    int info = 0;
+    if (at > 0) {
+        R ur = tr / at, ui = -ti / at;          /* conj(t) / |t| */
+        *ar = sr * ur - si * ui;
+        *ai = sr * ui + si * ur;
+        *be = at;
+    } else {
+        *ar = FN(cmod)(sr, si);
+        *ai = 0;
+        *be = 0;
+        if (*ar == 0) info |= 8;
+    }
+    FN(normalize_ab)(ar, ai, be);
+    return info;
+}
+
+int FN(oracle_ceigvals)(int64_t m, const double *S, int64_t lds, const double *T, int64_t ldt,
+                        double *alpha_re, double *alpha_im, double *beta)
+{
+    int info = 0;
+    for (int64_t k = 0; k < m; ++k) {
+        R ar, ai, be;
+        info |= FN(ceig)(S, lds, T, ldt, k, &ar, &ai, &be);
+        alpha_re[k] = (double)ar; alpha_im[k] = (double)ai; beta[k] = (double)be;
+    }
+    return info;
+}
+
+/* y[0:r] -= (beta S[0:r, r] - alpha T[0:r, r]) w_r, protected by ProtectUpdate with the
+ * exact bound of the column, the solved entry and the rows above. */
+static void FN(cupdate_above)(const double *S, int64_t lds, const double *T, int64_t ldt, int64_t r,
+                              R a, R b, R be, R *wr, R *wi, int64_t n, int64_t *k)
+{
+    if (r == 0) return;
+    R aabs = FABS(a) + FABS(b);
+    R cn = 0;
+    for (int64_t i = 0; i < r; ++i) {
+        R v = be * (FABS(CRE(S, lds, i, r)) + FABS(CIM(S, lds, i, r))) +
+              aabs * (FABS(CRE(T, ldt, i, r)) + FABS(CIM(T, ldt, i, r)));
+        if (v > cn) cn = v;
+    }
+    R wn = FN(cabs1)(wr[r], wi[r]), yn = 0;
+    for (int64_t i = 0; i < r; ++i) {
+        R v = FN(cabs1)(wr[i], wi[i]);
+        if (v > yn) yn = v;
+    }
+    int q = FN(oracle_pu)(cn, wn, yn);
+    if (q) { FN(scale_all)(wr, wi, n, q, 1); *k += q; }
+    R ur = be * wr[r], ui = be * wi[r];                        /* beta w_r */
+    R vr = a * wr[r] - b * wi[r], vi = b * wr[r] + a * wi[r];  /* alpha w_r */
+    for (int64_t i = 0; i < r; ++i) {
+        R sr = CRE(S, lds, i, r), si = CIM(S, lds, i, r);
+        R tr = CRE(T, ldt, i, r), ti = CIM(T, ldt, i, r);
+        /* S (beta w) - T (alpha w), complex products */
+        wr[i] -= (sr * ur - si * ui) - (tr * vr - ti * vi);
+        wi[i] -= (sr * ui + si * ur) - (tr * vi + ti * vr);
+    }
+}
+
+static int FN(ceigvec)(const double *S, int64_t lds, const double *T, int64_t ldt, int64_t p,
+                       R *wr, R *wi, int64_t *kout)
+{
+    int info = 0;
+    R a, b, be;
+    info |= FN(ceig)(S, lds, T, ldt, p, &a, &b, &be);
+    int64_t n = p + 1, k = 0;
+    for (int64_t i = 0; i < n; ++i) { wr[i] = 0; wi[i] = 0; }
+    wr[p] = 1;
+    if (info & 8) { *kout = 0; return info; }
+    FN(cupdate_above)(S, lds, T, ldt, p, a, b, be, wr, wi, n, &k);
+    for (int64_t j = p - 1; j >= 0; --j) {
+        R sr = CRE(S, lds, j, j), si = CIM(S, lds, j, j);
+        R tr = CRE(T, ldt, j, j), ti = CIM(T, ldt, j, j);
+        /* d = beta s_jj - alpha t_jj */
+        R dr = be * sr - (a * tr - b * ti);
+        R di = be * si - (a * ti + b * tr);
+        R smin = U_ROUND * (be * (FABS(sr) + FABS(si)) + (FABS(a) + FABS(b)) * (FABS(tr) + FABS(ti)));
+        if (smin < TINY) smin = TINY;
+        if (FN(cabs1)(dr, di) < smin) { dr = smin; di = 0; info |= 16; }
+        int q = FN(oracle_pd)(FN(cabs1)(wr[j], wi[j]), FN(cabs1)(dr, di) / 2);
+        if (q) { FN(scale_all)(wr, wi, n, q, 1); k += q; }
+        R e, f;
+        FN(oracle_cdiv)(wr[j], wi[j], dr, di, &e, &f);
+        wr[j] = e; wi[j] = f;
+        FN(cupdate_above)(S, lds, T, ldt, j, a, b, be, wr, wi, n, &k);
+    }
+    *kout = k;
+    return info;
+}
+
+/* All selected eigenvectors of the complex pencil; Z complex (interleaved), column k the
+ * eigenvector of eigenvalue k.  normalize = 1: divided by max_i |Re z_i| + |Im z_i|, scales 0;
+ * else the mantissa in Z and the exponent in scales (2^scales[k] Z[:, k], with z_k = 1). */
+int FN(oracle_ctgevc)(int64_t m, const double *S, int64_t lds, const double *T, int64_t ldt,
+                      const int32_t *select, double *Z, int64_t ldz, int32_t *scales,
+                      int normalize, int nthreads)
+{
+    if (m <= 0) return 0;
+    for (int64_t c = 0; c < m; ++c) {
+        for (int64_t i = 0; i < m; ++i) { Z[2 * (i + c * ldz)] = 0; Z[2 * (i + c * ldz) + 1] = 0; }
+        scales[c] = 0;
+    }
+    int tinfo = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1) reduction(| : tinfo)
+    {
+        R *wr = (R *)malloc(sizeof(R) * (size_t)(m + 1));
+        R *wi = (R *)malloc(sizeof(R) * (size_t)(m + 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t s = m - 1; s >= 0; --s) {
+            if (select && !select[s]) continue;
+            int64_t k = 0;
+            tinfo |= FN(ceigvec)(S, lds, T, ldt, s, wr, wi, &k);
+            R nrm = 1;
+            if (normalize) {
+                nrm = 0;
+                for (int64_t i = 0; i <= s; ++i) {
+                    R v = FN(cabs1)(wr[i], wi[i]);
+                    if (v > nrm) nrm = v;
+                }
+                if (nrm == 0) nrm = 1;
+            }
+            for (int64_t i = 0; i <= s; ++i) {
+                Z[2 * (i + s * ldz)] = (double)(wr[i] / nrm);
+                Z[2 * (i + s * ldz) + 1] = (double)(wi[i] / nrm);
+            }
+            scales[s] = normalize ? 0 : (int32_t)k;
+        }
+        free(wr);
+        free(wi);
+    }
+    return tinfo;
+}
+#undef CRE
+#undef CIM

@@ -227,3 +227,49 @@ def batch_sizes(count: int = 512, lo: int = 64, hi: int = 2048, seed: int = 3999
     """Sizes m_i ~ U{lo..hi} of a batch of independent pencils."""
     rng = _stream(seed, 0)
     return rng.integers(lo, hi + 1, size=count)
+
+
+COMPLEX_KINDS = ("complex", "complex_stress", "complex_realeig")
+
+
+def complex_schur_pencil(m: int, seed: int, kind: str = "complex", ld: int | None = None):
+    """Return (S, T): complex upper-triangular pencils (a complex generalized Schur form, the
+    pencils of the conclusion's complex-arithmetic extension: no 2x2 blocks), complex128,
+    column-major (Fortran order), shape (m, m); with ``ld`` > m they are views of (ld, m)
+    buffers.
+
+    Recipe: column j has its own Philox stream keyed by (seed, j + 1), drawing in order
+    s_jj = N(0,1) + i N(0,1); |t_jj| ~ U[0.5, 2] and its phase ~ U[0, 2 pi); then the real and
+    imaginary parts of S[0:j, j] (N(0,1) each), then those of T[0:j, j].  Kinds:
+    * "complex_stress": |t_jj| = 10**U[-12, -6] and every off-diagonal entry times 1e100 (the
+      overflow-stress recipe of the real pencils);
+    * "complex_realeig": every third column (j % 3 == 1) keeps only the real parts of s_jj and
+      of t_jj = |t_jj| (phase 0), so that its eigenvalue s_jj / t_jj is exactly real (and
+      distinct almost surely).
+    Entries below the diagonal are zero."""
+    if kind not in COMPLEX_KINDS:
+        raise ValueError(f"kind must be one of {COMPLEX_KINDS}")
+    ld = max(m, 1) if ld is None else int(ld)
+    if ld < max(m, 1):
+        raise ValueError("ld must be >= m")
+    Sb = np.zeros((ld, m), dtype=np.complex128, order="F")
+    Tb = np.zeros((ld, m), dtype=np.complex128, order="F")
+    S, T = Sb[:m], Tb[:m]
+    stress = kind == "complex_stress"
+    for j in range(m):
+        rng = _stream(seed, j + 1)
+        s = complex(rng.standard_normal(), rng.standard_normal())
+        mag = 10.0 ** rng.uniform(-12.0, -6.0) if stress else rng.uniform(0.5, 2.0)
+        ph = rng.uniform(0.0, 2.0 * np.pi)
+        t = mag * complex(np.cos(ph), np.sin(ph))
+        if kind == "complex_realeig" and j % 3 == 1:
+            s, t = complex(s.real, 0.0), complex(mag, 0.0)
+        S[j, j] = s
+        T[j, j] = t
+        if j > 0:
+            sr, si = rng.standard_normal(j), rng.standard_normal(j)
+            tr, ti = rng.standard_normal(j), rng.standard_normal(j)
+            scale = 1e100 if stress else 1.0
+            S[:j, j] = (sr + 1j * si) * scale
+            T[:j, j] = (tr + 1j * ti) * scale
+    return S, T
