@@ -182,6 +182,27 @@ int rtgevc_left(int64_t m, const double *S, int64_t lds, const double *T, int64_
                 const int32_t *select, double *Y, int64_t ldy, int32_t *scales, int32_t *info,
                 void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream);
 
+/* Complex-arithmetic pencils (the conclusion's extension of the method, Section 7): S and T
+ * complex upper triangular of order m (no 2x2 blocks), stored column-major with the real and
+ * imaginary parts of each entry interleaved (C99 double complex / std::complex<double>);
+ * lds, ldt, ldz count complex entries.  For every selected eigenvalue k (lambda = s_kk / t_kk)
+ * column k of Z receives the eigenvector z, (beta S - alpha T) z = 0, with z_k = 1 before
+ * normalisation (the phase), rows below k zero; with normalisation max_i |Re z_i| + |Im z_i| = 1
+ * and scales 0, else z = 2^scales[k] Z[:, k].  select: device int32[m] or NULL (all).
+ * The call scales each row of (S, T) by conj(t_ii) 2^-e (right eigenvectors unchanged, the
+ * diagonal of T becomes real) and solves the real form of order 2m, each complex entry
+ * x + i y as the block [[x, -y], [y, x]], with the real path (its tile size, band, schedule and
+ * precision options apply to order 2m; the mixed mode's refinement too); a complex eigenvalue
+ * is then a 2x2 block of the real form, an exactly real one two 1x1 blocks, and the complex
+ * eigenvector is read back from the real one.  Robustness, info bits and return codes as for
+ * rtgevc() (-11/-12: workspace NULL, misaligned or below
+ * rtgevc_complex_workspace_size(m, opts): rtgevc's workspace for order 2m plus 96 m^2 + 16 m
+ * bytes for the real form and its eigenvectors). */
+size_t rtgevc_complex_workspace_size(int64_t m, const rtgevc_opts *opts);
+int rtgevc_complex(int64_t m, const double *S, int64_t lds, const double *T, int64_t ldt,
+                   const int32_t *select, double *Z, int64_t ldz, int32_t *scales, int32_t *info,
+                   void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream);
+
 /* Back-transformation to the eigenvectors of the original pencil (the step after the
  * path).  With the real Schur decomposition S = U^T A V, T = U^T B V of Section 1 (U, V
  * orthogonal, (S, T) the real Schur pencil given to rtgevc), S z = lambda T z gives

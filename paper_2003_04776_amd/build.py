@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librtgevc.so")
 SOURCES = ["api.hip", "preprocess.hip", "solve.hip", "update.hip", "update_i8.hip", "walker.hip", "consolidate.hip",
-           "backtransform.hip", "left.hip", "refine.hip"]
+           "backtransform.hip", "left.hip", "refine.hip", "complex.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

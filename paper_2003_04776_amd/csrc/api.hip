@@ -17,6 +17,7 @@
 
 #include "rtgevc.h"
 #include "back.hpp"
+#include "complex.hpp"
 #include "layout.hpp"
 #include "schedule.hpp"
 #include "slices.hpp"
@@ -41,6 +42,8 @@ void launch_refine_setup(const PencilDesc& P, const RefineDesc& R, hipStream_t s
 void launch_refine_estimate(const PencilDesc& P, const RefineDesc& R, int pass, bool final_pass, hipStream_t s);
 void launch_refine_residual(const PencilDesc& P, const RefineDesc& R, hipStream_t s);
 void launch_refine_apply(const PencilDesc& P, const RefineDesc& R, hipStream_t s);
+void launch_complex_realify(const ComplexDesc& C, hipStream_t s);
+void launch_complex_extract(const ComplexDesc& C, hipStream_t s);
 }  // namespace rgev
 
 using namespace rgev;
@@ -469,10 +472,11 @@ hipError_t enqueue_refine(const PencilDesc& P, const RefineDesc& R, int sweeps, 
 hipError_t enqueue_right(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt,
                          const int32_t* select, double* Z, int64_t ldz, int32_t* scales, int32_t* info,
                          void* work, const rtgevc_opts* opts, hipStream_t s, PencilDesc* out,
-                         bool one_stream = false) {
+                         bool one_stream = false, int cform = 0) {
   if (resolve_schedule(m, opts) == 2) {
     WalkDesc W;
     PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts, &W);
+    P.cform = cform;
     *out = P;
     launch_preprocess(P, s);
     hipError_t err = launch_walk(P, W, s);
@@ -481,6 +485,7 @@ hipError_t enqueue_right(int64_t m, const double* S, int64_t lds, const double* 
   }
   RefineDesc R;
   PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts, nullptr, &R);
+  P.cform = cform;
   *out = P;
   const int sweeps = resolve_sweeps(opts);
   if (one_stream) {
@@ -585,6 +590,64 @@ int rtgevc_noalloc(int64_t m, const double* S, int64_t lds, const double* T, int
   PencilDesc P;
   return hip_code(enqueue_right(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts,
                                 static_cast<hipStream_t>(stream), &P, /*one_stream=*/true));
+}
+
+size_t rtgevc_complex_workspace_size(int64_t m, const rtgevc_opts* opts) {
+  if (m < 0) return 0;
+  if (m == 0) return kAlign;
+  const size_t n2 = (size_t)(2 * m) * (size_t)(2 * m);
+  return rtgevc_workspace_size(2 * m, opts) + 3 * up(n2 * sizeof(double)) + 2 * up((size_t)(2 * m) * sizeof(int32_t));
+}
+
+int rtgevc_complex(int64_t m, const double* S, int64_t lds, const double* T, int64_t ldt, const int32_t* select,
+                   double* Z, int64_t ldz, int32_t* scales, int32_t* info, void* work, size_t work_bytes,
+                   const rtgevc_opts* opts, void* stream) {
+  const int64_t lo = m > 1 ? m : 1;
+  if (m < 0) return -1;
+  if (m > 0 && !S) return -2;
+  if (lds < lo) return -3;
+  if (m > 0 && !T) return -4;
+  if (ldt < lo) return -5;
+  if (m > 0 && !Z) return -7;
+  if (ldz < lo) return -8;
+  if (!opts_ok(opts)) return -13;
+  if (m == 0) return 0;
+  if (!work || (reinterpret_cast<uintptr_t>(work) % kAlign) != 0) return -11;
+  if (work_bytes < rtgevc_complex_workspace_size(m, opts)) return -12;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t m2 = 2 * m;
+  const size_t n2 = (size_t)m2 * (size_t)m2;
+  // [the real path's workspace for order 2m][S2][T2][Z2][sel2][scales2]
+  char* base = static_cast<char*>(work);
+  size_t off = rtgevc_workspace_size(m2, opts);
+  ComplexDesc C;
+  memset(&C, 0, sizeof(C));
+  C.m = m;
+  C.lds = lds;
+  C.ldt = ldt;
+  C.ldz = ldz;
+  C.S = S;
+  C.T = T;
+  C.Z = Z;
+  C.scales = scales;
+  C.select = select;
+  C.S2 = reinterpret_cast<double*>(base + off);
+  off += up(n2 * sizeof(double));
+  C.T2 = reinterpret_cast<double*>(base + off);
+  off += up(n2 * sizeof(double));
+  C.Z2 = reinterpret_cast<double*>(base + off);
+  off += up(n2 * sizeof(double));
+  C.sel2 = reinterpret_cast<int32_t*>(base + off);
+  off += up((size_t)m2 * sizeof(int32_t));
+  C.scales2 = reinterpret_cast<int32_t*>(base + off);
+  C.normalize = opts ? opts->normalize : 1;
+  launch_complex_realify(C, s);
+  PencilDesc P;
+  hipError_t err = enqueue_right(m2, C.S2, m2, C.T2, m2, C.sel2, C.Z2, m2, C.scales2, info, work, opts, s, &P,
+                                 false, /*cform=*/1);
+  launch_complex_extract(C, s);
+  if (err == hipSuccess) err = hipGetLastError();
+  return hip_code(err);
 }
 
 size_t rtgevc_left_workspace_size(int64_t m, const rtgevc_opts* opts) {

@@ -82,6 +82,10 @@ struct PencilDesc {
   // correction is zero, and only tile columns j with tflag[j] != 0 are solved and updated
   int32_t* tflag;     // [Mmax], read in correction mode only
   int32_t rhs;
+  // the real form of a complex pencil (complex.hip): every 2x2 diagonal block is
+  // [[a, -b], [b, a]] with T block c I, and a complex column's vector lies in one of the two
+  // invariant subspaces of the form, so its 2x2 blocks are solved as complex 1x1 systems
+  int32_t cform;
   int32_t mb;
   int32_t Mmax;
   int32_t normalize;

@@ -126,6 +126,29 @@ __device__ __forceinline__ void solve2(double a, double b, double be, double s00
   y1 = jp ? w1 : w2;
 }
 
+// The real form of a complex pencil (PencilDesc::cform): a complex column's vector is
+// v (x) (1, -sg i), so on the 2x2 block [[a_j, -b_j], [b_j, a_j]] (T block c_j I) it is the
+// complex 1x1 system (beta (a_j + sg i b_j) - alpha c_j) w = y0 + sg i y1 over 2 (the part of
+// (y0, y1) in that subspace), with (y0, y1) = (w, -sg i w); solving it so keeps the other
+// subspace, whose pivot beta (a_j - sg i b_j) - alpha c_j may be nearly singular when alpha/beta
+// is close to the conjugate of eigenvalue j, at zero.
+__device__ __forceinline__ void solve2c(double a, double b, double be, double aj, double bj, double cj, double sg,
+                                        Cx& y0, Cx& y1, int& qs, int& flags) {
+  // y0 + sg i y1 = (y0.r - sg y1.i) + i (y0.i + sg y1.r)
+  const Cx cv = cx(0.5 * (y0.r - sg * y1.i), 0.5 * (y0.i + sg * y1.r));
+  Cx d = cx(be * aj - a * cj, be * sg * bj - b * cj);
+  const double smin = local_smin(be, fabs(a) + fabs(b), fmax(fabs(aj), fabs(bj)), fabs(cj));
+  if (cn1(d) < smin) {
+    d = cx(smin, 0.0);
+    flags |= kInfoPerturbed;
+  }
+  const int q = with_margin(protect_division(cn1(cv), 0.5 * cn1(d)));
+  qs += q;
+  const Cx w = cdivx(cscl(cv, q), d);
+  y0 = w;
+  y1 = cx(sg * w.i, -sg * w.r);   // -sg i w
+}
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int solve_threads(int mb) { return mb < 64 ? 64 : mb; }
@@ -238,6 +261,9 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
   const bool owner = selected && kind != 2;
   const int pc = (kind == 2 ? tcol - 1 : tcol) + (c0 - r0);   // local row of own block (tip tile)
   const double aabs = fabs(a) + fabs(b);
+  // real form of a complex pencil: the subspace of a complex column, from the sign of the
+  // sub-diagonal of its own 2x2 block (its eigenvalue (a + i b) / c has b of that sign)
+  const double csg = (P.cform && pair) ? (P.S[(c + 1) + c * P.lds] > 0.0 ? 1.0 : -1.0) : 0.0;
   int e = 0;
   double ybound = 0.0;
   int flags = 0;
@@ -359,6 +385,10 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
         if (tip && q0 == pc) {
           if (P.rhs) {
             // correction mode: the correction is zero at the tip (z0 = z1 = 0)
+          } else if (csg != 0.0) {
+            // real form of a complex pencil: the tip in the column's subspace, (sg i, 1), exactly
+            z0 = cx(0.0, csg);
+            z1 = cx(1.0, 0.0);
           } else if (nb == 1) {
             z0 = cx(1.0, 0.0);
           } else {
@@ -380,8 +410,11 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
         } else {
           z0 = stk[1];
           z1 = stk[0];
-          solve2(a, b, be, Sg[lq0][lq0], Sg[lq0][lq], Sg[lq][lq0], Sg[lq][lq], Tg[lq0][lq0], Tg[lq0][lq],
-                 Tg[lq][lq], z0, z1, qs, flags);
+          if (csg != 0.0)
+            solve2c(a, b, be, Sg[lq0][lq0], Sg[lq][lq0], Tg[lq0][lq0], csg, z0, z1, qs, flags);
+          else
+            solve2(a, b, be, Sg[lq0][lq0], Sg[lq0][lq], Sg[lq][lq0], Sg[lq][lq], Tg[lq0][lq0], Tg[lq0][lq],
+                   Tg[lq][lq], z0, z1, qs, flags);
         }
         if (q0 > 0) {
           // ProtectUpdate for y[0:q0] -= (beta S - alpha T)[0:q0, q0..q] z (inside the group

@@ -57,6 +57,10 @@ def load():
     L.rtgevc_workspace_size.argtypes = [i64, op]
     L.rtgevc.restype = ctypes.c_int
     L.rtgevc.argtypes = [i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, vp, sz, op, vp]
+    L.rtgevc_complex_workspace_size.restype = sz
+    L.rtgevc_complex_workspace_size.argtypes = [i64, op]
+    L.rtgevc_complex.restype = ctypes.c_int
+    L.rtgevc_complex.argtypes = [i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, vp, sz, op, vp]
     L.rtgevc_noalloc.restype = ctypes.c_int
     L.rtgevc_noalloc.argtypes = [i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, op, vp]
     L.rtgevc_eigvals.restype = ctypes.c_int
@@ -90,7 +94,7 @@ EXPORTED = ("rtgevc_workspace_size", "rtgevc", "rtgevc_eigvals", "rtgevc_timed",
             "rtgevc_batched_workspace_size", "rtgevc_batched", "rtgevc_left_workspace_size", "rtgevc_left",
             "rtgevc_backtransform_workspace_size",
             "rtgevc_backtransform", "rtgevc_resolve_opts", "rtgevc_strerror", "rtgevc_version",
-            "rtgevc_noalloc")
+            "rtgevc_noalloc", "rtgevc_complex_workspace_size", "rtgevc_complex")
 NOALLOC_SCRATCH_BYTES = 64 << 20   # RTGEVC_NOALLOC_SCRATCH_BYTES
 ERR_SCRATCH = -2000                # RTGEVC_ERR_SCRATCH
 TIMED_NSTATS = 14
@@ -302,6 +306,72 @@ def tgevc_noalloc(S, T, select=None, normalize: bool = True, mb: int = 0, band: 
                                ctypes.byref(o), _stream_ptr(stream))
     _check(rc, "rtgevc_noalloc")
     return Result(Z, scales[:m], info)
+
+
+def _cld(A, m: int) -> int:
+    import torch
+    if A.dtype != torch.complex128 or A.dim() != 2 or A.device.type != "cuda":
+        raise ValueError("expected a complex128 CUDA matrix")
+    if tuple(A.shape) != (m, m):
+        raise ValueError(f"expected shape ({m}, {m}), got {tuple(A.shape)}")
+    if m > 1 and A.stride(0) != 1:
+        raise ValueError("expected a column-major matrix (stride(0) == 1)")
+    return max(A.stride(1), m, 1) if m > 1 else max(m, 1)
+
+
+def ccolmajor_to_device(A: np.ndarray, device="cuda", ld: int | None = None):
+    """Copy a column-major complex numpy matrix to a column-major complex128 device tensor."""
+    import torch
+    m, n = A.shape
+    ld = m if ld is None else ld
+    buf = torch.zeros((n, ld), dtype=torch.complex128, device=device)
+    buf[:, :m] = torch.from_numpy(np.ascontiguousarray(A.T))
+    return buf.t()[:m]
+
+
+class ComplexSolver:
+    """Eigenvectors of complex upper-triangular pencils of order m (rtgevc_complex), holding
+    the workspace (one torch allocation, made once)."""
+
+    def __init__(self, m: int, mb: int = 0, normalize: bool = True, band: int = 0, device="cuda",
+                 schedule: int = 0, precision: int = 0, max_refine: int = 0, refine_bits: int = 0):
+        import torch
+        self.m = int(m)
+        self.opts = make_opts(mb, normalize, band, schedule, 0, precision, max_refine, refine_bits)
+        self.nbytes = int(load().rtgevc_complex_workspace_size(self.m, ctypes.byref(self.opts)))
+        self.work = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
+        self.device = device
+
+    def run(self, S, T, select=None, Z=None, scales=None, info=None, stream=None) -> Result:
+        import torch
+        m = self.m
+        lds, ldt = _cld(S, m), _cld(T, m)
+        if Z is None:
+            Z = torch.empty((m, max(m, 1)), dtype=torch.complex128, device=self.device).t()[:m]
+        ldz = _cld(Z, m)
+        if scales is None:
+            scales = torch.empty(max(m, 1), dtype=torch.int32, device=self.device)
+        if info is None:
+            info = torch.zeros(1, dtype=torch.int32, device=self.device)
+        sel = None
+        if select is not None:
+            sel = torch.as_tensor(select, dtype=torch.int32, device=self.device).contiguous()
+            if sel.shape != (m,):
+                raise ValueError("select must have length m")
+        rc = load().rtgevc_complex(m, S.data_ptr(), lds, T.data_ptr(), ldt,
+                                   sel.data_ptr() if sel is not None else None,
+                                   Z.data_ptr(), ldz, scales.data_ptr(), info.data_ptr(),
+                                   self.work.data_ptr(), self.nbytes, ctypes.byref(self.opts),
+                                   _stream_ptr(stream))
+        _check(rc, "rtgevc_complex")
+        return Result(Z, scales[:m], info)
+
+
+def tgevc_complex(S, T, select=None, normalize: bool = True, mb: int = 0, band: int = 0, stream=None,
+                  schedule: int = 0, precision: int = 0) -> Result:
+    """All (or the selected) right eigenvectors of a complex upper-triangular pencil (S, T)."""
+    return ComplexSolver(S.shape[0], mb=mb, normalize=normalize, band=band, device=S.device,
+                         schedule=schedule, precision=precision).run(S, T, select, stream=stream)
 
 
 def _i64_array(vals):

@@ -221,3 +221,28 @@ def test_noalloc_argument_errors_and_scratch_limit():
     mixed = rt.make_opts(precision=1)
     assert rt.workspace_size(4096, precision=1) > rt.NOALLOC_SCRATCH_BYTES
     assert call(m=4096, lds=4096, ldt=4096, ldz=4096, opts=mixed) == rt.ERR_SCRATCH
+
+
+def test_complex_workspace_and_argument_errors():
+    lib = rt.load()
+    o = rt.make_opts()
+    n = int(lib.rtgevc_complex_workspace_size(100, ctypes.byref(o)))
+    assert n >= rt.workspace_size(200) + 3 * 8 * 200 * 200
+    assert lib.rtgevc_complex_workspace_size(-1, ctypes.byref(o)) == 0
+
+    def call(m=4, S=1, lds=4, T=1, ldt=4, Z=1, ldz=4, work=256, nbytes=None, opts=o):
+        nb = int(lib.rtgevc_complex_workspace_size(max(m, 0), ctypes.byref(opts))) if nbytes is None else nbytes
+        return lib.rtgevc_complex(m, S, lds, T, ldt, None, Z, ldz, None, None, work, nb, ctypes.byref(opts), None)
+
+    assert call(m=-1) == -1
+    assert call(S=None) == -2
+    assert call(lds=3) == -3
+    assert call(T=None) == -4
+    assert call(ldt=3) == -5
+    assert call(Z=None) == -7
+    assert call(ldz=3) == -8
+    assert call(work=None) == -11
+    assert call(work=257) == -11
+    assert call(nbytes=16) == -12
+    assert call(opts=rt.make_opts(mb=48)) == -13
+    assert call(m=0, S=None, T=None, Z=None, lds=1, ldt=1, ldz=1) == 0
