@@ -310,6 +310,35 @@ def bench_back(args, m, Sd, Zf, scales, blk):
     return res
 
 
+def bench_complex(args, mc):
+    """All eigenvectors of a complex upper-triangular pencil of order mc (rtgevc_complex: the
+    real form of order 2 mc through the real path), timed with events around each call.
+    Complex-arithmetic flop count 8 mc^3 / 3 (a complex multiply-add is 8 real flops)."""
+    import numpy as np
+    import torch
+    from paper_2003_04776_amd import pencils
+    from paper_2003_04776_amd import rtgevc as rt
+    log(f"[bench] complex pencil of order {mc}")
+    S, T = pencils.complex_schur_pencil(mc, args.seed + 7, threads=16)
+    Sd, Td = rt.ccolmajor_to_device(S), rt.ccolmajor_to_device(T)
+    del S, T
+    sv = rt.ComplexSolver(mc, mb=args.mb, band=args.band)
+    Z = torch.empty((mc, mc), dtype=torch.complex128, device="cuda").t()
+    sc = torch.empty(mc, dtype=torch.int32, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ms, _ = time_calls(lambda: sv.run(Sd, Td, Z=Z, scales=sc, info=info), args.steps, args.warmup)
+    F = 8.0 * mc ** 3 / 3.0
+    res = {"what": f"all eigenvectors of a complex upper-triangular pencil of order {mc}, FP64, normalised "
+                   f"(its real form of order {2 * mc} through the real path)",
+           "ms_per_call": round(ms, 3), "flops_per_call": F,
+           "value": round(F / (ms * 1e-3) / 1e12, 4), "unit": "TFLOP/s (complex-arithmetic count 8 m^3/3)",
+           "info": int(info.item())}
+    log(f"[bench] complex: {ms:.1f} ms per call")
+    del sv, Z, Sd, Td
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,6 +359,8 @@ def main():
                     help="skip the left eigenvectors timed after the right ones")
     ap.add_argument("--no-back", dest="back", action="store_false",
                     help="skip the back-transformation X = V Z timed after the eigenvectors")
+    ap.add_argument("--no-complex", dest="complex", action="store_false",
+                    help="skip the complex pencil of order m / 2 timed after the real one")
     ap.add_argument("--seed", type=int, default=400)
     ap.add_argument("--kind", default="normal", choices=("normal", "stress", "zeroinf", "degenerate", "general", "unbalanced"))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -516,6 +547,8 @@ def main():
         out["left"] = bench_left(args, m, Sd, Td, F, float(np.median(dev_ms)))
     if args.back:
         out["backtransform"] = bench_back(args, m, Sd, Zf, scales, blk)
+    if args.complex and args.precision == 0:
+        out["complex"] = bench_complex(args, m // 2)
     if rank == 0 and not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a column sample")
         out["cpu_baseline"], idx, Zo = cpu_baseline(S, T, blk, m, args.cpu_seconds)

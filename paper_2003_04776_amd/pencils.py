@@ -232,7 +232,8 @@ def batch_sizes(count: int = 512, lo: int = 64, hi: int = 2048, seed: int = 3999
 COMPLEX_KINDS = ("complex", "complex_stress", "complex_realeig")
 
 
-def complex_schur_pencil(m: int, seed: int, kind: str = "complex", ld: int | None = None):
+def complex_schur_pencil(m: int, seed: int, kind: str = "complex", ld: int | None = None,
+                         threads: int = 1):
     """Return (S, T): complex upper-triangular pencils (a complex generalized Schur form, the
     pencils of the conclusion's complex-arithmetic extension: no 2x2 blocks), complex128,
     column-major (Fortran order), shape (m, m); with ``ld`` > m they are views of (ld, m)
@@ -246,7 +247,8 @@ def complex_schur_pencil(m: int, seed: int, kind: str = "complex", ld: int | Non
     * "complex_realeig": every third column (j % 3 == 1) keeps only the real parts of s_jj and
       of t_jj = |t_jj| (phase 0), so that its eigenvalue s_jj / t_jj is exactly real (and
       distinct almost surely).
-    Entries below the diagonal are zero."""
+    Entries below the diagonal are zero.  ``threads`` > 1 fills the columns from that many
+    threads (same values: every column has its own stream)."""
     if kind not in COMPLEX_KINDS:
         raise ValueError(f"kind must be one of {COMPLEX_KINDS}")
     ld = max(m, 1) if ld is None else int(ld)
@@ -256,7 +258,19 @@ def complex_schur_pencil(m: int, seed: int, kind: str = "complex", ld: int | Non
     Tb = np.zeros((ld, m), dtype=np.complex128, order="F")
     S, T = Sb[:m], Tb[:m]
     stress = kind == "complex_stress"
-    for j in range(m):
+    if threads > 1 and m >= 2048:
+        from concurrent.futures import ThreadPoolExecutor
+        chunk = 256
+        with ThreadPoolExecutor(max_workers=int(threads)) as ex:
+            list(ex.map(lambda j0: _fill_complex(S, T, seed, kind, j0, min(j0 + chunk, m)), range(0, m, chunk)))
+    else:
+        _fill_complex(S, T, seed, kind, 0, m)
+    return S, T
+
+
+def _fill_complex(S, T, seed: int, kind: str, j0: int, j1: int) -> None:
+    stress = kind == "complex_stress"
+    for j in range(j0, j1):
         rng = _stream(seed, j + 1)
         s = complex(rng.standard_normal(), rng.standard_normal())
         mag = 10.0 ** rng.uniform(-12.0, -6.0) if stress else rng.uniform(0.5, 2.0)
@@ -272,4 +286,3 @@ def complex_schur_pencil(m: int, seed: int, kind: str = "complex", ld: int | Non
             scale = 1e100 if stress else 1.0
             S[:j, j] = (sr + 1j * si) * scale
             T[:j, j] = (tr + 1j * ti) * scale
-    return S, T

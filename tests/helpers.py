@@ -163,3 +163,29 @@ def backward_errors(S, T, Z, ar, ai, be, kind=None):
             out[c] = float(np.abs(r).sum() / den) if den > 0 else 0.0
             c += 1
     return out
+
+
+def backward_errors_torch(S, T, Z, ar, ai, be, kind):
+    """backward_errors for every eigenvalue at once on the GPU (S, T, Z column-major torch
+    FP64 tensors on one device; ar, ai, be, kind numpy).  Returns a numpy array of omega."""
+    import torch
+    dev = Z.device
+    kind = np.asarray(kind)
+    first = np.nonzero(kind != 2)[0]
+    pair = kind[first] == 1
+    a = torch.from_numpy(np.asarray(ar, dtype=float)[first]).to(dev)
+    b = torch.from_numpy(np.where(pair, np.asarray(ai, dtype=float)[first], 0.0)).to(dev)
+    bt = torch.from_numpy(np.asarray(be, dtype=float)[first]).to(dev)
+    fi = torch.from_numpy(first).to(dev)
+    nx = torch.from_numpy(np.where(pair, first + 1, first)).to(dev)
+    pm = torch.from_numpy(pair).to(dev)
+    SZ, TZ = S @ Z, T @ Z
+    rx = bt * SZ[:, fi] - a * TZ[:, fi] + b * TZ[:, nx]
+    ry = torch.where(pm, bt * SZ[:, nx] - b * TZ[:, fi] - a * TZ[:, nx], torch.zeros_like(rx))
+    num = rx.abs().sum(dim=0) + ry.abs().sum(dim=0)
+    del SZ, TZ, rx, ry
+    aZ = Z.abs()
+    az = aZ[:, fi] + torch.where(pm, aZ[:, nx], torch.zeros_like(aZ[:, fi]))
+    del aZ
+    den = bt * (S.abs() @ az).sum(dim=0) + (a.abs() + b.abs()) * (T.abs() @ az).sum(dim=0)
+    return (num / torch.where(den > 0, den, torch.ones_like(den))).cpu().numpy()

@@ -85,6 +85,21 @@ def test_parity_small(m, mb, seed):
     assert max(eta.values()) <= 64 * m * U
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_order_256_seeds(seed):
+    """The order-256 workload on its five seeds: every column against the oracle, the
+    normwise residual and the componentwise backward error of every column."""
+    from helpers import backward_errors
+    S, T, blk = pencils.schur_pencil(256, seed)
+    Zg, sc, info = run_gpu(S, T)
+    assert info == 0
+    worst, errs, nill = compare(S, T, Zg)
+    assert worst <= TOL and nill <= 2
+    ar, ai, be, _ = oracle.eigvals(S, T)
+    assert max(residuals(S, T, Zg, ar, ai, be).values()) <= 64 * 256 * U
+    assert max(backward_errors(S, T, Zg, ar, ai, be).values()) <= 16 * U
+
+
 @pytest.mark.parametrize("m,mb,seed,kind,precision", [(300, 64, 40, "zeroinf", 0), (700, 128, 41, "zeroinf", 0),
                                                       (701, 128, 42, "zeroinf", 1), (1000, 64, 43, "degenerate", 0),
                                                       (1000, 128, 44, "degenerate", 1)])
@@ -316,8 +331,22 @@ def _full_size(m, seed, kind, nsample, mb=0, precision=0):
     eta = residuals_torch(Sd, Td, Z, ar, ai, be, blk)
     _say(f"   max eta {eta.max():.3e} bound {64 * m * U:.3e}")
     assert eta.max() <= 64 * m * U
+    # the componentwise backward error of every column (a check that the normwise residual,
+    # dominated by the largest entries of S and T, cannot make): an FP64 substitution keeps
+    # it at a few units of roundoff
+    from helpers import backward_errors_torch
+    om = backward_errors_torch(Sd, Td, Z, ar, ai, be, blk)
+    _say(f"   backward error: median {np.median(om):.2e} max {om.max():.2e}")
+    assert om.max() <= 16 * U
     # oracle on a deterministic sample of columns spread over the range
     cols = sorted(set(np.linspace(0, m - 1, nsample).astype(int).tolist()))
+    if precision == 1:
+        # plus the columns where the mixed result differs most from the FP64 one
+        Zf = rt.Solver(m, mb=mb).run(Sd, Td).Z
+        torch.cuda.synchronize()
+        top = torch.topk((Z - Zf).abs().amax(dim=0), 8).indices.cpu().numpy()
+        del Zf
+        cols = sorted(set(cols) | set(int(c) for c in top))
     sel = np.zeros(m, dtype=np.int32)
     sel[cols] = 1
     Zo, _, _ = oracle.tgevc(S, T, select=sel)
