@@ -51,6 +51,24 @@ __device__ __forceinline__ int protect_update(double t, double x, double y) {
   return q > 0 ? q : 0;
 }
 
+// The same two functions with the common case decided by one comparison, and the exact
+// function evaluated only where that fails on an active lane (inactive lanes get 0):
+//  - division: b <= t 2^1020 is the first exit of protect_division (for t >= 1 the scaled
+//    t is at least 2^1020, or infinite, and protect_division returns 0 as well);
+//  - update: fl(t x + y) <= 2^1019 bounds the exact sum by 2^1019 (1 + 2^-52) < Omega
+//    (1 - 2^-50), where protect_update returns 0 as well (an overflowing t x gives infinity
+//    and takes the exact path).
+__device__ __forceinline__ int protect_division_fast(double b, double t, bool active = true) {
+  int q = 0;
+  if (active && !(b <= ldexp(t, kOmegaExp))) q = protect_division(b, t);
+  return q;
+}
+__device__ __forceinline__ int protect_update_fast(double t, double x, double y, bool active = true) {
+  int q = 0;
+  if (active && !(fma(t, x, y) <= 0x1p1019)) q = protect_update(t, x, y);
+  return q;
+}
+
 // 1/x from the hardware reciprocal estimate refined by two Newton-Raphson steps
 // (r <- r + r (1 - x r); each step squares the relative error), for normal x whose
 // reciprocal is normal: the divisions of the diagonal solves, whose divisors are at least
@@ -61,34 +79,6 @@ __device__ __forceinline__ double recip(double x) {
   r = fma(r, fma(-x, r, 1.0), r);
   r = fma(r, fma(-x, r, 1.0), r);
   return r;
-}
-
-// Complex quotient (a + ib) / (c + id) by Smith's method, with the refinements of
-// Baudin & Smith (2012) for intermediate products that underflow.  Requires |d| <= |c|.
-__device__ __forceinline__ void smith_core(double a, double b, double c, double d, double& e, double& f) {
-  const double r = d * recip(c);
-  const double t = recip(c + d * r);
-  if (r != 0.0 || d == 0.0) {
-    // (d == 0 lands here too: r = 0 and the products with r vanish)
-    const double br = b * r;
-    e = (br != 0.0) ? (a + br) * t : a * t + (b * t) * r;
-    const double ar = a * r;
-    f = (ar != 0.0) ? (b - ar) * t : b * t - (a * t) * r;
-  } else {
-    // d / c underflowed
-    e = (a + d * (b / c)) * t;
-    f = (b - d * (a / c)) * t;
-  }
-}
-
-// The larger of |c|, |d| goes to the divisor's real slot; the swap is done with
-// selects so lanes with different orderings share one instruction stream.
-__device__ __forceinline__ void complex_div(double a, double b, double c, double d, double& e, double& f) {
-  const bool sw = fabs(d) > fabs(c);
-  double e1, f1;
-  smith_core(sw ? b : a, sw ? a : b, sw ? d : c, sw ? c : d, e1, f1);
-  e = e1;
-  f = sw ? -f1 : f1;
 }
 
 __device__ __forceinline__ double abs1(double x, double y) { return fabs(x) + fabs(y); }

@@ -6,9 +6,14 @@
 
 namespace rgev {
 
+// Registers are capped at 256 a lane (the rank-2G update's accumulators in ordinary vector
+// registers, which the build asks for): a tile-update workgroup holds 256 a lane, so a solve
+// fits beside one of them.  A solve that needed the whole register file of its CU would wait,
+// while a large update launch runs, until none of that launch's workgroups were left to
+// start, delaying the chain of solves that every band of the schedule waits for.
 // tile row r of one pencil: tiles (r, j), j = r .. M-1
 template <int MB>
-__global__ __launch_bounds__(solve_total(MB), solve_waves_per_simd(MB)) void solve_kernel(PencilDesc P, int r) {
+__global__ __launch_bounds__(solve_total(MB), solve_waves_per_simd(MB)) __attribute__((amdgpu_num_vgpr(256))) void solve_kernel(PencilDesc P, int r) {
   constexpr int CS = SolveShape<MB>::CS;
   __shared__ SolveSmem<MB> sm;
   solve_tile<MB>(P, r, r + (int)blockIdx.x / CS, (int)blockIdx.x % CS, sm);
@@ -18,7 +23,7 @@ __global__ __launch_bounds__(solve_total(MB), solve_waves_per_simd(MB)) void sol
 // (bands of R tile rows from the top, B_p of them), the row io places above the band's
 // last row; tiles (r, j), j >= r
 template <int MB>
-__global__ __launch_bounds__(solve_total(MB), solve_waves_per_simd(MB)) void solve_batched_kernel(const PencilDesc* __restrict__ D, int R, int t, int io) {
+__global__ __launch_bounds__(solve_total(MB), solve_waves_per_simd(MB)) __attribute__((amdgpu_num_vgpr(256))) void solve_batched_kernel(const PencilDesc* __restrict__ D, int R, int t, int io) {
   constexpr int CS = SolveShape<MB>::CS;
   __shared__ SolveSmem<MB> sm;
   const PencilDesc P = D[blockIdx.y];

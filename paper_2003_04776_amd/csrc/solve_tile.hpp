@@ -31,13 +31,27 @@ __device__ __forceinline__ Cx cx(double r, double i) { return Cx{r, i}; }
 __device__ __forceinline__ Cx cmul(Cx x, Cx y) { return Cx{x.r * y.r - x.i * y.i, x.r * y.i + x.i * y.r}; }
 __device__ __forceinline__ Cx csub(Cx x, Cx y) { return Cx{x.r - y.r, x.i - y.i}; }
 __device__ __forceinline__ double cn1(Cx x) { return fabs(x.r) + fabs(x.i); }
-__device__ __forceinline__ Cx cdivx(Cx x, Cx y) {
-  Cx z;
-  complex_div(x.r, x.i, y.r, y.i, z.r, z.i);
-  return z;
+// 1/d = 2^-e r for d != 0: with d' = 2^-e d scaled so that max(|Re d'|, |Im d'|) is in
+// [1/2, 1), r = conj(d') / |d'|^2, where |d'|^2 is in [1/4, 2) (no overflow or underflow in
+// forming it) and |r| = 1/|d'| <= 2.  A quotient x / d is then 2^-e (x r): two rounded
+// products more than a correctly rounded quotient, and for |x|_1 <= Omega nothing overflows
+// before the final power of two, which the protections bound.
+struct CInv {
+  Cx r;
+  int e;
+};
+__device__ __forceinline__ CInv cinv(Cx d) {
+  int e;
+  frexp(fmax(fabs(d.r), fabs(d.i)), &e);
+  const double dr = ldexp(d.r, -e), di = ldexp(d.i, -e);
+  const double rn = recip(fma(dr, dr, di * di));
+  return CInv{Cx{dr * rn, -di * rn}, e};
 }
 // (ldexp by 0 is the identity, so no select on q is needed)
 __device__ __forceinline__ Cx cscl(Cx x, int q) { return Cx{ldexp(x.r, -q), ldexp(x.i, -q)}; }
+// x / d as 2^-(q + e) (x r) for the inverse 2^-e r of d: a protection's scale 2^-q of the
+// numerator folded into the same power of two
+__device__ __forceinline__ Cx cdiv_inv(Cx x, const CInv& v, int q = 0) { return cscl(cmul(x, v.r), q + v.e); }
 
 // When a protection has to scale, the solves scale by 2^128 more than the least
 // exponent: any power of two that meets the bound represents the same vector, and the
@@ -52,19 +66,22 @@ __device__ __forceinline__ double local_smin(double be, double aabs, double smax
   return s < kTiny ? kTiny : s;
 }
 
+// The solves below run on every lane of a wave (their control flow is uniform); act is
+// false for a lane whose result is not used, which then neither raises a flag nor runs the
+// exact path of a protection.
+
 // (beta s - alpha t) w = y for one row; alpha = a + i b (b = 0 for a real column).
 __device__ __forceinline__ Cx solve1(double a, double b, double be, double s, double t, Cx y, int& qs,
-                                     int& flags) {
+                                     int& flags, bool act) {
   Cx d = cx(be * s - a * t, -b * t);
   const double smin = local_smin(be, fabs(a) + fabs(b), fabs(s), fabs(t));
-  if (cn1(d) < smin) {
-    d = cx(smin, 0.0);
-    flags |= kInfoPerturbed;
-  }
+  const bool pert = cn1(d) < smin;
+  d = pert ? cx(smin, 0.0) : d;
+  flags |= (pert && act) ? kInfoPerturbed : 0;
   // |y/d|_1 <= 2 |y|_1 / |d|_1
-  const int q = with_margin(protect_division(cn1(y), 0.5 * cn1(d)));
+  const int q = with_margin(protect_division_fast(cn1(y), 0.5 * cn1(d), act));
   qs += q;
-  return cdivx(cscl(y, q), d);
+  return cdiv_inv(y, cinv(d), q);
 }
 
 // 2x2 block: Gaussian elimination with complete pivoting on |.|_1, every division
@@ -72,7 +89,7 @@ __device__ __forceinline__ Cx solve1(double a, double b, double be, double s, do
 // (Written with selects only, so nothing is indexed dynamically.)
 __device__ __forceinline__ void solve2(double a, double b, double be, double s00, double s01, double s10,
                                        double s11, double t00, double t01, double t11, Cx& y0, Cx& y1,
-                                       int& qs, int& flags) {
+                                       int& qs, int& flags, bool act) {
   const Cx C00 = cx(be * s00 - a * t00, -b * t00);
   const Cx C01 = cx(be * s01 - a * t01, -b * t01);
   const Cx C10 = cx(be * s10, 0.0);
@@ -81,46 +98,43 @@ __device__ __forceinline__ void solve2(double a, double b, double be, double s00
   const double tmax = fmax(fmax(fabs(t00), fabs(t01)), fabs(t11));
   const double smin = local_smin(be, fabs(a) + fabs(b), smax, tmax);
   const double v00 = cn1(C00), v01 = cn1(C01), v10 = cn1(C10), v11 = cn1(C11);
-  // pivot (ip, jp): the entry of largest |.|_1
-  int ip = 0, jp = 0;
-  double best = v00;
-  if (v01 > best) { best = v01; ip = 0; jp = 1; }
-  if (v10 > best) { best = v10; ip = 1; jp = 0; }
-  if (v11 > best) { best = v11; ip = 1; jp = 1; }
-  Cx u11, u12, c21, c22;
-  if (best < smin) {
-    u11 = cx(smin, 0.0); u12 = cx(0.0, 0.0); c21 = cx(0.0, 0.0); c22 = cx(smin, 0.0);
-    ip = 0; jp = 0;
-    flags |= kInfoPerturbed;
-  } else {
-    // rows/columns permuted so the pivot is (0, 0): u11 = C[ip][jp], u12 = C[ip][1-jp],
-    // c21 = C[1-ip][jp], c22 = C[1-ip][1-jp]
-    const Cx r0a = ip ? C10 : C00, r0b = ip ? C11 : C01;   // pivot row
-    const Cx r1a = ip ? C00 : C10, r1b = ip ? C01 : C11;   // other row
-    u11 = jp ? r0b : r0a;
-    u12 = jp ? r0a : r0b;
-    c21 = jp ? r1b : r1a;
-    c22 = jp ? r1a : r1b;
-  }
-  const Cx l21 = cdivx(c21, u11);
+  // pivot (ip, jp): the entry of largest |.|_1 (the first of equal ones)
+  const bool c01 = v01 > v00;
+  const double b0 = c01 ? v01 : v00;
+  const bool c10 = v10 > b0;
+  const double b1 = c10 ? v10 : b0;
+  const bool c11 = v11 > b1;
+  const double best = c11 ? v11 : b1;
+  const bool pert = best < smin;
+  const bool ip = !pert && (c11 || c10);
+  const bool jp = !pert && (c11 || (!c10 && c01));
+  // rows/columns permuted so the pivot is (0, 0): u11 = C[ip][jp], u12 = C[ip][1-jp],
+  // c21 = C[1-ip][jp], c22 = C[1-ip][1-jp]; a block below the threshold is replaced by smin I
+  const Cx r0a = ip ? C10 : C00, r0b = ip ? C11 : C01;   // pivot row
+  const Cx r1a = ip ? C00 : C10, r1b = ip ? C01 : C11;   // other row
+  const Cx u11 = pert ? cx(smin, 0.0) : (jp ? r0b : r0a);
+  const Cx u12 = pert ? cx(0.0, 0.0) : (jp ? r0a : r0b);
+  const Cx c21 = pert ? cx(0.0, 0.0) : (jp ? r1b : r1a);
+  const Cx c22 = pert ? cx(smin, 0.0) : (jp ? r1a : r1b);
+  const CInv i11 = cinv(u11);
+  const Cx l21 = cdiv_inv(c21, i11);
   Cx u22 = csub(c22, cmul(l21, u12));
-  if (cn1(u22) < smin) {
-    u22 = cx(smin, 0.0);
-    flags |= kInfoPerturbed;
-  }
+  const bool pert2 = cn1(u22) < smin;
+  u22 = pert2 ? cx(smin, 0.0) : u22;
+  flags |= ((pert || pert2) && act) ? kInfoPerturbed : 0;
   Cx ya = ip ? y1 : y0, yb = ip ? y0 : y1;
-  int q = with_margin(protect_update(cn1(l21), cn1(ya), cn1(yb)));
+  int q = with_margin(protect_update_fast(cn1(l21), cn1(ya), cn1(yb), act));
   ya = cscl(ya, q); yb = cscl(yb, q); qs += q;
   Cx r2 = csub(yb, cmul(l21, ya));
-  q = with_margin(protect_division(cn1(r2), 0.5 * cn1(u22)));
-  r2 = cscl(r2, q); ya = cscl(ya, q); qs += q;
-  Cx w2 = cdivx(r2, u22);
-  q = with_margin(protect_update(cn1(u12), cn1(w2), cn1(ya)));
+  q = with_margin(protect_division_fast(cn1(r2), 0.5 * cn1(u22), act));
+  ya = cscl(ya, q); qs += q;
+  Cx w2 = cdiv_inv(r2, cinv(u22), q);
+  q = with_margin(protect_update_fast(cn1(u12), cn1(w2), cn1(ya), act));
   w2 = cscl(w2, q); ya = cscl(ya, q); qs += q;
   Cx n1 = csub(ya, cmul(u12, w2));
-  q = with_margin(protect_division(cn1(n1), 0.5 * cn1(u11)));
-  n1 = cscl(n1, q); w2 = cscl(w2, q); qs += q;
-  const Cx w1 = cdivx(n1, u11);
+  q = with_margin(protect_division_fast(cn1(n1), 0.5 * cn1(u11), act));
+  w2 = cscl(w2, q); qs += q;
+  const Cx w1 = cdiv_inv(n1, i11, q);
   // unknown jp gets w1, the other gets w2
   y0 = jp ? w2 : w1;
   y1 = jp ? w1 : w2;
@@ -133,18 +147,17 @@ __device__ __forceinline__ void solve2(double a, double b, double be, double s00
 // subspace, whose pivot beta (a_j - sg i b_j) - alpha c_j may be nearly singular when alpha/beta
 // is close to the conjugate of eigenvalue j, at zero.
 __device__ __forceinline__ void solve2c(double a, double b, double be, double aj, double bj, double cj, double sg,
-                                        Cx& y0, Cx& y1, int& qs, int& flags) {
+                                        Cx& y0, Cx& y1, int& qs, int& flags, bool act) {
   // y0 + sg i y1 = (y0.r - sg y1.i) + i (y0.i + sg y1.r)
   const Cx cv = cx(0.5 * (y0.r - sg * y1.i), 0.5 * (y0.i + sg * y1.r));
   Cx d = cx(be * aj - a * cj, be * sg * bj - b * cj);
   const double smin = local_smin(be, fabs(a) + fabs(b), fmax(fabs(aj), fabs(bj)), fabs(cj));
-  if (cn1(d) < smin) {
-    d = cx(smin, 0.0);
-    flags |= kInfoPerturbed;
-  }
-  const int q = with_margin(protect_division(cn1(cv), 0.5 * cn1(d)));
+  const bool pert = cn1(d) < smin;
+  d = pert ? cx(smin, 0.0) : d;
+  flags |= (pert && act) ? kInfoPerturbed : 0;
+  const int q = with_margin(protect_division_fast(cn1(cv), 0.5 * cn1(d), act));
   qs += q;
-  const Cx w = cdivx(cscl(cv, q), d);
+  const Cx w = cdiv_inv(cv, cinv(d), q);
   y0 = w;
   y1 = cx(sg * w.i, -sg * w.r);   // -sg i w
 }
@@ -180,17 +193,20 @@ template <int MB>
 struct SolveSmem {
   static constexpr int LDY = SolveShape<MB>::LDY, BW = SolveShape<MB>::NCY, G = 8;
   double Y[MB * LDY];          // the tile's columns held by this workgroup
-  double Bop[2 * G][BW];       // [-beta z ; alpha z] of the group, own parts
-  double Sg[G][G], Tg[G][G];   // diagonal block of the group: [row][column]
-  double tcnS[MB], tcnT[MB];
-  double cmax[BW];
+  // per column: eigenvalue, block kind, whether it is solved, and the epilogue's values
   double colA[BW], colB[BW], colBe[BW];
-  int fcol[BW];                // scale exponent still owed by the rows above the group
+  double cmax[BW];
   int ecol[BW];                // exponent of the second column of a pair
   int colG[BW];
   int wexp[BW];                // mixed precision: column exponent of W (X D half)
-  int8_t tblk[MB];
   int8_t colKind[BW];
+  int8_t colOn[BW];            // 1: a selected column of the tile (its B operand is not zero)
+  // diagonal block of the group, S (Pn[0]) and T (Pn[1]), by columns: entry (row i,
+  // column c) at Pn[.][c][i], so a column's G entries are one aligned vector
+  alignas(16) double Pn[2][G][G];
+  double tcnS[MB], tcnT[MB];
+  int fcol[BW];                // scale exponent still owed by the rows above the group
+  int8_t tblk[MB];
 };
 
 // Solve of column slice z of tile (r, j) of one pencil (a workgroup of solve_total(MB)
@@ -202,9 +218,8 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
   constexpr int LDY = SolveShape<MB>::LDY;
   constexpr int G = 8;          // rows per group (recursive blocking inside the tile)
   auto& Y = sm.Y;
-  auto& Bop = sm.Bop;
-  auto& Sg = sm.Sg;
-  auto& Tg = sm.Tg;
+  auto& colOn = sm.colOn;
+  auto& Pn = sm.Pn;
   auto& tcnS = sm.tcnS;
   auto& tcnT = sm.tcnT;
   auto& fcol = sm.fcol;
@@ -269,6 +284,13 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
   int flags = 0;
 
   // ---- structure and column norms of the diagonal tile, right-hand side Y_rj ----
+  if (colthr) {
+    colA[lc] = a;
+    colB[lc] = b;
+    colBe[lc] = be;
+    colKind[lc] = (int8_t)kind;
+    colOn[lc] = (int8_t)(inrange && selected);
+  }
   if (lc < hr) {
     tblk[lc] = P.blk[r0 + lc];
     tcnS[lc] = P.cnS[r0 + lc];
@@ -296,11 +318,17 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
     }
   }
 
+  // The second rows of the tile's 2x2 blocks as two 64-bit masks, the same in every wave
+  // (scalar registers), so the block structure costs no shared-memory read in the loops.
+  __syncthreads();   // tblk visible
+  const uint64_t two_lo = __ballot(lane < hr && tblk[lane] == 2);
+  const uint64_t two_hi = __ballot(64 + lane < hr && tblk[(64 + lane) % MB] == 2);
+  auto second = [&](int i) -> bool { return ((i < 64 ? two_lo : two_hi) >> (i & 63)) & 1; };
   // groups of at most G rows from the bottom, never splitting a 2x2 block
   auto group_lo = [&](int g1) {
     int g0 = g1 - G + 1;
     if (g0 < 0) g0 = 0;
-    if (g0 > 0 && tblk[g0] == 2) ++g0;
+    if (g0 > 0 && second(g0)) ++g0;
     return g0;
   };
   // the group's diagonal block of S and T (lanes 0..63 of wave 0 hold one entry each)
@@ -317,23 +345,176 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
   };
   auto panel_publish = [&]() {
     if (wave == 0) {
-      Sg[lane / G][lane % G] = pOk ? psc * pS : 0.0;
-      Tg[lane / G][lane % G] = pOk ? psc * pT : 0.0;
+      Pn[0][lane % G][lane / G] = pOk ? psc * pS : 0.0;
+      Pn[1][lane % G][lane / G] = pOk ? psc * pT : 0.0;
     }
   };
-  __syncthreads();   // tblk visible
   int g1 = hr - 1;
   int g0 = group_lo(g1);
   panel_fetch(g0);
   panel_publish();
   __syncthreads();
 
+  static_assert(G == 8, "the group's rows are one 8-wide register vector");
+  typedef double d8 __attribute__((ext_vector_type(8)));
   while (g1 >= 0) {
     const int gn1 = g0 - 1;                       // next group
     const int gn0 = gn1 >= 0 ? group_lo(gn1) : -1;
     panel_fetch(gn0);                             // lands during this group's work
+    double yb_above = ybound;   // bound on the rows above the group
+    int qsg = 0;                // scaling raised inside the group
+    double zng = 0.0;           // largest |z|_1 of the group's solved rows (at their current scale)
+
+    // ---- blocks of the group, bottom up; updates stay inside the group ----
+    // Each column's substitution is private to the thread that owns it (a complex pair
+    // belongs to the thread of its first column), so the blocks need no barrier.  The
+    // group's rows live in registers, (yr[k], yi[k]) = row g0 + k: a block reads its rows
+    // by a uniform index, and its update is applied to all G rows with the block's full
+    // panel columns (rows at or below the block are no longer used, so nothing has to
+    // move and every other register index is a constant).  Every lane runs the solve;
+    // work marks the lanes whose result is used, and the others take z = 0, so their
+    // rows are left as they were.
+    d8 yr, yi;
+    d8 cnv;   // beta |S col|_1 + |alpha| |T col|_1 of the group's rows (zero past the group)
+    const int yc0 = lc < NCY ? lc : 0, yc1 = pair ? lc + 1 : yc0;   // (threads past the columns read column 0)
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int row = g0 + k <= g1 ? g0 + k : g1;   // (rows past the group: never used)
+      yr[k] = Y[row * LDY + yc0];
+      yi[k] = pair ? Y[row * LDY + yc1] : 0.0;
+      cnv[k] = g0 + k <= g1 ? be * tcnS[row] + aabs * tcnT[row] : 0.0;
+    }
+    const double cng = ((cnv[0] + cnv[1]) + (cnv[2] + cnv[3])) + ((cnv[4] + cnv[5]) + (cnv[6] + cnv[7]));
+    // a block's solved rows: rescale what is already solved if the block raised the
+    // scaling (rare: scaling has head room), store, and extend the group's bound
+    auto settle = [&](int q0, int q, int qs, Cx z0, Cx z1, double cn) {
+      if (qs > 0) {
+        yr = d8{ldexp(yr[0], -qs), ldexp(yr[1], -qs), ldexp(yr[2], -qs), ldexp(yr[3], -qs),
+                ldexp(yr[4], -qs), ldexp(yr[5], -qs), ldexp(yr[6], -qs), ldexp(yr[7], -qs)};
+        yi = d8{ldexp(yi[0], -qs), ldexp(yi[1], -qs), ldexp(yi[2], -qs), ldexp(yi[3], -qs),
+                ldexp(yi[4], -qs), ldexp(yi[5], -qs), ldexp(yi[6], -qs), ldexp(yi[7], -qs)};
+        for (int i = q + 1; i <= g1; ++i) {
+          Y[i * LDY + lc] = ldexp(Y[i * LDY + lc], -qs);
+          if (pair) Y[i * LDY + lc + 1] = ldexp(Y[i * LDY + lc + 1], -qs);
+        }
+        qsg += qs;
+        e += qs;
+        ybound = ldexp(ybound, -qs);
+        yb_above = ldexp(yb_above, -qs);
+        zng = ldexp(zng, -qs);
+      }
+      Y[q0 * LDY + lc] = z0.r;
+      if (pair) Y[q0 * LDY + lc + 1] = z0.i;
+      if (q != q0) {
+        Y[q * LDY + lc] = z1.r;
+        if (pair) Y[q * LDY + lc + 1] = z1.i;
+      }
+      const double zn = fmax(cn1(z0), cn1(z1));
+      zng = fmax(zng, zn);
+      if (q0 > 0) ybound = fma(cn, zn, ybound);
+    };
+    int q = g1;
+    while (q >= g0) {
+      // a block: rows q0 .. q (q0 = q for a 1x1 block), local rows lq0 .. lq
+      const bool two = second(q);
+      const int q0 = two ? q - 1 : q;
+      const int lq0 = q0 - g0, lq = q - g0;
+      const Cx y0 = cx(yr[lq0], yi[lq0]), y1 = cx(yr[lq], yi[lq]);
+      const double cn = two ? cnv[lq0] + cnv[lq] : cnv[lq];
+      const bool work = owner && !(tip && q0 > pc);
+      const bool at_tip = tip && q0 == pc;   // the column's own block (singular for its eigenvalue)
+      const bool act = work && !at_tip;
+      int qs = 0;
+      Cx z0, z1;
+      if (!two) {
+        // ---- 1x1 block ----
+        z0 = solve1(a, b, be, Pn[0][lq][lq], Pn[1][lq][lq], y1, qs, flags, act);
+        z1 = cx(0.0, 0.0);
+        if (at_tip) {
+          // the tip of a real eigenvalue (zero in correction mode)
+          z0 = cx(P.rhs ? 0.0 : 1.0, 0.0);
+          qs = 0;
+        }
+      } else {
+        // ---- 2x2 block ----
+        const double s00 = Pn[0][lq0][lq0], s10 = Pn[0][lq0][lq], s01 = Pn[0][lq][lq0], s11 = Pn[0][lq][lq];
+        const double t00 = Pn[1][lq0][lq0], t01 = Pn[1][lq][lq0], t11 = Pn[1][lq][lq];
+        z0 = y0;
+        z1 = y1;
+        if (P.cform) {
+          // real form of a complex pencil: a complex column in its subspace, a real one as usual
+          Cx c0 = z0, c1 = z1, g0v = z0, g1v = z1;
+          int qc = 0, qg = 0;
+          solve2c(a, b, be, s00, s10, t00, csg, c0, c1, qc, flags, act && csg != 0.0);
+          solve2(a, b, be, s00, s01, s10, s11, t00, t01, t11, g0v, g1v, qg, flags, act && csg == 0.0);
+          z0 = csg != 0.0 ? c0 : g0v;
+          z1 = csg != 0.0 ? c1 : g1v;
+          qs = csg != 0.0 ? qc : qg;
+        } else {
+          solve2(a, b, be, s00, s01, s10, s11, t00, t01, t11, z0, z1, qs, flags, act);
+        }
+        if (tip) {
+          // the column's own block: the tip
+          Cx tz0 = cx(0.0, 0.0), tz1 = cx(0.0, 0.0);
+          int tq = 0;
+          if (P.rhs) {
+            // correction mode: the correction is zero at the tip (z0 = z1 = 0)
+          } else if (csg != 0.0) {
+            // real form of a complex pencil: the tip in the column's subspace, (sg i, 1), exactly
+            tz0 = cx(0.0, csg);
+            tz1 = cx(1.0, 0.0);
+          } else {
+            // second row of the singular block beta S_b - alpha T_b gives z_p for z_{p+1} = 1
+            double m21 = be * s10;
+            const Cx nn = cx(-(be * s11 - a * t11), b * t11);
+            const double smin = local_smin(be, aabs, fmax(fabs(s10), fabs(s11)), fabs(t11));
+            const bool pert = fabs(m21) < smin;
+            m21 = pert ? smin : m21;
+            flags |= (pert && work && at_tip) ? kInfoPerturbed : 0;
+            tq = with_margin(protect_division_fast(cn1(nn), fabs(m21), work && at_tip));
+            const Cx ns = cscl(nn, tq);
+            const double rm = recip(m21);
+            tz0 = cx(ns.r * rm, ns.i * rm);
+            tz1 = cx(ldexp(1.0, -tq), 0.0);
+          }
+          if (at_tip) {
+            z0 = tz0;
+            z1 = tz1;
+            qs = tq;
+          }
+        }
+      }
+      if (q0 > 0) {
+        // ProtectUpdate for y[0:q0] -= (beta S - alpha T)[0:q0, q0..q] z (inside the group
+        // now, above it at the end of the group; the column norms bound both)
+        const int qu = with_margin(protect_update_fast(cn, fmax(cn1(z0), cn1(z1)), ldexp(ybound, -qs), work));
+        z0 = cscl(z0, qu);
+        z1 = cscl(z1, qu);
+        qs += qu;
+      }
+      z0 = work ? z0 : cx(0.0, 0.0);
+      z1 = work ? z1 : cx(0.0, 0.0);
+      if (work) settle(q0, q, qs, z0, z1, cn);
+      // y += S (-beta z) + T (alpha z) with the block's columns
+      auto apply = [&](int c, Cx z) {
+        const d8 cs = *reinterpret_cast<const d8*>(&Pn[0][c][0]);
+        const d8 ct = *reinterpret_cast<const d8*>(&Pn[1][c][0]);
+        const double ur = -be * z.r, ui = -be * z.i;
+        const double vr = a * z.r - b * z.i, vi = a * z.i + b * z.r;
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+          yr[k] = fma(ct[k], vr, fma(cs[k], ur, yr[k]));
+          yi[k] = fma(ct[k], vi, fma(cs[k], ui, yi[k]));
+        }
+      };
+      apply(lq0, z0);
+      if (two) apply(lq, z1);
+      q = q0 - 1;
+    }
+
     // operands of the rank-2G update of the rows above (A = [S | T] rows 0..g0-1 of the
-    // group's columns), 16 x 4 blocks in the layout of the FP64 matrix instruction
+    // group's columns), 16 x 4 blocks in the layout of the FP64 matrix instruction, issued
+    // now so that they land during the end of the group (not held through its blocks)
     double af[MB / 16][4];   // raw entries; masked and scaled where they are used
 #pragma unroll
     for (int rb = 0; rb < MB / 16; ++rb)
@@ -346,142 +527,10 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
         const int64_t ro = ok ? r0 + row : 0, co = ok ? r0 + col : 0;
         af[rb][st] = kk < G ? S[ro + co * lds] : T[ro + co * ldt];
       }
-    double yb_above = ybound;   // bound on the rows above the group
-    int qsg = 0;                // scaling raised inside the group
-
-    // ---- blocks of the group, bottom up; updates stay inside the group ----
-    // Each column's substitution is private to the thread that owns it (a complex pair
-    // belongs to the thread of its first column), so the blocks need no barrier.  The
-    // unsolved rows live in registers as a stack, stk[k] = row (top) - k: a block takes
-    // its rows from the top, the rows above it are updated in place, and the stack
-    // shifts by the block size, so every register index is a constant.
-    Cx stk[G];
-    const int yc0 = lc < NCY ? lc : 0, yc1 = pair ? lc + 1 : yc0;   // (threads past the columns read column 0)
-#pragma unroll
-    for (int k = 0; k < G; ++k) {
-      const int row = g1 - k >= 0 ? g1 - k : 0;   // (rows above the group: never stored)
-      stk[k] = cx(Y[row * LDY + yc0], pair ? Y[row * LDY + yc1] : 0.0);
-    }
-    int q = g1;
-    while (q >= g0) {
-      const int q0 = (tblk[q] == 2) ? q - 1 : q;
-      const int nb = q - q0 + 1;
-      const int lq0 = q0 - g0, lq = q - g0;      // positions in the group panel
-      // the block's columns of the panel for the rows above it: entry k is row q0 - 1 - k
-      double sc0[G - 1], tc0[G - 1], sc1[G - 1], tc1[G - 1];
-#pragma unroll
-      for (int k = 0; k < G - 1; ++k) {
-        const int li = lq0 - 1 - k >= 0 ? lq0 - 1 - k : 0;
-        sc0[k] = Sg[li][lq0];
-        tc0[k] = Tg[li][lq0];
-        sc1[k] = Sg[li][lq];
-        tc1[k] = Tg[li][lq];
-      }
-      const bool work = owner && !(tip && q0 > pc);
-      Cx z0 = cx(0.0, 0.0), z1 = cx(0.0, 0.0);
-      double cn = 0.0;
-      if (work) {
-        int qs = 0;
-        if (tip && q0 == pc) {
-          if (P.rhs) {
-            // correction mode: the correction is zero at the tip (z0 = z1 = 0)
-          } else if (csg != 0.0) {
-            // real form of a complex pencil: the tip in the column's subspace, (sg i, 1), exactly
-            z0 = cx(0.0, csg);
-            z1 = cx(1.0, 0.0);
-          } else if (nb == 1) {
-            z0 = cx(1.0, 0.0);
-          } else {
-            // second row of the singular block beta S_b - alpha T_b gives z_p for z_{p+1} = 1
-            const double s21 = Sg[lq][lq0], s22 = Sg[lq][lq], t22 = Tg[lq][lq];
-            double m21 = be * s21;
-            const Cx nn = cx(-(be * s22 - a * t22), b * t22);
-            const double smin = local_smin(be, aabs, fmax(fabs(s21), fabs(s22)), fabs(t22));
-            if (fabs(m21) < smin) { m21 = smin; flags |= kInfoPerturbed; }
-            const int qd = with_margin(protect_division(cn1(nn), fabs(m21)));
-            const Cx ns = cscl(nn, qd);
-            const double rm = recip(m21);
-            z0 = cx(ns.r * rm, ns.i * rm);
-            z1 = cx(ldexp(1.0, -qd), 0.0);
-            qs += qd;
-          }
-        } else if (nb == 1) {
-          z0 = solve1(a, b, be, Sg[lq][lq], Tg[lq][lq], stk[0], qs, flags);
-        } else {
-          z0 = stk[1];
-          z1 = stk[0];
-          if (csg != 0.0)
-            solve2c(a, b, be, Sg[lq0][lq0], Sg[lq][lq0], Tg[lq0][lq0], csg, z0, z1, qs, flags);
-          else
-            solve2(a, b, be, Sg[lq0][lq0], Sg[lq0][lq], Sg[lq][lq0], Sg[lq][lq], Tg[lq0][lq0], Tg[lq0][lq],
-                   Tg[lq][lq], z0, z1, qs, flags);
-        }
-        if (q0 > 0) {
-          // ProtectUpdate for y[0:q0] -= (beta S - alpha T)[0:q0, q0..q] z (inside the group
-          // now, above it at the end of the group; the column norms bound both)
-          cn = be * tcnS[q0] + aabs * tcnT[q0];
-          if (nb == 2) cn += be * tcnS[q] + aabs * tcnT[q];
-          const double zn = fmax(cn1(z0), cn1(z1));
-          const int qu = with_margin(protect_update(cn, zn, ldexp(ybound, -qs)));
-          z0 = cscl(z0, qu);
-          z1 = cscl(z1, qu);
-          qs += qu;
-        }
-        if (qs > 0) {
-          // the unsolved rows now, the group's solved rows in LDS; the rows above and below
-          // the group at its end
-#pragma unroll
-          for (int k = 0; k < G; ++k) stk[k] = cscl(stk[k], qs);
-          for (int i = q + 1; i <= g1; ++i) {
-            Y[i * LDY + lc] = ldexp(Y[i * LDY + lc], -qs);
-            if (pair) Y[i * LDY + lc + 1] = ldexp(Y[i * LDY + lc + 1], -qs);
-          }
-          qsg += qs;
-          e += qs;
-          ybound = ldexp(ybound, -qs);
-          yb_above = ldexp(yb_above, -qs);
-        }
-        Y[q0 * LDY + lc] = z0.r;
-        if (pair) Y[q0 * LDY + lc + 1] = z0.i;
-        if (nb == 2) {
-          Y[q * LDY + lc] = z1.r;
-          if (pair) Y[q * LDY + lc + 1] = z1.i;
-        }
-        if (q0 > 0) ybound += cn * fmax(cn1(z0), cn1(z1));
-      }
-      // pop the block; stk[k] is now row q0 - 1 - k
-#pragma unroll
-      for (int k = 0; k < G; ++k) {
-        const Cx s1 = k + 1 < G ? stk[k + 1] : cx(0.0, 0.0);
-        const Cx s2 = k + 2 < G ? stk[k + 2] : cx(0.0, 0.0);
-        stk[k] = nb == 1 ? s1 : s2;
-      }
-      if (work) {
-        // y -= S (beta z) - T (alpha z) on the rows above the block (real and imaginary
-        // parts); entries above the group are scratch
-        const Cx u0 = cx(be * z0.r, be * z0.i), u1 = cx(be * z1.r, be * z1.i);
-        const Cx v0 = cx(a * z0.r - b * z0.i, a * z0.i + b * z0.r);
-        const Cx v1 = cx(a * z1.r - b * z1.i, a * z1.i + b * z1.r);
-#pragma unroll
-        for (int k = 0; k < G - 1; ++k) {
-          double dr = sc0[k] * u0.r - tc0[k] * v0.r, di = sc0[k] * u0.i - tc0[k] * v0.i;
-          dr += sc1[k] * u1.r - tc1[k] * v1.r;   // (z1 = 0 for a 1x1 block)
-          di += sc1[k] * u1.i - tc1[k] * v1.i;
-          stk[k].r -= dr;
-          stk[k].i -= di;
-        }
-      }
-      q = q0 - 1;
-    }
 
     // ---- end of group: bound the rank-2G update of the rows above, settle scales ----
     if (owner && g0 > 0) {
-      double cng = 0.0, zng = 0.0;
-      for (int i = g0; i <= g1; ++i) {
-        cng += be * tcnS[i] + aabs * tcnT[i];
-        zng = fmax(zng, fabs(Y[i * LDY + lc]) + (pair ? fabs(Y[i * LDY + lc + 1]) : 0.0));
-      }
-      const int qg = with_margin(protect_update(cng, zng, yb_above));
+      const int qg = with_margin(protect_update_fast(cng, zng, yb_above));
       if (qg > 0) {
         for (int i = g0; i <= g1; ++i) {
           Y[i * LDY + lc] = ldexp(Y[i * LDY + lc], -qg);
@@ -492,7 +541,7 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
         yb_above = ldexp(yb_above, -qg);
         zng = ldexp(zng, -qg);
       }
-      ybound = yb_above + cng * zng;
+      ybound = fma(cng, zng, yb_above);
     }
     if (owner && qsg > 0)   // the solved rows below the group (rare: scaling has head room)
       for (int i = g1 + 1; i < hr; ++i) {
@@ -504,69 +553,67 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
       if (pair) fcol[lc + 1] = qsg;
     }
     __syncthreads();   // the group's solved values and scales are final
-    // B operand: [-beta z ; alpha z] own parts, zero for rows outside the group
-#pragma unroll
-    for (int t = 0; t < G; ++t) {
-      const int i = g0 + t;
-      double bu = 0.0, bv = 0.0;
-      if (i <= g1 && selected) {
-        const double own = Y[i * LDY + lc];
-        const double oth = Y[i * LDY + partner];
-        const double zr = kind == 2 ? oth : own, zi = kind == 0 ? 0.0 : (kind == 1 ? oth : own);
-        bu = -be * own;
-        bv = kind == 2 ? (b * zr + a * zi) : (a * zr - b * zi);
-      }
-      if (colthr) {
-        Bop[t][lc] = bu;
-        Bop[G + t][lc] = bv;
-      }
-    }
     panel_publish();   // the next group's diagonal block (its loads had the whole group)
-    __syncthreads();
 
     // ---- rank-2G update of the rows above the group on the FP64 matrix cores ----
     // Y[0:g0, :] <- 2^-fcol Y[0:g0, :] + [S | T][0:g0, group] * [-beta z ; alpha z]
+    // B operand entry (k, n): row g0 + (k mod G) of column n, -beta z (k < G) or alpha z
+    // (k >= G), own parts (a pair's real part in its first column, imaginary in its
+    // second); zero for rows past the group and for columns not solved
+    auto bop = [&](int k, int n) -> double {
+      const int i = g0 + (k & (G - 1));
+      const int ir = i <= g1 ? i : g1;   // (rows past the group: read in range, dropped)
+      const int kd = colKind[n];
+      const int np = kd == 1 ? n + 1 : (kd == 2 ? n - 1 : n);
+      const double own = Y[ir * LDY + n], oth = Y[ir * LDY + np];
+      const double zr = kd == 2 ? oth : own, zi = kd == 0 ? 0.0 : (kd == 1 ? oth : own);
+      const double an = colA[n], bn = colB[n];
+      const double v = k < G ? -colBe[n] * own : (kd == 2 ? (bn * zr + an * zi) : (an * zr - bn * zi));
+      return (i <= g1 && colOn[n]) ? v : 0.0;
+    };
     if (g0 > 0) {
       const int nrb = (g0 + 15) / 16, ncb = (hw + 15) / 16;
       constexpr int nw = NTOT / 64;
-      // A wave owns whole column blocks; its row blocks are independent chains, issued
-      // interleaved.  NR (a compile-time bound on the row blocks) keeps every operand in
-      // registers and every instruction unconditional: rows at or below the group and
-      // columns past the tile are computed and dropped, and operand columns past the
-      // group meet zero rows of B.
-      auto rank_update = [&](auto nr_c) {
-        constexpr int NR = decltype(nr_c)::value;
-        for (int cb = wave; cb < ncb; cb += nw) {
-          const int col = 16 * cb + lane % 16;
-          const int colr = col < NCY ? col : NCY - 1;   // (columns past those held: dropped)
-          const int fs = fcol[colr];
-          d4 acc[NR];
-#pragma unroll
-          for (int rb = 0; rb < NR; ++rb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-              acc[rb][v] = ldexp(Y[(16 * rb + lane / 16 + 4 * v) * LDY + colr], -fs);
-#pragma unroll
-          for (int st = 0; st < 4; ++st) {
-            const double bf = Bop[4 * st + lane / 16][colr];
-#pragma unroll
-            for (int rb = 0; rb < NR; ++rb)
-              acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(psc * af[rb][st], bf, acc[rb], 0, 0, 0);
-          }
-          const bool cok = col < hw;
-#pragma unroll
-          for (int rb = 0; rb < NR; ++rb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int row = 16 * rb + lane / 16 + 4 * v;
-              if (row < g0 && cok) Y[row * LDY + col] = acc[rb][v];
-            }
-        }
-      };
+      // A wave owns whole column blocks and takes their row blocks in chunks of NRC, the
+      // chunks past the rows above the group skipped (a uniform test); a chunk's row
+      // blocks are independent chains, issued interleaved.  Every operand index is a
+      // constant, so the operands stay in registers: rows at or below the group and
+      // columns past the tile are computed and dropped, and operand columns past the group
+      // meet zero rows of B.
       constexpr int NR0 = MB / 16;
-      if (nrb > NR0 / 2) rank_update(std::integral_constant<int, NR0>{});
-      else if (nrb > NR0 / 4 || NR0 < 4) rank_update(std::integral_constant<int, (NR0 / 2 > 0 ? NR0 / 2 : 1)>{});
-      else rank_update(std::integral_constant<int, (NR0 / 4 > 0 ? NR0 / 4 : 1)>{});
+      constexpr int NRC = NR0 < 4 ? NR0 : 4;
+      for (int cb = wave; cb < ncb; cb += nw) {
+        const int col = 16 * cb + lane % 16;
+        const int colr = col < NCY ? col : NCY - 1;   // (columns past those held: dropped)
+        const int fs = fcol[colr];
+        const bool cok = col < hw;
+        double bf[4];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) bf[st] = bop(4 * st + lane / 16, colr);
+#pragma unroll
+        for (int ch = 0; ch < NR0 / NRC; ++ch) {
+          if (NRC * ch < nrb) {
+            d4 acc[NRC];
+#pragma unroll
+            for (int i = 0; i < NRC; ++i)
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                acc[i][v] = ldexp(Y[(16 * (NRC * ch + i) + lane / 16 + 4 * v) * LDY + colr], -fs);
+#pragma unroll
+            for (int st = 0; st < 4; ++st)
+#pragma unroll
+              for (int i = 0; i < NRC; ++i)
+                acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(psc * af[NRC * ch + i][st], bf[st], acc[i], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < NRC; ++i)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int row = 16 * (NRC * ch + i) + lane / 16 + 4 * v;
+                if (row < g0 && cok) Y[row * LDY + col] = acc[i][v];
+              }
+          }
+        }
+      }
     }
     __syncthreads();
     g1 = gn1;
@@ -582,13 +629,7 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
   double nx = 0.0;
   if (inrange)
     for (int i = 0; i < hr; ++i) nx = fmax(nx, fabs(Y[i * LDY + lc]));
-  if (colthr) {
-    cmax[lc] = nx;
-    colA[lc] = a;
-    colB[lc] = b;
-    colBe[lc] = be;
-    colKind[lc] = (int8_t)kind;
-  }
+  if (colthr) cmax[lc] = nx;
   if (own) {
     P.exps[(int64_t)r * m + c] = e;
     P.norms[(int64_t)r * m + c] = nx;
