@@ -109,6 +109,15 @@ typedef struct rtgevc_opts {
                          threshold.  Needs 8 m^2 more bytes of workspace.                 */
   int32_t refine_bits;/* threshold of the flag: 2^-refine_bits (1..100); 0 = the residual
                          bound 64 m 2^-53.                                              */
+  int32_t split;      /* band wavefront: the update that applies a solved band to every tile
+                         row above it is issued in launches of about this many tiles
+                         (whole tile rows, from the bottom); 0 = automatic (from the tuning
+                         table when mb and band are the table's as well, else one launch),
+                         -1 = one launch.  Performance only: each tile's update is the same
+                         computation in any launch, so every value gives the same
+                         eigenvectors bit for bit.  The launch boundaries give the chain of
+                         tile solves, which runs beside these updates on the caller's
+                         stream, a share of the GPU.                                    */
 } rtgevc_opts;
 
 /* Bytes of device workspace rtgevc() needs for order m with these options
@@ -293,8 +302,8 @@ int rtgevc_batched(int32_t count, const int64_t *m, const double *const *S, cons
  * as a pencil of rtgevc_batched: its band is opts->band, or 2 when that is 0).  The automatic choices come
  * from a table compiled into the library, written by an autotuning sweep on the GPU
  * (performance parameters only: every choice computes the same eigenvectors).
- * out receives mb, band, schedule, normalize, precision and the refinement sweeps in max_refine
- * (-1 when none run) and refine_bits as given.  Returns 0, -1 (m < 0),
+ * out receives mb, band, schedule, normalize, precision, the refinement sweeps in max_refine
+ * (-1 when none run), refine_bits as given and split (tiles per launch; -1: one launch).  Returns 0, -1 (m < 0),
  * -3 (invalid opts) or -4 (out is NULL).  Host only; touches no GPU. */
 int rtgevc_resolve_opts(int64_t m, int32_t batched, const rtgevc_opts *opts, rtgevc_opts *out);
 

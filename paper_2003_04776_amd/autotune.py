@@ -1,12 +1,16 @@
 """Autotuner: sweeps the performance parameters of the solver on the GPU and writes the
 table the library compiles in.
 
-Parameters are performance choices only — tile size mb, update band R and schedule (band
-wavefront or persistent walker) for single pencils in FP64, tile size and band for the
-mixed-precision mode, tile size per order bucket for batches — never bounds: every choice computes
-the same eigenvectors, so a table from another machine is safe, merely slower.
+Parameters are performance choices only — tile size mb, update band R, schedule (band
+wavefront or persistent walker) and the tiles per launch of a band's update of the rows above
+it (split) for single pencils in FP64, tile size, band and split for the mixed-precision mode,
+tile size per order bucket for batches — never bounds: every choice computes the same
+eigenvectors, so a table from another machine is safe, merely slower.
 
-    python -m paper_2003_04776_amd.autotune [--out-dir DIR] [--quick]
+    python -m paper_2003_04776_amd.autotune [--out-dir DIR] [--quick] [--splits-only]
+
+(--splits-only keeps the tile sizes, bands and schedules of the table the library was built
+with and sweeps only the splits.)
 
 writes DIR/tuning.json (every timing of the sweep) and DIR/tuning_table.inc (the chosen
 entries, in the form csrc/tuning_table.inc expects); copy both into the package (the
@@ -27,7 +31,8 @@ ROOT = os.path.dirname(HERE)
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-SINGLE_SIZES = (256, 1024, 4096, 8192, 32768)
+SINGLE_SIZES = (256, 1024, 4096, 8192, 16384, 32768)
+SPLITS = (0, 1024, 2048, 4096, 8192)   # 0: one launch per band
 BATCH_BUCKETS = ((64, 128), (128, 256), (256, 512), (512, 1024), (1024, 2048))
 MBS = (32, 64, 128)
 BANDS = (1, 2, 4, 8)
@@ -57,9 +62,9 @@ def mixed_candidates(m):
             yield mb, band
 
 
-def time_single(m, mb, band, schedule, Sd, Td, Z, sc, info, reps, precision=0):
+def time_single(m, mb, band, schedule, Sd, Td, Z, sc, info, reps, precision=0, split=0):
     from paper_2003_04776_amd import rtgevc as rt
-    solver = rt.Solver(m, mb=mb, band=band, schedule=schedule, precision=precision)
+    solver = rt.Solver(m, mb=mb, band=band, schedule=schedule, precision=precision, split=split if split else -1)
     solver.run_timed(Sd, Td, Z, sc, info)          # warm-up (first launch of each kernel)
     best = math.inf
     for _ in range(reps):
@@ -85,11 +90,13 @@ def time_batch(ms, mb, Sd, Td, reps):
     return best
 
 
-def choose_single(results, mixed=None):
-    """results: {m: {(mb, band, schedule): ms}}, mixed: {m: {(mb, band): ms}} -> table entries
-    (m_max, mb, band, schedule, mb_mixed, band_mixed), sizes ascending; each measured size's
+def choose_single(results, mixed=None, splits=None):
+    """results: {m: {(mb, band, schedule): ms}}, mixed: {m: {(mb, band): ms}}, splits:
+    {m: {"fp64": {split: ms}, "mixed": {split: ms}}} -> table entries (m_max, mb, band,
+    schedule, split, mb_mixed, band_mixed, split_mixed), sizes ascending; each measured size's
     best choice covers up to the geometric midpoint to the next.  Without mixed timings the
-    mixed columns repeat the FP64 tile size and band."""
+    mixed columns repeat the FP64 tile size and band; without split timings a band's update
+    is one launch (split 0)."""
     sizes = sorted(results)
     out = []
     for i, m in enumerate(sizes):
@@ -98,8 +105,11 @@ def choose_single(results, mixed=None):
             (mbx, bandx), _ = min(mixed[m].items(), key=lambda kv: kv[1])
         else:
             mbx, bandx = mb, band
+        sp = (splits or {}).get(m, {})
+        split = min(sp["fp64"].items(), key=lambda kv: kv[1])[0] if sp.get("fp64") else 0
+        splitx = min(sp["mixed"].items(), key=lambda kv: kv[1])[0] if sp.get("mixed") else 0
         m_max = int(math.sqrt(m * sizes[i + 1])) if i + 1 < len(sizes) else None
-        out.append((m_max, mb, band, schedule, mbx, bandx))
+        out.append((m_max, mb, band, schedule, split, mbx, bandx, splitx))
     return out
 
 
@@ -118,12 +128,14 @@ def render_inc(single, batch, source):
         "// Performance parameters chosen per problem size (never bounds: every choice computes",
         "// the same eigenvectors).  Written by paper_2003_04776_amd/autotune.py from a sweep on",
         f"// the GPU ({source}).",
-        "// Single pencils: the first entry with m <= m_max applies: {m_max, mb, band, schedule} for",
-        "// FP64, then {mb, band} for mixed precision.",
+        "// Single pencils: the first entry with m <= m_max applies: {m_max, mb, band, schedule, split}",
+        "// for FP64, then {mb, band, split} for mixed precision (split: tiles per launch of a band's",
+        "// update of the rows above it, 0 = one launch).",
         "static const TuneSingle kTuneSingle[] = {",
     ]
-    for m_max, mb, band, schedule, mbx, bandx in single:
-        lines.append(f"    {{{m_max if m_max is not None else 'INT64_MAX'}, {mb}, {band}, {schedule}, {mbx}, {bandx}}},")
+    for m_max, mb, band, schedule, split, mbx, bandx, splitx in single:
+        lines.append(f"    {{{m_max if m_max is not None else 'INT64_MAX'}, {mb}, {band}, {schedule}, {split}, "
+                     f"{mbx}, {bandx}, {splitx}}},")
     lines += ["};", "// Pencils of a batch (tile size per order bucket).", "static const TuneBatch kTuneBatch[] = {"]
     for m_max, mb in batch:
         lines.append(f"    {{{m_max if m_max is not None else 'INT64_MAX'}, {mb}}},")
@@ -137,6 +149,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="smaller sweep (sizes up to 8192)")
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--splits-only", action="store_true",
+                    help="keep the built table's tile sizes, bands and schedules; sweep the splits")
     args = ap.parse_args()
 
     import numpy as np
@@ -147,7 +161,7 @@ def main():
 
     dev = torch.cuda.get_device_properties(0)
     record = {"device": dev.name, "gcn_arch": getattr(dev, "gcnArchName", ""), "single": {}, "batch": {}}
-    single, mixed = {}, {}
+    single, mixed, splits = {}, {}, {}
     sizes = [m for m in SINGLE_SIZES if not (args.quick and m > 8192)]
     for m in sizes:
         S, T, _ = pencils.schur_pencil(m, 500 + m, threads=16)
@@ -156,22 +170,42 @@ def main():
         Z = rt.colmajor_empty(m)
         sc = torch.empty(m, dtype=torch.int32, device="cuda")
         info = torch.zeros(1, dtype=torch.int32, device="cuda")
-        single[m] = {}
-        for mb, band, schedule in single_candidates(m):
-            t = time_single(m, mb, band, schedule, Sd, Td, Z, sc, info, args.reps)
-            single[m][(mb, band, schedule)] = t
-            record["single"].setdefault(str(m), {})[f"mb={mb},band={band},schedule={schedule}"] = round(t, 4)
-            print(f"[tune] single m={m} mb={mb} band={band} schedule={schedule}: {t:.3f} ms", flush=True)
-        mixed[m] = {}
-        for mb, band in mixed_candidates(m):
-            t = time_single(m, mb, band, 1, Sd, Td, Z, sc, info, args.reps, precision=1)
-            mixed[m][(mb, band)] = t
-            record.setdefault("mixed", {}).setdefault(str(m), {})[f"mb={mb},band={band}"] = round(t, 4)
-            print(f"[tune] mixed m={m} mb={mb} band={band}: {t:.3f} ms", flush=True)
+        single[m], mixed[m] = {}, {}
+        if args.splits_only:
+            single[m][rt.resolve_opts(m, with_schedule=True)] = 0.0
+            mixed[m][rt.resolve_opts(m, precision=1)] = 0.0
+        else:
+            for mb, band, schedule in single_candidates(m):
+                t = time_single(m, mb, band, schedule, Sd, Td, Z, sc, info, args.reps)
+                single[m][(mb, band, schedule)] = t
+                record["single"].setdefault(str(m), {})[f"mb={mb},band={band},schedule={schedule}"] = round(t, 4)
+                print(f"[tune] single m={m} mb={mb} band={band} schedule={schedule}: {t:.3f} ms", flush=True)
+            for mb, band in mixed_candidates(m):
+                t = time_single(m, mb, band, 1, Sd, Td, Z, sc, info, args.reps, precision=1)
+                mixed[m][(mb, band)] = t
+                record.setdefault("mixed", {}).setdefault(str(m), {})[f"mb={mb},band={band}"] = round(t, 4)
+                print(f"[tune] mixed m={m} mb={mb} band={band}: {t:.3f} ms", flush=True)
+        # the splits of the chosen tile size and band (the walker has no band updates)
+        (mb, band, schedule), _ = min(single[m].items(), key=lambda kv: kv[1])
+        (mbx, bandx), _ = min(mixed[m].items(), key=lambda kv: kv[1])
+        splits[m] = {"fp64": {}, "mixed": {}}
+        for split in SPLITS if schedule == 1 else (0,):
+            t = time_single(m, mb, band, schedule, Sd, Td, Z, sc, info, args.reps, split=split)
+            splits[m]["fp64"][split] = t
+            record.setdefault("split", {}).setdefault(str(m), {})[f"fp64,split={split}"] = round(t, 4)
+            print(f"[tune] split m={m} mb={mb} band={band} split={split}: {t:.3f} ms", flush=True)
+        for split in SPLITS:
+            t = time_single(m, mbx, bandx, 1, Sd, Td, Z, sc, info, args.reps, precision=1, split=split)
+            splits[m]["mixed"][split] = t
+            record.setdefault("split", {}).setdefault(str(m), {})[f"mixed,split={split}"] = round(t, 4)
+            print(f"[tune] split mixed m={m} mb={mbx} band={bandx} split={split}: {t:.3f} ms", flush=True)
         del Sd, Td, Z
         torch.cuda.empty_cache()
     batch = {}
     for bi, (lo, hi) in enumerate(BATCH_BUCKETS):
+        if args.splits_only:
+            batch[(lo, hi)] = {rt.resolve_opts(hi, batched=True)[0]: 0.0}
+            continue
         rng = np.random.default_rng(7000 + bi)
         ms = [int(v) for v in rng.integers(lo, hi, size=args.batch_count)]
         Sd, Td = [], []
@@ -189,11 +223,19 @@ def main():
             print(f"[tune] batch [{lo},{hi}) x{len(ms)} mb={mb}: {t:.3f} ms", flush=True)
         del Sd, Td
         torch.cuda.empty_cache()
-    ch_single, ch_batch = choose_single(single, mixed), choose_batch(batch)
-    record["chosen_single"] = [{"m_max": a, "mb": b, "band": c, "schedule": d, "mb_mixed": e, "band_mixed": f}
-                               for a, b, c, d, e, f in ch_single]
+    ch_single, ch_batch = choose_single(single, mixed, splits), choose_batch(batch)
+    record["chosen_single"] = [{"m_max": a, "mb": b, "band": c, "schedule": d, "split": e, "mb_mixed": f,
+                                "band_mixed": g, "split_mixed": h} for a, b, c, d, e, f, g, h in ch_single]
     record["chosen_batch"] = [{"m_max": a, "mb": b} for a, b in ch_batch]
     os.makedirs(args.out_dir, exist_ok=True)
+    prev = os.path.join(args.out_dir, "tuning.json")
+    if args.splits_only and os.path.exists(prev):
+        # keep the timings of the sweep that chose the tile sizes, bands and schedules
+        with open(prev) as f:
+            old = json.load(f)
+        for key in ("single", "mixed", "batch"):
+            if key in old:
+                record[key] = old[key]
     with open(os.path.join(args.out_dir, "tuning.json"), "w") as f:
         json.dump(record, f, indent=1)
     with open(os.path.join(args.out_dir, "tuning_table.inc"), "w") as f:

@@ -55,8 +55,8 @@ __host__ __device__ inline size_t up(size_t x) { return (x + kAlign - 1) / kAlig
 
 struct TuneSingle {
   int64_t m_max;
-  int32_t mb, band, schedule;   // FP64
-  int32_t mb_mixed, band_mixed; // mixed precision (always the band wavefront)
+  int32_t mb, band, schedule, split;   // FP64
+  int32_t mb_mixed, band_mixed, split_mixed; // mixed precision (always the band wavefront)
 };
 struct TuneBatch {
   int64_t m_max;
@@ -83,6 +83,17 @@ int resolve_mb(int64_t m, const rtgevc_opts* o) {
   return mixed(o) ? tune_single(m).mb_mixed : tune_single(m).mb;
 }
 
+// tiles per launch of the band schedule's updates of the rows above a band, 0 for one
+// launch (automatic: the table entry of m when the tile size and band are the table's as
+// well, else one launch)
+int resolve_split(int64_t m, const rtgevc_opts* o) {
+  if (o && o->split != 0) return o->split > 0 ? o->split : 0;
+  const TuneSingle& t = tune_single(m);
+  const bool mx = mixed(o);
+  if (resolve_mb(m, o) != (mx ? t.mb_mixed : t.mb) || resolve_band(m, o) != (mx ? t.band_mixed : t.band)) return 0;
+  return mx ? t.split_mixed : t.split;
+}
+
 bool opts_ok(const rtgevc_opts* o) {
   if (!o) return true;
   if (o->mb != 0 && o->mb != 32 && o->mb != 64 && o->mb != 128) return false;
@@ -94,6 +105,7 @@ bool opts_ok(const rtgevc_opts* o) {
   if (o->precision == 1 && o->schedule == 2) return false;   // the walker runs FP64 updates
   if (o->max_refine < -1 || o->max_refine > 3) return false;
   if (o->refine_bits < 0 || o->refine_bits > 100) return false;
+  if (o->split < -1) return false;
   return true;
 }
 
@@ -335,7 +347,7 @@ hipError_t enqueue_rows(const PencilDesc& P, int rows, hipStream_t sa, Aux& ax, 
     bool record(int e, int s) { return ok(hipEventRecord(ev[e], st[s])); }
     bool wait(int s, int e) { return ok(hipStreamWaitEvent(st[s], ev[e], 0)); }
   } ops{P, {sa, ax.side}, {ax.evC, ax.evJ, ax.evU[0], ax.evU[1]}, mark, err};
-  band_schedule(rows, P.band, ops);
+  band_schedule(rows, P.band, P.split, ops);
   return err;
 }
 
@@ -392,6 +404,7 @@ PencilDesc make_desc(int64_t m, const double* S, int64_t lds, const double* T, i
   carve(P, static_cast<char*>(work), m, resolve_mb(m, opts), resolve_band(m, opts), walk, resolve_precision(opts),
         resolve_sweeps(opts) > 0 ? ref : nullptr);
   if (ref) ref->tau = resolve_tau(m, opts);
+  P.split = resolve_split(m, opts);
   P.info = info ? info : &P.ctrl->info_local;
   P.normalize = opts ? opts->normalize : 1;
   if (walk) walk->spin_limit = (opts && opts->watchdog > 0) ? opts->watchdog : kDefaultSpinLimit;
@@ -435,7 +448,7 @@ hipError_t enqueue_rows_one_stream(const PencilDesc& P, int rows, hipStream_t s)
     bool record(int, int) { return true; }
     bool wait(int, int) { return true; }
   } ops{P, s};
-  band_schedule(rows, P.band, ops);
+  band_schedule(rows, P.band, 0, ops);   // (one stream: no other launches to let in)
   return hipGetLastError();
 }
 
@@ -763,8 +776,18 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
   PencilDesc P = make_desc(m, S, lds, T, ldt, select, Z, ldz, scales, info, work, opts, walker ? &W : nullptr,
                            walker ? nullptr : &R);
   const int sweeps = walker ? 0 : resolve_sweeps(opts);
-  // events bracket every launch on the stream it runs on
-  const int nev = 2 * (3 * P.Mmax + 8);
+  // events bracket every launch on the stream it runs on: the schedule's launches for the
+  // largest tile count (a dry run of the same schedule), plus the few outside it
+  struct Count {
+    int n = 0;
+    bool solve(int, int) { ++n; return true; }
+    bool update(int, int, int, int, int, int) { ++n; return true; }
+    bool record(int, int) { return true; }
+    bool wait(int, int) { return true; }
+  } cnt;
+  band_schedule(P.Mmax, P.band, P.split, cnt);
+  const int nlaunch = cnt.n + 8;
+  const int nev = 2 * nlaunch;
   std::lock_guard<std::mutex> lock(g_event_mu);
   std::lock_guard<std::mutex> lock2(g_aux_mu);
   hipEvent_t* ev = nullptr;
@@ -775,12 +798,16 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
   err = get_aux(&ax);
   if (err != hipSuccess) return hip_code(err);
   auto mark_on = [&](hipStream_t st) {
+    if (used >= nev) {   // (not reached: the count above bounds the launches)
+      if (err == hipSuccess) err = hipErrorInvalidValue;
+      return;
+    }
     const hipError_t e = hipEventRecord(ev[used++], st);
     if (err == hipSuccess) err = e;
   };
   auto mark = [&]() { mark_on(s); };
   struct Span { int cls, e0, e1; };
-  Span* spans = new Span[3 * P.Mmax + 8];
+  Span* spans = new Span[nlaunch];
   int nsp = 0;
   mark();
   launch_preprocess(P, s);
@@ -799,7 +826,7 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
   } else if (err == hipSuccess) {
     const hipError_t e = enqueue_rows(P, M, s, *ax, [&](int kind, bool before, hipStream_t st) {
       mark_on(st);
-      if (!before) {
+      if (!before && nsp < nlaunch) {
         spans[nsp] = Span{kind, used - 2, used - 1};
         ++nsp;
       }
@@ -979,6 +1006,8 @@ int rtgevc_resolve_opts(int64_t m, int32_t batched, const rtgevc_opts* opts, rtg
   const int sweeps = batched ? 0 : resolve_sweeps(opts);
   out->max_refine = sweeps > 0 ? sweeps : -1;
   out->refine_bits = opts ? opts->refine_bits : 0;
+  const int split = batched ? 0 : resolve_split(m, opts);
+  out->split = split > 0 ? split : -1;
   return 0;
 }
 

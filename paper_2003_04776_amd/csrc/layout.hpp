@@ -90,6 +90,7 @@ struct PencilDesc {
   int32_t Mmax;
   int32_t normalize;
   int32_t band;       // R: tile rows per update band
+  int32_t split;      // tiles per launch of a band's update of the rows above it (0: one launch)
   int32_t wslots;     // 2R source-row slots of W, eW, nW
   int32_t precision;  // 0: FP64 contraction; 1: split operands on the int8 matrix cores
 };

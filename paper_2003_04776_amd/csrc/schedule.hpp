@@ -9,7 +9,11 @@
 //   C(b)   on the caller's stream A: the band's rows from the bottom up, each solve
 //          followed by the small update of the band rows above it;
 //   U1(b)  on A: the band applied to the next band's rows [R (b - 1), R b);
-//   U2(b)  on the side stream B: the band applied to every row above, [0, R (b - 1)).
+//   U2(b)  on the side stream B: the band applied to every row above, [0, R (b - 1)), in
+//          launches of about `split` tiles each (whole tile rows, from the bottom; 0: one
+//          launch).  The launches are independent; their boundaries give the chain's
+//          launches on A a share of the GPU, which a single large launch keeps to itself
+//          until its last workgroups are placed.
 // Dependencies (every one is an event or stream order):
 //   U1(b)  needs U2(b + 1), which also read-modifies-writes rows of band b - 1 (the
 //          sources of a tile are applied in descending order, and a tile column's first
@@ -17,7 +21,9 @@
 //   C(b)   needs U2(b + 2), the last writer of its rows and the last reader of the W
 //          slots (two bands of them) it is about to overwrite: C(b) follows U1(b + 1)
 //          on A, which waited for U2(b + 2);
-//   U2(b)  needs C(b) (its sources), and stream order on B puts it after U2(b + 1).
+//   U2(b)  needs C(b) (its sources), and stream order on B puts it after U2(b + 1); it also
+//          waits for U1(b), which the chain C(b - 1) waits for: started together, the large
+//          U2(b) would take the GPU from the small U1(b) and delay the chain by its length.
 // C(b - 1) needs U1(b) and U2(b + 1) only, so it overlaps U2(b) (the look-ahead).
 #pragma once
 
@@ -31,7 +37,7 @@ enum SchedEvent { kEvC = 0, kEvJ = 1, kEvU0 = 2, kEvU1 = 3 };
 //       record(event, stream), wait(stream, event)    event order between the streams
 // Each returns false on failure, which stops the enqueue.
 template <class Ops>
-bool band_schedule(int rows, int R, Ops& ops) {
+bool band_schedule(int rows, int R, int split, Ops& ops) {
   bool ok = true;
   auto chk = [&](bool b) { ok = ok && b; };
   // the side stream starts after everything already queued on the caller's stream
@@ -46,14 +52,17 @@ bool band_schedule(int rows, int R, Ops& ops) {
       if (i > r_lo) chk(ops.update(r_lo, i, i, i, i, kStreamA));
     }
     if (r_lo > 0 && ok) {
-      chk(ops.record(kEvC, kStreamA));
       const int nlo = r_lo > R ? r_lo - R : 0;
       // U2(b + 1): evU[(b + 1) & 1] was last recorded after it
       chk(ops.wait(kStreamA, ((b + 1) & 1) ? kEvU1 : kEvU0));
       chk(ops.update(nlo, r_lo, r_lo, r_lo, r_hi, kStreamA));
+      chk(ops.record(kEvC, kStreamA));   // C(b) and U1(b)
       if (nlo > 0) {
         chk(ops.wait(kStreamB, kEvC));
-        chk(ops.update(0, nlo, r_lo, r_lo, r_hi, kStreamB));
+        const int ncol = rows - r_lo;   // tile columns r_lo .. rows - 1
+        int cr = split > 0 ? (split + ncol - 1) / ncol : nlo;   // tile rows per launch
+        if (cr < 1) cr = 1;
+        for (int hi = nlo; hi > 0 && ok; hi -= cr) chk(ops.update(hi - cr > 0 ? hi - cr : 0, hi, r_lo, r_lo, r_hi, kStreamB));
         chk(ops.record((b & 1) ? kEvU1 : kEvU0, kStreamB));
       }
     }

@@ -37,7 +37,7 @@ class RtgevcError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("mb", ctypes.c_int32), ("normalize", ctypes.c_int32), ("band", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("watchdog", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("max_refine", ctypes.c_int32), ("refine_bits", ctypes.c_int32)]
+                ("max_refine", ctypes.c_int32), ("refine_bits", ctypes.c_int32), ("split", ctypes.c_int32)]
 
 
 _lib = None
@@ -109,8 +109,9 @@ PRECISION_MIXED = 1    # tile-update contraction on the int8 matrix cores from s
 
 
 def make_opts(mb: int = 0, normalize: bool = True, band: int = 0, schedule: int = 0, watchdog: int = 0,
-              precision: int = 0, max_refine: int = 0, refine_bits: int = 0) -> Opts:
+              precision: int = 0, max_refine: int = 0, refine_bits: int = 0, split: int = 0) -> Opts:
     o = Opts()
+    o.split = int(split)
     o.max_refine = int(max_refine)
     o.refine_bits = int(refine_bits)
     o.precision = int(precision)
@@ -129,15 +130,16 @@ def workspace_size(m: int, mb: int = 0, normalize: bool = True, band: int = 0, s
 
 
 def resolve_opts(m: int, batched: bool = False, mb: int = 0, band: int = 0, normalize: bool = True,
-                 schedule: int = 0, precision: int = 0, with_schedule: bool = False):
-    """(mb, band) — and the schedule with with_schedule — the library would use for order m
-    with these options."""
-    o, out = make_opts(mb, normalize, band, schedule, 0, precision), Opts()
+                 schedule: int = 0, precision: int = 0, with_schedule: bool = False, split: int = 0,
+                 with_split: bool = False):
+    """(mb, band) — and the schedule with with_schedule, then the tiles per launch of a
+    band's update of the rows above it (-1: one launch) with with_split — the library would
+    use for order m with these options."""
+    o, out = make_opts(mb, normalize, band, schedule, 0, precision, split=split), Opts()
     _check(load().rtgevc_resolve_opts(int(m), 1 if batched else 0, ctypes.byref(o), ctypes.byref(out)),
            "rtgevc_resolve_opts")
-    if with_schedule:
-        return int(out.mb), int(out.band), int(out.schedule)
-    return int(out.mb), int(out.band)
+    res = (int(out.mb), int(out.band)) + ((int(out.schedule),) if with_schedule else ())
+    return res + ((int(out.split),) if with_split else ())
 
 
 def strerror(code: int) -> str:
@@ -196,11 +198,11 @@ class Solver:
 
     def __init__(self, m: int, mb: int = 0, normalize: bool = True, band: int = 0, device="cuda",
                  schedule: int = 0, watchdog: int = 0, precision: int = 0, left: bool = False,
-                 max_refine: int = 0, refine_bits: int = 0):
+                 max_refine: int = 0, refine_bits: int = 0, split: int = 0):
         import torch
         self.m = int(m)
         self.left = bool(left)
-        self.opts = make_opts(mb, normalize, band, schedule, watchdog, precision, max_refine, refine_bits)
+        self.opts = make_opts(mb, normalize, band, schedule, watchdog, precision, max_refine, refine_bits, split)
         size = load().rtgevc_left_workspace_size if self.left else load().rtgevc_workspace_size
         self.nbytes = int(size(self.m, ctypes.byref(self.opts)))
         self.work = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)

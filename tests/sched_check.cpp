@@ -82,9 +82,10 @@ int main(int argc, char** argv) {
   rp.rows = atoi(argv[1]);
   rp.R = atoi(argv[2]);
   rp.drop = argc > 3 ? atoi(argv[3]) : -1;
+  const int split = argc > 4 ? atoi(argv[4]) : 0;
   // pre-processing before and consolidation after, on the caller's stream
   rp.launch(Op{0, 0, {0, 0}, 0, rp.rows, 0, 0, rp.rows - 1});
-  rgev::band_schedule(rp.rows, rp.R, rp);
+  rgev::band_schedule(rp.rows, rp.R, split, rp);
   rp.launch(Op{3, 0, {0, 0}, 0, rp.rows, 0, 0, rp.rows - 1});
   const int rows = rp.rows, R = rp.R, WS = 2 * R;
   const std::vector<Op>& ops = rp.ops;

@@ -70,6 +70,7 @@ def test_argument_errors_before_any_gpu_work():
     assert _call(opts=rt.make_opts(precision=1, max_refine=-2)) == -13
     assert _call(opts=rt.make_opts(precision=1, refine_bits=101)) == -13
     assert _call(opts=rt.make_opts(refine_bits=-1)) == -13
+    assert _call(opts=rt.make_opts(split=-2)) == -13
     assert _call(opts=rt.make_opts(schedule=3)) == -13
     assert _call(opts=rt.make_opts(watchdog=-1)) == -13
     assert _call(opts=rt.make_opts(precision=2)) == -13

@@ -16,13 +16,16 @@ def test_choose_single_and_batch():
     res = {256: {(64, 1, 1): 2.0, (128, 4, 1): 1.0}, 4096: {(64, 2, 1): 5.0, (128, 1, 2): 4.0},
            32768: {(128, 4, 1): 9.0}}
     mixed = {256: {(64, 2): 3.0, (128, 1): 2.0}, 32768: {(128, 8): 7.0, (128, 4): 8.0}}
-    ch = autotune.choose_single(res, mixed)
-    # sizes without mixed timings repeat the FP64 tile size and band in the mixed columns
-    assert ch == [(1024, 128, 4, 1, 128, 1), (11585, 128, 1, 2, 128, 1), (None, 128, 4, 1, 128, 8)]
+    splits = {32768: {"fp64": {0: 9.0, 1024: 9.5}, "mixed": {0: 7.0, 2048: 6.5, 4096: 6.8}}}
+    ch = autotune.choose_single(res, mixed, splits)
+    # sizes without mixed timings repeat the FP64 tile size and band in the mixed columns;
+    # sizes without split timings take one launch per band (0)
+    assert ch == [(1024, 128, 4, 1, 0, 128, 1, 0), (11585, 128, 1, 2, 0, 128, 1, 0),
+                  (None, 128, 4, 1, 0, 128, 8, 2048)]
     chb = autotune.choose_batch({(64, 128): {32: 1.0, 64: 2.0}, (128, 256): {64: 1.0, 128: 3.0}})
     assert chb == [(128, 32), (None, 64)]
     text = autotune.render_inc(ch, chb, "test")
-    assert "{INT64_MAX, 128, 4, 1, 128, 8}" in text and "{128, 32}" in text
+    assert "{INT64_MAX, 128, 4, 1, 0, 128, 8, 2048}" in text and "{128, 32}" in text
 
 
 def _parse_inc():
@@ -39,18 +42,29 @@ def test_compiled_table_is_well_formed_and_used():
     assert single[-1][0] == "INT64_MAX" and batch[-1][0] == "INT64_MAX"
     bounds = [int(e[0]) for e in single[:-1]]
     assert bounds == sorted(bounds)
-    for m_max, mb, band, schedule, mbx, bandx in single:
+    for m_max, mb, band, schedule, split, mbx, bandx, splitx in single:
         assert int(mb) in (32, 64, 128) and 1 <= int(band) <= 8 and int(schedule) in (1, 2)
         assert int(mbx) in (32, 64, 128) and 1 <= int(bandx) <= 8
+        assert int(split) >= 0 and int(splitx) >= 0
     for m_max, mb in batch:
         assert int(mb) in (32, 64, 128)
     # the library resolves automatic options from this table
     lo = 1
-    for m_max, mb, band, schedule, mbx, bandx in single:
+    for m_max, mb, band, schedule, split, mbx, bandx, splitx in single:
         for m in {lo, (lo + int(m_max)) // 2 if m_max != "INT64_MAX" else lo + 1000}:
-            assert rt.resolve_opts(m, with_schedule=True) == (int(mb), int(band), int(schedule)), (m, mb, band)
-            # mixed precision: its own tile size and band, always the band schedule
-            assert rt.resolve_opts(m, precision=1, with_schedule=True) == (int(mbx), int(bandx), 1)
+            sp = int(split) if int(split) > 0 else -1
+            assert rt.resolve_opts(m, with_schedule=True, with_split=True) == (int(mb), int(band), int(schedule),
+                                                                                  sp), (m, mb, band)
+            # mixed precision: its own tile size, band and split, always the band schedule
+            spx = int(splitx) if int(splitx) > 0 else -1
+            assert rt.resolve_opts(m, precision=1, with_schedule=True, with_split=True) == (int(mbx), int(bandx),
+                                                                                             1, spx)
+            # a split of the caller's overrides the table; a tile size or band other than the
+            # table's takes one launch unless a split is given
+            assert rt.resolve_opts(m, split=333, with_split=True)[-1] == 333
+            assert rt.resolve_opts(m, split=-1, with_split=True)[-1] == -1
+            other = 32 if int(mb) != 32 else 64
+            assert rt.resolve_opts(m, mb=other, with_split=True)[-1] == -1
         if m_max != "INT64_MAX":
             lo = int(m_max) + 1
     lo = 1

@@ -35,13 +35,13 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def run_gpu(S, T, mb=0, select=None, normalize=True, ld=None, band=0, precision=0):
+def run_gpu(S, T, mb=0, select=None, normalize=True, ld=None, band=0, precision=0, split=0):
     torch = _torch()
     from paper_2003_04776_amd import rtgevc as rt
     m = S.shape[0]
     Sd = rt.colmajor_to_device(S, ld=ld)
     Td = rt.colmajor_to_device(T, ld=ld)
-    solver = rt.Solver(m, mb=mb, normalize=normalize, band=band, precision=precision)
+    solver = rt.Solver(m, mb=mb, normalize=normalize, band=band, precision=precision, split=split)
     res = solver.run(Sd, Td, select=select)
     torch.cuda.synchronize()
     return res.Z.cpu().numpy(), res.scales.cpu().numpy(), int(res.info.item())
@@ -300,6 +300,41 @@ def test_common_power_of_two_prescale():
     assert info == 256
     Zr, _, _ = run_gpu(S, T, mb=64)
     assert np.max(np.abs(Zg - Zr)) <= 1e-14
+
+
+@pytest.mark.parametrize("precision,kind", [(0, "normal"), (0, "stress"), (1, "normal")])
+def test_split_updates_bitwise(precision, kind):
+    """The update of the rows above a band in launches of 1, 40 or 500 tiles, against one
+    launch per band: the same eigenvectors, scales and info bit for bit (tile 32, band 2, 40
+    tile rows)."""
+    m = 1270
+    S, T, _ = pencils.schur_pencil(m, 28, kind=kind)
+    ref = run_gpu(S, T, mb=32, band=2, precision=precision, split=-1, normalize=False)
+    for split in (1, 40, 500):
+        got = run_gpu(S, T, mb=32, band=2, precision=precision, split=split, normalize=False)
+        _say("split", split, "precision", precision, kind)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and got[2] == ref[2]
+
+
+def test_timed_with_many_launches():
+    """The timed entry point with one launch per tile row of each band update (split 1, tile
+    32, band 1: thousands of launches, each bracketed by events): no error, and the same
+    eigenvectors as the untimed call."""
+    torch = _torch()
+    from paper_2003_04776_amd import rtgevc as rt
+    m = 1270
+    S, T, _ = pencils.schur_pencil(m, 29)
+    Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
+    sv = rt.Solver(m, mb=32, band=1, split=1)
+    Z = rt.colmajor_empty(m)
+    sc = torch.zeros(m, dtype=torch.int32, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    st = sv.run_timed(Sd, Td, Z, sc, info)
+    torch.cuda.synchronize()
+    assert st["total_ms"] > 0 and st["update_ms"] > 0
+    ref = sv.run(Sd, Td)
+    torch.cuda.synchronize()
+    assert torch.equal(Z, ref.Z)
 
 
 def test_repeat_is_deterministic():

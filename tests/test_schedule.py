@@ -23,8 +23,8 @@ def checker(tmp_path_factory):
     return exe
 
 
-def _run(exe, rows, band, drop=-1):
-    r = subprocess.run([exe, str(rows), str(band), str(drop)], capture_output=True, text=True)
+def _run(exe, rows, band, drop=-1, split=0):
+    r = subprocess.run([exe, str(rows), str(band), str(drop), str(split)], capture_output=True, text=True)
     return r.returncode, r.stdout.strip()
 
 
@@ -37,6 +37,22 @@ def test_band_schedule_orders_every_conflict(checker, band):
     for rows in list(range(1, 71)) + [129, 256]:
         rc, out = _run(checker, rows, band)
         assert rc == 0 and out.startswith("OK"), (rows, band, out)
+
+
+@pytest.mark.parametrize("split", [1, 7, 64, 1024, 4096])
+@pytest.mark.parametrize("band", [1, 4, 8])
+def test_split_updates_keep_every_order(checker, band, split):
+    """The update of the rows above a band in several launches of about `split` tiles: the
+    same checks, and more launches than with one launch per band where a band's update has
+    more tiles than that."""
+    for rows in list(range(1, 41)) + [128, 256]:
+        rc, out = _run(checker, rows, band, split=split)
+        assert rc == 0 and out.startswith("OK"), (rows, band, split, out)
+        n_split = int(out.split()[1])
+        n_one = int(_run(checker, rows, band)[1].split()[1])
+        assert n_split >= n_one
+        if split == 1 and rows > 2 * band + 1:
+            assert n_split > n_one
 
 
 def test_replay_detects_a_missing_wait(checker):
