@@ -90,6 +90,23 @@ def time_batch(ms, mb, Sd, Td, reps):
     return best
 
 
+SPLIT_GAIN = 0.01   # a split must beat one launch per band by this fraction to be chosen
+
+
+def choose_split(times, tiles=None):
+    """{split: ms} -> the split to tabulate: the fastest, unless it is within SPLIT_GAIN of
+    one launch per band (split 0), which then stays (fewer launches at the same time).
+    Splits of at least `tiles` (the tile count of the pencil, more than any band update has)
+    issue the same launches as split 0 and are not candidates."""
+    if not times:
+        return 0
+    times = {s: t for s, t in times.items() if s == 0 or tiles is None or s < tiles}
+    best, t = min(times.items(), key=lambda kv: kv[1])
+    if 0 in times and t >= (1.0 - SPLIT_GAIN) * times[0]:
+        return 0
+    return best
+
+
 def choose_single(results, mixed=None, splits=None):
     """results: {m: {(mb, band, schedule): ms}}, mixed: {m: {(mb, band): ms}}, splits:
     {m: {"fp64": {split: ms}, "mixed": {split: ms}}} -> table entries (m_max, mb, band,
@@ -106,8 +123,8 @@ def choose_single(results, mixed=None, splits=None):
         else:
             mbx, bandx = mb, band
         sp = (splits or {}).get(m, {})
-        split = min(sp["fp64"].items(), key=lambda kv: kv[1])[0] if sp.get("fp64") else 0
-        splitx = min(sp["mixed"].items(), key=lambda kv: kv[1])[0] if sp.get("mixed") else 0
+        split = choose_split(sp.get("fp64"), ((m + mb - 1) // mb) ** 2)
+        splitx = choose_split(sp.get("mixed"), ((m + mbx - 1) // mbx) ** 2)
         m_max = int(math.sqrt(m * sizes[i + 1])) if i + 1 < len(sizes) else None
         out.append((m_max, mb, band, schedule, split, mbx, bandx, splitx))
     return out
@@ -121,6 +138,31 @@ def choose_batch(results):
         mb, _ = min(results[(lo, hi)].items(), key=lambda kv: kv[1])
         out.append((hi if i + 1 < len(buckets) else None, mb))
     return out
+
+
+def record_timings(rec):
+    """The timings of a tuning.json record in the form the choose_ functions take."""
+    def kv(key):
+        return dict(p.split("=") for p in key.split(","))
+    single = {int(m): {(int(kv(k)["mb"]), int(kv(k)["band"]), int(kv(k)["schedule"])): t for k, t in d.items()}
+              for m, d in rec.get("single", {}).items()}
+    mixed = {int(m): {(int(kv(k)["mb"]), int(kv(k)["band"])): t for k, t in d.items()}
+             for m, d in rec.get("mixed", {}).items()}
+    # sizes whose splits were swept on the tile size and band of a built table
+    for m, base in rec.get("split_base", {}).items():
+        b, x = kv(base["fp64"]), kv(base["mixed"])
+        single.setdefault(int(m), {(int(b["mb"]), int(b["band"]), int(b["schedule"])): 0.0})
+        mixed.setdefault(int(m), {(int(x["mb"]), int(x["band"])): 0.0})
+    splits = {}
+    for m, d in rec.get("split", {}).items():
+        for k, t in d.items():
+            prec, sp = k.split(",")
+            splits.setdefault(int(m), {}).setdefault(prec, {})[int(sp.split("=")[1])] = t
+    batch = {}
+    for b, d in rec.get("batch", {}).items():
+        lo, hi = (int(x) for x in b.split("-"))
+        batch[(lo, hi)] = {int(k.split("=")[1]): t for k, t in d.items()}
+    return single, mixed, splits, batch
 
 
 def render_inc(single, batch, source):
@@ -151,7 +193,18 @@ def main():
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--splits-only", action="store_true",
                     help="keep the built table's tile sizes, bands and schedules; sweep the splits")
+    ap.add_argument("--rechoose", metavar="JSON",
+                    help="no sweep: choose the entries again from the timings of a tuning.json")
     args = ap.parse_args()
+    if args.rechoose:
+        with open(args.rechoose) as f:
+            rec = json.load(f)
+        single, mixed, splits, batch = record_timings(rec)
+        os.makedirs(args.out_dir, exist_ok=True)
+        with open(os.path.join(args.out_dir, "tuning_table.inc"), "w") as f:
+            f.write(render_inc(choose_single(single, mixed, splits), choose_batch(batch),
+                               f"{rec.get('device', '?')}, timings of {os.path.basename(args.rechoose)}"))
+        return
 
     import numpy as np
     import torch
@@ -188,6 +241,8 @@ def main():
         # the splits of the chosen tile size and band (the walker has no band updates)
         (mb, band, schedule), _ = min(single[m].items(), key=lambda kv: kv[1])
         (mbx, bandx), _ = min(mixed[m].items(), key=lambda kv: kv[1])
+        record.setdefault("split_base", {})[str(m)] = {"fp64": f"mb={mb},band={band},schedule={schedule}",
+                                                       "mixed": f"mb={mbx},band={bandx}"}
         splits[m] = {"fp64": {}, "mixed": {}}
         for split in SPLITS if schedule == 1 else (0,):
             t = time_single(m, mb, band, schedule, Sd, Td, Z, sc, info, args.reps, split=split)

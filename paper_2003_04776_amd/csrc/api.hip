@@ -162,6 +162,7 @@ __host__ __device__ size_t carve(PencilDesc& P, char* base, int64_t m, int mb, i
   P.nu = c.take<double>(base, (size_t)Mmax * Mmax);
   P.exps = c.take<int32_t>(base, (size_t)Mmax * m);
   P.norms = c.take<double>(base, (size_t)Mmax * m);
+  P.segn = c.take<double>(base, (size_t)Mmax * m);
   P.W = c.take<double>(base, (size_t)wslots * Mmax * w_tile_doubles(mb));
   P.eW = c.take<int32_t>(base, (size_t)wslots * m);
   P.nW = c.take<double>(base, (size_t)wslots * m);
@@ -464,6 +465,7 @@ hipError_t enqueue_refine(const PencilDesc& P, const RefineDesc& R, int sweeps, 
   C.ldz = P.m;
   C.exps = R.cexps;
   C.norms = R.cnorms;
+  C.segn = nullptr;   // (the correction's segment maxima are not needed; z's stay)
   C.sel = R.rf;
   C.rhs = 1;
   C.tflag = R.tflag;

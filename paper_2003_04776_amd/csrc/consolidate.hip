@@ -3,8 +3,10 @@
 // the column's common exponent is E_c = max_k exps[k][c], and each segment is
 // rescaled by the exact power of two 2^(exps[k][c] - E_c) (flushing to zero when the
 // gap exceeds the exponent range).  Optionally each eigenvector is then divided by
-// max_i (|x_i| + |y_i|).  Rows below the eigenvector's tile and unselected columns
-// are zeroed.  One workgroup per eigenvalue (a complex pair is handled as one).
+// max_i (|x_i| + |y_i|), which comes from the per-segment maxima the solves recorded
+// (segn, scaled by the same powers of two), so Z is read and written once.  Rows below
+// the eigenvector's tile and unselected columns are zeroed.  One workgroup per
+// eigenvalue (a complex pair is handled as one).
 #include <hip/hip_runtime.h>
 
 #include "layout.hpp"
@@ -53,25 +55,40 @@ __device__ __forceinline__ void consolidate_body(const PencilDesc& P) {
   for (int k = threadIdx.x; k <= jt; k += kConsThreads) E = max(E, P.exps[(int64_t)k * m + c]);
   double Ed = block_max((double)E, red);   // exponents are exact in double
   E = (int)Ed;
-  // rescale every segment to the common exponent
+  // the normalisation: max_i |x_i| + |y_i| over the rescaled segments
   double nm = 0.0;
-  for (int64_t i = threadIdx.x; i < rend; i += kConsThreads) {
-    const int d = P.exps[(int64_t)P.tileof[i] * m + c] - E;
-    const double x = ldexp(zx[i], d);
-    zx[i] = x;
-    double v = fabs(x);
-    if (cplx) {
-      const double y = ldexp(zy[i], d);
-      zy[i] = y;
-      v += fabs(y);
-    }
-    nm = fmax(nm, v);
+  if (P.normalize) {
+    for (int k = threadIdx.x; k <= jt; k += kConsThreads)
+      nm = fmax(nm, ldexp(P.segn[(int64_t)k * m + c], P.exps[(int64_t)k * m + c] - E));
+    nm = block_max(nm, red);
   }
-  nm = block_max(nm, red);
-  if (P.normalize && nm > 0.0) {
-    for (int64_t i = threadIdx.x; i < rend; i += kConsThreads) {
-      zx[i] = zx[i] / nm;
-      if (cplx) zy[i] = zy[i] / nm;
+  // rescale every segment to the common exponent (and divide by the norm); a thread's
+  // kUnroll rows of a step are loaded before any is stored, so each keeps that many loads
+  // of the column in flight
+  const bool div = P.normalize && nm > 0.0;
+  constexpr int kUnroll = 4;
+  for (int64_t i0 = threadIdx.x; i0 < rend; i0 += kUnroll * kConsThreads) {
+    double x[kUnroll], y[kUnroll];
+    int d[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = i0 + u * kConsThreads;
+      const int64_t ir = i < rend ? i : rend - 1;   // (rows past the end: read, not stored)
+      x[u] = zx[ir];
+      y[u] = cplx ? zy[ir] : 0.0;
+      d[u] = P.exps[(int64_t)P.tileof[ir] * m + c] - E;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = i0 + u * kConsThreads;
+      if (i < rend) {
+        const double xs = ldexp(x[u], d[u]);
+        zx[i] = div ? xs / nm : xs;
+        if (cplx) {
+          const double ys = ldexp(y[u], d[u]);
+          zy[i] = div ? ys / nm : ys;
+        }
+      }
     }
   }
   for (int64_t i = rend + threadIdx.x; i < m; i += kConsThreads) {

@@ -60,6 +60,11 @@ struct PencilDesc {
   double* nu;
   int32_t* exps;
   double* norms;
+  // segn[t][c]: max over the rows of segment (t, c) of |x_i| + |y_i| for a complex pair (x
+  // its first column, y its second; stored at both), |x_i| for a real column, in the units
+  // of the segment's exponent: the final segments' norms for the normalisation (NULL in
+  // the descriptor of a refinement's correction solve, which leaves them alone)
+  double* segn;
   double* W;
   int32_t* eW;
   double* nW;

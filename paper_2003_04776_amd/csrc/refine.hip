@@ -556,25 +556,43 @@ __device__ __forceinline__ void apply_column(const PencilDesc& P, const RefineDe
   if (kind == 2 || !R.rf[c]) return;
   const int jt = P.tileof[c];
   const int64_t blk_end = c + (kind == 0 ? 1 : 2);
-  for (int q = 0; q < (kind == 1 ? 2 : 1); ++q) {
-    const int64_t cc = c + q;
-    double* z = P.Z + cc * P.ldz;
-    const double* d = R.Zc + cc * m;
-    for (int t = 0; t <= jt; ++t) {
-      const int r0 = P.edges[t], r1 = P.edges[t + 1];
-      const int64_t e = (int64_t)t * m + cc;
-      const int sh = R.cexps[e] - P.exps[e];
-      double nm = 0.0;
-      for (int64_t i = r0 + threadIdx.x; i < r1; i += kRefThreads) {
-        double v = z[i];
-        if (i < blk_end) {
-          v -= ldexp(d[i], sh);
-          z[i] = v;
+  const bool pair = kind == 1;
+  // a pair's two columns together (they share every segment exponent), so the segment's
+  // max |x_i| + |y_i| is formed as well
+  double* zx = P.Z + c * P.ldz;
+  double* zy = pair ? zx + P.ldz : zx;
+  const double* dx = R.Zc + c * m;
+  const double* dy = pair ? dx + m : dx;
+  for (int t = 0; t <= jt; ++t) {
+    const int r0 = P.edges[t], r1 = P.edges[t + 1];
+    const int64_t e = (int64_t)t * m + c;
+    const int shx = R.cexps[e] - P.exps[e];
+    const int shy = pair ? R.cexps[e + 1] - P.exps[e + 1] : shx;
+    double nx = 0.0, ny = 0.0, ns = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kRefThreads) {
+      double x = zx[i], y = pair ? zy[i] : 0.0;
+      if (i < blk_end) {
+        x -= ldexp(dx[i], shx);
+        zx[i] = x;
+        if (pair) {
+          y -= ldexp(dy[i], shy);
+          zy[i] = y;
         }
-        nm = fmax(nm, fabs(v));
       }
-      nm = wg_max(nm, red);
-      if (threadIdx.x == 0) P.norms[e] = nm;
+      nx = fmax(nx, fabs(x));
+      ny = fmax(ny, fabs(y));
+      ns = fmax(ns, fabs(x) + fabs(y));
+    }
+    nx = wg_max(nx, red);
+    ny = wg_max(ny, red);
+    ns = wg_max(ns, red);
+    if (threadIdx.x == 0) {
+      P.norms[e] = nx;
+      P.segn[e] = ns;
+      if (pair) {
+        P.norms[e + 1] = ny;
+        P.segn[e + 1] = ns;
+      }
     }
   }
 }

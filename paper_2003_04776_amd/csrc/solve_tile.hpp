@@ -625,14 +625,25 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
   __syncthreads();
   if (kind == 2) e = ecol[lc];
 
-  // ---- segment norm and exponent ----
-  double nx = 0.0;
+  // ---- segment norms and exponent ----
+  double nx = 0.0, ns = 0.0;   // max |x_i|; max |x_i| + |y_i| of a pair (its first column's thread)
   if (inrange)
-    for (int i = 0; i < hr; ++i) nx = fmax(nx, fabs(Y[i * LDY + lc]));
+    for (int i = 0; i < hr; ++i) {
+      const double ax = fabs(Y[i * LDY + lc]);
+      nx = fmax(nx, ax);
+      if (pair) ns = fmax(ns, ax + fabs(Y[i * LDY + lc + 1]));
+    }
   if (colthr) cmax[lc] = nx;
   if (own) {
     P.exps[(int64_t)r * m + c] = e;
     P.norms[(int64_t)r * m + c] = nx;
+    if (P.segn) {   // (none for a correction solve)
+      if (kind == 0) P.segn[(int64_t)r * m + c] = nx;
+      if (pair) {
+        P.segn[(int64_t)r * m + c] = ns;
+        P.segn[(int64_t)r * m + c + 1] = ns;
+      }
+    }
   }
   if (flags) atomicOr(P.info, flags);
   __syncthreads();

@@ -28,6 +28,34 @@ def test_choose_single_and_batch():
     assert "{INT64_MAX, 128, 4, 1, 0, 128, 8, 2048}" in text and "{128, 32}" in text
 
 
+def test_choose_split_keeps_one_launch_within_noise():
+    """A split is tabulated only when it beats one launch per band by more than 1 %, and
+    splits at least as large as the pencil's tile count (the same launches as one per band)
+    are not candidates."""
+    assert autotune.choose_split({0: 100.0, 1024: 99.5, 4096: 101.0}, 10 ** 6) == 0
+    assert autotune.choose_split({0: 100.0, 1024: 90.0, 4096: 95.0}, 10 ** 6) == 1024
+    assert autotune.choose_split({0: 100.0, 8192: 90.0}, 16) == 0
+    assert autotune.choose_split({}, 16) == 0 and autotune.choose_split(None) == 0
+
+
+def test_rechoose_from_recorded_timings():
+    """record_timings reads back what a sweep records (tile sizes, bands, schedules, the split
+    sweep on a built table's choices, batches), and choosing from it gives the same table."""
+    rec = {"single": {"4096": {"mb=64,band=2,schedule=1": 5.0, "mb=128,band=1,schedule=2": 4.0}},
+           "mixed": {"4096": {"mb=64,band=8": 6.0}},
+           "split_base": {"32768": {"fp64": "mb=128,band=4,schedule=1", "mixed": "mb=128,band=8"}},
+           "split": {"32768": {"fp64,split=0": 500.0, "fp64,split=1024": 600.0, "mixed,split=0": 400.0,
+                               "mixed,split=1024": 360.0}},
+           "batch": {"64-128": {"mb=32": 1.0, "mb=64": 2.0}}}
+    single, mixed, splits, batch = autotune.record_timings(rec)
+    assert single == {4096: {(64, 2, 1): 5.0, (128, 1, 2): 4.0}, 32768: {(128, 4, 1): 0.0}}
+    assert mixed == {4096: {(64, 8): 6.0}, 32768: {(128, 8): 0.0}}
+    assert splits == {32768: {"fp64": {0: 500.0, 1024: 600.0}, "mixed": {0: 400.0, 1024: 360.0}}}
+    assert batch == {(64, 128): {32: 1.0, 64: 2.0}}
+    assert autotune.choose_single(single, mixed, splits) == [(11585, 128, 1, 2, 0, 64, 8, 0),
+                                                            (None, 128, 4, 1, 0, 128, 8, 1024)]
+
+
 def _parse_inc():
     text = open(os.path.join(HERE, "csrc", "tuning_table.inc")).read()
     single_txt = text.split("kTuneSingle[] = {")[1].split("};")[0]
