@@ -10,7 +10,9 @@ algorithmic count F(m) = 2 m^3 / 3 (each eigenvector of order p costs 2 p^2 flop
 
 Prints one JSON line (rank 0) with the roofline of the dominant kernel (the FP64-MFMA
 tile update, timed with HIP events on the stream it runs on) and the CPU oracle timed
-on a column sample of the same pencil.
+on a column sample of the same pencil.  Extra keys time the other configurations: the
+mixed-precision mode, left eigenvectors, the back-transformation, a complex pencil of
+order m / 2, one pencil of order 8192 (order_8192) and the batch of 512 pencils (batched).
 """
 from __future__ import annotations
 
@@ -33,7 +35,7 @@ METRIC = "FP64-equiv TFLOP/s + time for all eigvecs at m=32768; mixed/FP64 speed
 # WRITE_SIZE, scaled by what the counters read for a plain 1 GiB device copy), for the default
 # workload; valid only while the kernel's sources hash to the value they had when the counters
 # were taken (profiles/update_kernel_m32768_fp64_traffic.md).
-TRAFFIC = {"sources_sha256_16": "a95ad599ad1295a8", "bytes_per_launch": 1.818e9,
+TRAFFIC = {"sources_sha256_16": "87b904c97f481c5c", "bytes_per_launch": 1.812e9,
            "workload": (32768, 128, 4, 1)}   # m, mb, band, schedule
 
 
@@ -151,24 +153,25 @@ def backward_error_stats(Sd, Td, Z, ar, ai, be, kind):
     return {"median": float(np.median(om)), "p99": float(np.quantile(om, 0.99)), "max": float(om.max())}
 
 
-def bench_batched(args):
-    """The batch workload: 512 pencils of orders U{64..2048} (seed 3999), pencil i from
+def run_batched(count, mb, band, steps, warmup):
+    """The batch workload: `count` pencils of orders U{64..2048} (seed 3999), pencil i from
     seed 3000 + i, all eigenvectors, one rtgevc_batched call captured in a graph; times
-    graph replays with events on the replay stream."""
+    graph replays with events on the replay stream.  Returns (ms per replay, wall ms per
+    replay, flops, orders, info nonzero count)."""
     import numpy as np
     import torch
 
     from paper_2003_04776_amd import pencils
     from paper_2003_04776_amd import rtgevc as rt
 
-    ms = [int(v) for v in pencils.batch_sizes(args.count)]
+    ms = [int(v) for v in pencils.batch_sizes(count)]
     log(f"[bench] generating {len(ms)} pencils, sum m = {sum(ms)}")
     Sd, Td = [], []
     for i, m in enumerate(ms):
         S, T, _ = pencils.schur_pencil(m, 3000 + i)
         Sd.append(rt.colmajor_to_device(S))
         Td.append(rt.colmajor_to_device(T))
-    bs = rt.BatchSolver(ms, mb=args.mb, band=args.band)
+    bs = rt.BatchSolver(ms, mb=mb, band=band)
     Z, sc, info = bs.outputs()
     bs.run(Sd, Td, Z, sc, info)
     torch.cuda.synchronize()
@@ -179,12 +182,12 @@ def bench_batched(args):
         with torch.cuda.graph(g, stream=st):
             bs.run(Sd, Td, Z, sc, info)
     torch.cuda.synchronize()
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         g.replay()
     torch.cuda.synchronize()
     times = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         g.replay()
@@ -193,21 +196,63 @@ def bench_batched(args):
         times.append(e0.elapsed_time(e1))
     wall = time.perf_counter() - t0
     F = float(sum(2.0 * m ** 3 / 3.0 for m in ms))
-    med = float(np.median(times))
+    nz = int((info != 0).sum().item())
+    del g, bs, Z, sc, info, Sd, Td
+    torch.cuda.empty_cache()
+    return float(np.median(times)), wall / max(steps, 1) * 1e3, F, ms, nz
+
+
+def batch_config(ms, mb, band):
+    from paper_2003_04776_amd import rtgevc as rt
+    return {"workload": f"{len(ms)} independent real Schur pencils, orders U{{64..2048}} (seed 3999), all "
+                        f"eigenvectors, robust FP64, one batched call replayed from a graph",
+            "sum_m": sum(ms), "mb": mb or "automatic",
+            "band": rt.resolve_opts(max(ms), batched=True, mb=mb, band=band)[1]}
+
+
+def bench_batched(args):
+    """--workload batched: the batch as the main line."""
+    med, wall, F, ms, nz = run_batched(args.count, args.mb, args.band, args.steps, args.warmup)
     out = {
         "metric": "FP64-equiv TFLOP/s, batch of pencils (graph replay)",
         "value": round(F / (med * 1e-3) / 1e12, 4),
         "unit": "TFLOP/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(med, 3), "wall_ms_per_step": round(wall / max(args.steps, 1) * 1e3, 3),
+        "ms_per_step": round(med, 3), "wall_ms_per_step": round(wall, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{len(ms)} independent real Schur pencils, orders U{{64..2048}} (seed 3999), all "
-                               f"eigenvectors, robust FP64, one batched call replayed from a graph",
-                   "sum_m": sum(ms), "flops_per_step": F, "mb": args.mb or "automatic",
-                   "band": rt.resolve_opts(max(ms), batched=True, mb=args.mb, band=args.band)[1]},
-        "info_nonzero": int((info != 0).sum().item()),
+        "config": dict(batch_config(ms, args.mb, args.band), flops_per_step=F),
+        "info_nonzero": nz,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_order(args, m2):
+    """One pencil of order m2 (the seeded normal generator, seed + 11), all eigenvectors with
+    the automatic options, FP64 and mixed precision (default refinement), timed with events
+    around each product call."""
+    import torch
+    from paper_2003_04776_amd import pencils
+    from paper_2003_04776_amd import rtgevc as rt
+    log(f"[bench] order {m2}")
+    S, T, _ = pencils.schur_pencil(m2, args.seed + 11, threads=16)
+    Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
+    del S, T
+    F = 2.0 * m2 ** 3 / 3.0
+    res = {"what": f"all right eigenvectors, order {m2}, automatic options", "flops_per_call": F}
+    for name, prec in (("fp64", 0), ("mixed", 1)):
+        sv = rt.Solver(m2, precision=prec)
+        Z = rt.colmajor_empty(m2)
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        ms, _ = time_calls(lambda: sv.run(Sd, Td, Z=Z, info=info), max(args.steps, 5), max(args.warmup, 1))
+        mb, band, split = rt.resolve_opts(m2, precision=prec, with_split=True)
+        res[name] = {"ms_per_call": round(ms, 3), "value": round(F / (ms * 1e-3) / 1e12, 4),
+                     "unit": "FP64-equiv TFLOP/s", "mb": mb, "band": band, "split": split,
+                     "info": int(info.item())}
+        log(f"[bench] order {m2} {name}: {ms:.2f} ms")
+        del sv, Z
+    del Sd, Td
+    torch.cuda.empty_cache()
+    return res
 
 
 def residual_max(Sd, Td, Z, ar, ai, be, kind):
@@ -359,6 +404,8 @@ def main():
                     help="skip the left eigenvectors timed after the right ones")
     ap.add_argument("--no-back", dest="back", action="store_false",
                     help="skip the back-transformation X = V Z timed after the eigenvectors")
+    ap.add_argument("--no-extra", dest="extra", action="store_false",
+                    help="skip the order-8192 pencil and the batch of --count pencils timed after the headline")
     ap.add_argument("--no-complex", dest="complex", action="store_false",
                     help="skip the complex pencil of order m / 2 timed after the real one")
     ap.add_argument("--seed", type=int, default=400)
@@ -549,6 +596,15 @@ def main():
         out["backtransform"] = bench_back(args, m, Sd, Zf, scales, blk)
     if args.complex and args.precision == 0:
         out["complex"] = bench_complex(args, m // 2)
+    if args.extra and args.precision == 0 and m > 8192:
+        # the other configurations of the headline: a smaller order and the batch
+        out["order_8192"] = bench_order(args, 8192)
+        med, wall, Fb, msb, nzb = run_batched(args.count, 0, 0, max(args.steps, 5), max(args.warmup, 2))
+        out["batched"] = {"config": batch_config(msb, 0, 0), "ms_per_call": round(med, 3),
+                          "wall_ms_per_call": round(wall, 3), "flops_per_call": Fb,
+                          "value": round(Fb / (med * 1e-3) / 1e12, 4), "unit": "FP64-equiv TFLOP/s",
+                          "info_nonzero": nzb}
+        log(f"[bench] batch of {len(msb)}: {med:.2f} ms")
     if rank == 0 and not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a column sample")
         out["cpu_baseline"], idx, Zo = cpu_baseline(S, T, blk, m, args.cpu_seconds)
