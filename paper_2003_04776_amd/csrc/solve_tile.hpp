@@ -281,6 +281,9 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
   const double csg = (P.cform && pair) ? (P.S[(c + 1) + c * P.lds] > 0.0 ? 1.0 : -1.0) : 0.0;
   int e = 0;
   double ybound = 0.0;
+  // largest |x_i|, |y_i| and |x_i| + |y_i| of the solved rows, at their current scale (a
+  // column's thread; scaling by powers of two keeps them exact): the segment norms
+  double tnx = 0.0, tny = 0.0, tns = 0.0;
   int flags = 0;
 
   // ---- structure and column norms of the diagonal tile, right-hand side Y_rj ----
@@ -296,22 +299,30 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
     tcnS[lc] = P.cnS[r0 + lc];
     tcnT[lc] = P.cnT[r0 + lc];
   }
-  for (int idx = lc; idx < MB * LDY; idx += NTOT) Y[idx] = 0.0;
-  __syncthreads();
-  if (!tip || P.rhs) {
-    // (in correction mode the tip tile too starts from the right-hand side held in Z)
-    // thread lc reads row lc of every column (coalesced down the columns), 16 loads in flight
-    if (lc < hr) {
-      const double* zrow = P.Z + (r0 + lc) + (int64_t)(c0 + lo) * ldz;
-      for (int col0 = 0; col0 < hw; col0 += 16) {
+  // (in correction mode the tip tile too starts from the right-hand side held in Z)
+  const bool loaded = !tip || P.rhs;
+  if (!loaded) {
+    // the tip tile starts from zero (the right-hand side of the tip's own system)
+    for (int idx = lc; idx < MB * LDY; idx += NTOT) Y[idx] = 0.0;
+  } else {
+    // thread t reads row t mod MB of one half of the columns (coalesced down the columns),
+    // 16 loads in flight; entries of Y past the tile are never used, so nothing is cleared
+    static_assert(NTOT >= 2 * MB, "two threads per row");
+    const int row = lc % MB, half = (lc / MB) & 1;
+    const int hw2 = (hw + 1) / 2, ca = half ? hw2 : 0, cb = half ? hw : hw2;
+    if (lc < 2 * MB && row < hr) {
+      const double* zrow = P.Z + (r0 + row) + (int64_t)(c0 + lo) * ldz;
+      for (int col0 = ca; col0 < cb; col0 += 16) {
         double v[16];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) v[t] = (col0 + t < hw) ? zrow[(int64_t)(col0 + t) * ldz] : 0.0;
+        for (int t = 0; t < 16; ++t) v[t] = (col0 + t < cb) ? zrow[(int64_t)(col0 + t) * ldz] : 0.0;
 #pragma unroll
         for (int t = 0; t < 16; ++t)
-          if (col0 + t < hw) Y[lc * LDY + col0 + t] = v[t];
+          if (col0 + t < cb) Y[row * LDY + col0 + t] = v[t];
       }
     }
+  }
+  if (loaded) {
     if (inrange) {
       e = P.exps[(int64_t)r * m + c];
       ybound = P.norms[(int64_t)r * m + c] + (kind != 0 ? P.norms[(int64_t)r * m + c0 + lo + partner] : 0.0);
@@ -357,6 +368,121 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
 
   static_assert(G == 8, "the group's rows are one 8-wide register vector");
   typedef double d8 __attribute__((ext_vector_type(8)));
+  // The column waves run the substitution.  A group's rank-2G update of the rows above it is
+  // split: the rows of the next group first, by all waves before that group starts, then the
+  // rest by the helper waves (the waves past the columns) while the column waves substitute
+  // the next group; with no helper wave (tiles of 32) the whole update comes first.
+  constexpr int NCW = (NCY + 63) / 64, NHW = NTOT / 64 - NCW;
+  // B operand entry (k, n) of the update by the group [bg0, bg1]: row bg0 + (k mod G) of column
+  // n, -beta z (k < G) or alpha z (k >= G), own parts (a pair's real part in its first column,
+  // imaginary in its second); zero for rows past the group and for columns not solved
+  auto bop = [&](int k, int n, int bg0, int bg1) -> double {
+    const int i = bg0 + (k & (G - 1));
+    const int ir = i <= bg1 ? i : bg1;   // (rows past the group: read in range, dropped)
+    const int kd = colKind[n];
+    const int np = kd == 1 ? n + 1 : (kd == 2 ? n - 1 : n);
+    const double own = Y[ir * LDY + n], oth = Y[ir * LDY + np];
+    const double zr = kd == 2 ? oth : own, zi = kd == 0 ? 0.0 : (kd == 1 ? oth : own);
+    const double an = colA[n], bn = colB[n];
+    const double v = k < G ? -colBe[n] * own : (kd == 2 ? (bn * zr + an * zi) : (an * zr - bn * zi));
+    return (i <= bg1 && colOn[n]) ? v : 0.0;
+  };
+  // Y[rlo:rhi, :] <- 2^-fcol Y[rlo:rhi, :] + [S | T][rlo:rhi, group] * [-beta z ; alpha z] for
+  // the group [bg0, bg1] (rhi <= bg0).  A fragments: rows 16 rb + lane % 16 of the group's
+  // columns (S then T), masked past the rows above the group and the group's columns.
+  auto afrag = [&](int rb, int st, int bg0, int bg1) -> double {
+    const int row = 16 * rb + lane % 16;
+    const int kk = 4 * st + lane / 16;   // 0..15: S columns 0..7, T columns 8..15
+    const int col = bg0 + (kk & (G - 1));
+    const bool ok = row < bg0 && col <= bg1;
+    const int64_t ro = ok ? r0 + row : 0, co = ok ? r0 + col : 0;
+    return kk < G ? S[ro + co * lds] : T[ro + co * ldt];
+  };
+  // one 16-row block rb of column block cb: acc <- 2^-fs Y + A B, rows in [rlo, rhi) stored
+  auto rank_block = [&](const double (&a4)[4], const double (&bf)[4], int rb, int cb, int rlo, int rhi) {
+    const int col = 16 * cb + lane % 16;
+    const int colr = col < NCY ? col : NCY - 1;   // (columns past those held: dropped)
+    const int fs = fcol[colr];
+    d4 acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = ldexp(Y[(16 * rb + lane / 16 + 4 * v) * LDY + colr], -fs);
+#pragma unroll
+    for (int st = 0; st < 4; ++st) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(psc * a4[st], bf[st], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * rb + lane / 16 + 4 * v;
+      if (row >= rlo && row < rhi && col < hw) Y[row * LDY + col] = acc[v];
+    }
+  };
+  auto bfrag = [&](double (&bf)[4], int cb, int bg0, int bg1) {
+    const int col = 16 * cb + lane % 16;
+    const int colr = col < NCY ? col : NCY - 1;
+#pragma unroll
+    for (int st = 0; st < 4; ++st) bf[st] = bop(4 * st + lane / 16, colr, bg0, bg1);
+  };
+  // the rows of the next group, [rlo, rhi) within two row blocks from rlo / 16, by every wave
+  // (its column blocks strided); the A fragments in au were loaded before
+  auto rank_near = [&](const double (&au)[2][4], int rlo, int rhi, int bg0, int bg1) {
+    if (rhi <= rlo) return;
+    const int rb0 = rlo / 16, nb = (rhi - 1) / 16 - rb0 + 1;   // 1 or 2 row blocks
+    const int ncb = (hw + 15) / 16;
+    for (int cb = wave; cb < ncb; cb += NTOT / 64) {
+      double bf[4];
+      bfrag(bf, cb, bg0, bg1);
+      rank_block(au[0], bf, rb0, cb, rlo, rhi);
+      if (nb > 1) rank_block(au[1], bf, rb0 + 1, cb, rlo, rhi);
+    }
+  };
+  // the rows [0, rhi), by waves wv0 .. wv0 + nwv - 1, each owning whole column blocks: row
+  // blocks in chunks of NRC, a chunk's row blocks independent chains issued interleaved.
+  // Every operand index is a constant, so the operands stay in registers.
+  constexpr int NR0 = MB / 16;
+  auto rank_far = [&](auto nrc_c, int rhi, int bg0, int bg1, int wv0, int nwv) {
+    constexpr int NRC = decltype(nrc_c)::value;
+    if (rhi <= 0 || wave < wv0 || wave >= wv0 + nwv) return;
+    const int rb_hi = (rhi + 15) / 16;
+    const int ncb = (hw + 15) / 16;
+    // every row block's A fragments at once (one memory latency for all of them)
+    double af[NR0][4];
+#pragma unroll
+    for (int rb = 0; rb < NR0; ++rb)
+#pragma unroll
+      for (int st = 0; st < 4; ++st) af[rb][st] = rb < rb_hi ? afrag(rb, st, bg0, bg1) : 0.0;
+    // column blocks (a runtime loop, so its addresses are not hoisted out of the group loop),
+    // each with its B fragments formed once and its chunks' row blocks as independent chains
+#pragma unroll 1
+    for (int cb = wave - wv0; cb < ncb; cb += nwv) {
+      const int col = 16 * cb + lane % 16;
+      const int colr = col < NCY ? col : NCY - 1;
+      const int fs = fcol[colr];
+      double bf[4];
+      bfrag(bf, cb, bg0, bg1);
+#pragma unroll
+      for (int ch = 0; ch < NR0 / NRC; ++ch) {
+        if (NRC * ch >= rb_hi) continue;
+        d4 acc[NRC];
+#pragma unroll
+        for (int i = 0; i < NRC; ++i)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            acc[i][v] = ldexp(Y[(16 * (NRC * ch + i) + lane / 16 + 4 * v) * LDY + colr], -fs);
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+#pragma unroll
+          for (int i = 0; i < NRC; ++i)
+            acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(psc * af[NRC * ch + i][st], bf[st], acc[i], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < NRC; ++i)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = 16 * (NRC * ch + i) + lane / 16 + 4 * v;
+            if (row < rhi && col < hw) Y[row * LDY + col] = acc[i][v];
+          }
+      }
+    }
+  };
+  constexpr int NRC_BIG = NR0 < 4 ? NR0 : 4;
+  int dg0 = 0, dg1 = 0, drh = 0;   // deferred: rows [0, drh) take the update of the group [dg0, dg1]
   while (g1 >= 0) {
     const int gn1 = g0 - 1;                       // next group
     const int gn0 = gn1 >= 0 ? group_lo(gn1) : -1;
@@ -364,169 +490,176 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
     double yb_above = ybound;   // bound on the rows above the group
     int qsg = 0;                // scaling raised inside the group
     double zng = 0.0;           // largest |z|_1 of the group's solved rows (at their current scale)
+    double cng = 0.0;           // sum over the group's rows of beta |S col|_1 + |alpha| |T col|_1
 
-    // ---- blocks of the group, bottom up; updates stay inside the group ----
-    // Each column's substitution is private to the thread that owns it (a complex pair
-    // belongs to the thread of its first column), so the blocks need no barrier.  The
-    // group's rows live in registers, (yr[k], yi[k]) = row g0 + k: a block reads its rows
-    // by a uniform index, and its update is applied to all G rows with the block's full
-    // panel columns (rows at or below the block are no longer used, so nothing has to
-    // move and every other register index is a constant).  Every lane runs the solve;
-    // work marks the lanes whose result is used, and the others take z = 0, so their
-    // rows are left as they were.
-    d8 yr, yi;
-    d8 cnv;   // beta |S col|_1 + |alpha| |T col|_1 of the group's rows (zero past the group)
-    const int yc0 = lc < NCY ? lc : 0, yc1 = pair ? lc + 1 : yc0;   // (threads past the columns read column 0)
-#pragma unroll
-    for (int k = 0; k < G; ++k) {
-      const int row = g0 + k <= g1 ? g0 + k : g1;   // (rows past the group: never used)
-      yr[k] = Y[row * LDY + yc0];
-      yi[k] = pair ? Y[row * LDY + yc1] : 0.0;
-      cnv[k] = g0 + k <= g1 ? be * tcnS[row] + aabs * tcnT[row] : 0.0;
-    }
-    const double cng = ((cnv[0] + cnv[1]) + (cnv[2] + cnv[3])) + ((cnv[4] + cnv[5]) + (cnv[6] + cnv[7]));
-    // a block's solved rows: rescale what is already solved if the block raised the
-    // scaling (rare: scaling has head room), store, and extend the group's bound
-    auto settle = [&](int q0, int q, int qs, Cx z0, Cx z1, double cn) {
-      if (qs > 0) {
-        yr = d8{ldexp(yr[0], -qs), ldexp(yr[1], -qs), ldexp(yr[2], -qs), ldexp(yr[3], -qs),
-                ldexp(yr[4], -qs), ldexp(yr[5], -qs), ldexp(yr[6], -qs), ldexp(yr[7], -qs)};
-        yi = d8{ldexp(yi[0], -qs), ldexp(yi[1], -qs), ldexp(yi[2], -qs), ldexp(yi[3], -qs),
-                ldexp(yi[4], -qs), ldexp(yi[5], -qs), ldexp(yi[6], -qs), ldexp(yi[7], -qs)};
-        for (int i = q + 1; i <= g1; ++i) {
-          Y[i * LDY + lc] = ldexp(Y[i * LDY + lc], -qs);
-          if (pair) Y[i * LDY + lc + 1] = ldexp(Y[i * LDY + lc + 1], -qs);
-        }
-        qsg += qs;
-        e += qs;
-        ybound = ldexp(ybound, -qs);
-        yb_above = ldexp(yb_above, -qs);
-        zng = ldexp(zng, -qs);
+    if (wave < NCW) {
+      // ---- blocks of the group, bottom up; updates stay inside the group ----
+      // Each column's substitution is private to the thread that owns it (a complex pair
+      // belongs to the thread of its first column), so the blocks need no barrier.  The
+      // group's rows live in registers, (yr[k], yi[k]) = row g0 + k: a block reads its rows
+      // by a uniform index, and its update is applied to all G rows with the block's full
+      // panel columns (rows at or below the block are no longer used, so nothing has to
+      // move and every other register index is a constant).  Every lane runs the solve;
+      // work marks the lanes whose result is used, and the others take z = 0, so their
+      // rows are left as they were.
+      d8 yr, yi;
+      d8 cnv;   // beta |S col|_1 + |alpha| |T col|_1 of the group's rows (zero past the group)
+      const int yc0 = lc < NCY ? lc : 0, yc1 = pair ? lc + 1 : yc0;   // (threads past the columns read column 0)
+  #pragma unroll
+      for (int k = 0; k < G; ++k) {
+        const int row = g0 + k <= g1 ? g0 + k : g1;   // (rows past the group: never used)
+        yr[k] = Y[row * LDY + yc0];
+        yi[k] = pair ? Y[row * LDY + yc1] : 0.0;
+        cnv[k] = g0 + k <= g1 ? be * tcnS[row] + aabs * tcnT[row] : 0.0;
       }
-      Y[q0 * LDY + lc] = z0.r;
-      if (pair) Y[q0 * LDY + lc + 1] = z0.i;
-      if (q != q0) {
-        Y[q * LDY + lc] = z1.r;
-        if (pair) Y[q * LDY + lc + 1] = z1.i;
-      }
-      const double zn = fmax(cn1(z0), cn1(z1));
-      zng = fmax(zng, zn);
-      if (q0 > 0) ybound = fma(cn, zn, ybound);
-    };
-    int q = g1;
-    while (q >= g0) {
-      // a block: rows q0 .. q (q0 = q for a 1x1 block), local rows lq0 .. lq
-      const bool two = second(q);
-      const int q0 = two ? q - 1 : q;
-      const int lq0 = q0 - g0, lq = q - g0;
-      const Cx y0 = cx(yr[lq0], yi[lq0]), y1 = cx(yr[lq], yi[lq]);
-      const double cn = two ? cnv[lq0] + cnv[lq] : cnv[lq];
-      const bool work = owner && !(tip && q0 > pc);
-      const bool at_tip = tip && q0 == pc;   // the column's own block (singular for its eigenvalue)
-      const bool act = work && !at_tip;
-      int qs = 0;
-      Cx z0, z1;
-      if (!two) {
-        // ---- 1x1 block ----
-        z0 = solve1(a, b, be, Pn[0][lq][lq], Pn[1][lq][lq], y1, qs, flags, act);
-        z1 = cx(0.0, 0.0);
-        if (at_tip) {
-          // the tip of a real eigenvalue (zero in correction mode)
-          z0 = cx(P.rhs ? 0.0 : 1.0, 0.0);
-          qs = 0;
-        }
-      } else {
-        // ---- 2x2 block ----
-        const double s00 = Pn[0][lq0][lq0], s10 = Pn[0][lq0][lq], s01 = Pn[0][lq][lq0], s11 = Pn[0][lq][lq];
-        const double t00 = Pn[1][lq0][lq0], t01 = Pn[1][lq][lq0], t11 = Pn[1][lq][lq];
-        z0 = y0;
-        z1 = y1;
-        if (P.cform) {
-          // real form of a complex pencil: a complex column in its subspace, a real one as usual
-          Cx c0 = z0, c1 = z1, g0v = z0, g1v = z1;
-          int qc = 0, qg = 0;
-          solve2c(a, b, be, s00, s10, t00, csg, c0, c1, qc, flags, act && csg != 0.0);
-          solve2(a, b, be, s00, s01, s10, s11, t00, t01, t11, g0v, g1v, qg, flags, act && csg == 0.0);
-          z0 = csg != 0.0 ? c0 : g0v;
-          z1 = csg != 0.0 ? c1 : g1v;
-          qs = csg != 0.0 ? qc : qg;
-        } else {
-          solve2(a, b, be, s00, s01, s10, s11, t00, t01, t11, z0, z1, qs, flags, act);
-        }
-        if (tip) {
-          // the column's own block: the tip
-          Cx tz0 = cx(0.0, 0.0), tz1 = cx(0.0, 0.0);
-          int tq = 0;
-          if (P.rhs) {
-            // correction mode: the correction is zero at the tip (z0 = z1 = 0)
-          } else if (csg != 0.0) {
-            // real form of a complex pencil: the tip in the column's subspace, (sg i, 1), exactly
-            tz0 = cx(0.0, csg);
-            tz1 = cx(1.0, 0.0);
-          } else {
-            // second row of the singular block beta S_b - alpha T_b gives z_p for z_{p+1} = 1
-            double m21 = be * s10;
-            const Cx nn = cx(-(be * s11 - a * t11), b * t11);
-            const double smin = local_smin(be, aabs, fmax(fabs(s10), fabs(s11)), fabs(t11));
-            const bool pert = fabs(m21) < smin;
-            m21 = pert ? smin : m21;
-            flags |= (pert && work && at_tip) ? kInfoPerturbed : 0;
-            tq = with_margin(protect_division_fast(cn1(nn), fabs(m21), work && at_tip));
-            const Cx ns = cscl(nn, tq);
-            const double rm = recip(m21);
-            tz0 = cx(ns.r * rm, ns.i * rm);
-            tz1 = cx(ldexp(1.0, -tq), 0.0);
+      cng = ((cnv[0] + cnv[1]) + (cnv[2] + cnv[3])) + ((cnv[4] + cnv[5]) + (cnv[6] + cnv[7]));
+      // a block's solved rows: rescale what is already solved if the block raised the
+      // scaling (rare: scaling has head room), store, and extend the group's bound
+      auto settle = [&](int q0, int q, int qs, Cx z0, Cx z1, double cn) {
+        if (qs > 0) {
+          yr = d8{ldexp(yr[0], -qs), ldexp(yr[1], -qs), ldexp(yr[2], -qs), ldexp(yr[3], -qs),
+                  ldexp(yr[4], -qs), ldexp(yr[5], -qs), ldexp(yr[6], -qs), ldexp(yr[7], -qs)};
+          yi = d8{ldexp(yi[0], -qs), ldexp(yi[1], -qs), ldexp(yi[2], -qs), ldexp(yi[3], -qs),
+                  ldexp(yi[4], -qs), ldexp(yi[5], -qs), ldexp(yi[6], -qs), ldexp(yi[7], -qs)};
+          for (int i = q + 1; i <= g1; ++i) {
+            Y[i * LDY + lc] = ldexp(Y[i * LDY + lc], -qs);
+            if (pair) Y[i * LDY + lc + 1] = ldexp(Y[i * LDY + lc + 1], -qs);
           }
-          if (at_tip) {
-            z0 = tz0;
-            z1 = tz1;
-            qs = tq;
-          }
+          qsg += qs;
+          e += qs;
+          ybound = ldexp(ybound, -qs);
+          yb_above = ldexp(yb_above, -qs);
+          zng = ldexp(zng, -qs);
+          tnx = ldexp(tnx, -qs);
+          tny = ldexp(tny, -qs);
+          tns = ldexp(tns, -qs);
         }
-      }
-      if (q0 > 0) {
-        // ProtectUpdate for y[0:q0] -= (beta S - alpha T)[0:q0, q0..q] z (inside the group
-        // now, above it at the end of the group; the column norms bound both)
-        const int qu = with_margin(protect_update_fast(cn, fmax(cn1(z0), cn1(z1)), ldexp(ybound, -qs), work));
-        z0 = cscl(z0, qu);
-        z1 = cscl(z1, qu);
-        qs += qu;
-      }
-      z0 = work ? z0 : cx(0.0, 0.0);
-      z1 = work ? z1 : cx(0.0, 0.0);
-      if (work) settle(q0, q, qs, z0, z1, cn);
-      // y += S (-beta z) + T (alpha z) with the block's columns
-      auto apply = [&](int c, Cx z) {
-        const d8 cs = *reinterpret_cast<const d8*>(&Pn[0][c][0]);
-        const d8 ct = *reinterpret_cast<const d8*>(&Pn[1][c][0]);
-        const double ur = -be * z.r, ui = -be * z.i;
-        const double vr = a * z.r - b * z.i, vi = a * z.i + b * z.r;
-#pragma unroll
-        for (int k = 0; k < G; ++k) {
-          yr[k] = fma(ct[k], vr, fma(cs[k], ur, yr[k]));
-          yi[k] = fma(ct[k], vi, fma(cs[k], ui, yi[k]));
+        Y[q0 * LDY + lc] = z0.r;
+        if (pair) Y[q0 * LDY + lc + 1] = z0.i;
+        if (q != q0) {
+          Y[q * LDY + lc] = z1.r;
+          if (pair) Y[q * LDY + lc + 1] = z1.i;
         }
+        const double zn = fmax(cn1(z0), cn1(z1));
+        zng = fmax(zng, zn);
+        tnx = fmax(tnx, fmax(fabs(z0.r), fabs(z1.r)));
+        tny = fmax(tny, fmax(fabs(z0.i), fabs(z1.i)));
+        tns = fmax(tns, zn);
+        if (q0 > 0) ybound = fma(cn, zn, ybound);
       };
-      apply(lq0, z0);
-      if (two) apply(lq, z1);
-      q = q0 - 1;
-    }
-
-    // operands of the rank-2G update of the rows above (A = [S | T] rows 0..g0-1 of the
-    // group's columns), 16 x 4 blocks in the layout of the FP64 matrix instruction, issued
-    // now so that they land during the end of the group (not held through its blocks)
-    double af[MB / 16][4];   // raw entries; masked and scaled where they are used
-#pragma unroll
-    for (int rb = 0; rb < MB / 16; ++rb)
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const int row = 16 * rb + lane % 16;
-        const int kk = 4 * st + lane / 16;        // 0..15: S columns 0..7, T columns 8..15
-        const int col = g0 + (kk & (G - 1));
-        const bool ok = row < g0 && col <= g1;
-        const int64_t ro = ok ? r0 + row : 0, co = ok ? r0 + col : 0;
-        af[rb][st] = kk < G ? S[ro + co * lds] : T[ro + co * ldt];
+      int q = g1;
+      while (q >= g0) {
+        // a block: rows q0 .. q (q0 = q for a 1x1 block), local rows lq0 .. lq
+        const bool two = second(q);
+        const int q0 = two ? q - 1 : q;
+        const int lq0 = q0 - g0, lq = q - g0;
+        const Cx y0 = cx(yr[lq0], yi[lq0]), y1 = cx(yr[lq], yi[lq]);
+        const double cn = two ? cnv[lq0] + cnv[lq] : cnv[lq];
+        const bool work = owner && !(tip && q0 > pc);
+        const bool at_tip = tip && q0 == pc;   // the column's own block (singular for its eigenvalue)
+        const bool act = work && !at_tip;
+        int qs = 0;
+        Cx z0, z1;
+        if (!two) {
+          // ---- 1x1 block ----
+          z0 = solve1(a, b, be, Pn[0][lq][lq], Pn[1][lq][lq], y1, qs, flags, act);
+          z1 = cx(0.0, 0.0);
+          if (at_tip) {
+            // the tip of a real eigenvalue (zero in correction mode)
+            z0 = cx(P.rhs ? 0.0 : 1.0, 0.0);
+            qs = 0;
+          }
+        } else {
+          // ---- 2x2 block ----
+          const double s00 = Pn[0][lq0][lq0], s10 = Pn[0][lq0][lq], s01 = Pn[0][lq][lq0], s11 = Pn[0][lq][lq];
+          const double t00 = Pn[1][lq0][lq0], t01 = Pn[1][lq][lq0], t11 = Pn[1][lq][lq];
+          z0 = y0;
+          z1 = y1;
+          if (P.cform) {
+            // real form of a complex pencil: a complex column in its subspace, a real one as usual
+            Cx c0 = z0, c1 = z1, g0v = z0, g1v = z1;
+            int qc = 0, qg = 0;
+            solve2c(a, b, be, s00, s10, t00, csg, c0, c1, qc, flags, act && csg != 0.0);
+            solve2(a, b, be, s00, s01, s10, s11, t00, t01, t11, g0v, g1v, qg, flags, act && csg == 0.0);
+            z0 = csg != 0.0 ? c0 : g0v;
+            z1 = csg != 0.0 ? c1 : g1v;
+            qs = csg != 0.0 ? qc : qg;
+          } else {
+            solve2(a, b, be, s00, s01, s10, s11, t00, t01, t11, z0, z1, qs, flags, act);
+          }
+          if (tip) {
+            // the column's own block: the tip
+            Cx tz0 = cx(0.0, 0.0), tz1 = cx(0.0, 0.0);
+            int tq = 0;
+            if (P.rhs) {
+              // correction mode: the correction is zero at the tip (z0 = z1 = 0)
+            } else if (csg != 0.0) {
+              // real form of a complex pencil: the tip in the column's subspace, (sg i, 1), exactly
+              tz0 = cx(0.0, csg);
+              tz1 = cx(1.0, 0.0);
+            } else {
+              // second row of the singular block beta S_b - alpha T_b gives z_p for z_{p+1} = 1
+              double m21 = be * s10;
+              const Cx nn = cx(-(be * s11 - a * t11), b * t11);
+              const double smin = local_smin(be, aabs, fmax(fabs(s10), fabs(s11)), fabs(t11));
+              const bool pert = fabs(m21) < smin;
+              m21 = pert ? smin : m21;
+              flags |= (pert && work && at_tip) ? kInfoPerturbed : 0;
+              tq = with_margin(protect_division_fast(cn1(nn), fabs(m21), work && at_tip));
+              const Cx ns = cscl(nn, tq);
+              const double rm = recip(m21);
+              tz0 = cx(ns.r * rm, ns.i * rm);
+              tz1 = cx(ldexp(1.0, -tq), 0.0);
+            }
+            if (at_tip) {
+              z0 = tz0;
+              z1 = tz1;
+              qs = tq;
+            }
+          }
+        }
+        if (q0 > 0) {
+          // ProtectUpdate for y[0:q0] -= (beta S - alpha T)[0:q0, q0..q] z (inside the group
+          // now, above it at the end of the group; the column norms bound both)
+          const int qu = with_margin(protect_update_fast(cn, fmax(cn1(z0), cn1(z1)), ldexp(ybound, -qs), work));
+          z0 = cscl(z0, qu);
+          z1 = cscl(z1, qu);
+          qs += qu;
+        }
+        z0 = work ? z0 : cx(0.0, 0.0);
+        z1 = work ? z1 : cx(0.0, 0.0);
+        if (work) settle(q0, q, qs, z0, z1, cn);
+        // y += S (-beta z) + T (alpha z) with the block's columns
+        auto apply = [&](int c, Cx z) {
+          const d8 cs = *reinterpret_cast<const d8*>(&Pn[0][c][0]);
+          const d8 ct = *reinterpret_cast<const d8*>(&Pn[1][c][0]);
+          const double ur = -be * z.r, ui = -be * z.i;
+          const double vr = a * z.r - b * z.i, vi = a * z.i + b * z.r;
+  #pragma unroll
+          for (int k = 0; k < G; ++k) {
+            yr[k] = fma(ct[k], vr, fma(cs[k], ur, yr[k]));
+            yi[k] = fma(ct[k], vi, fma(cs[k], ui, yi[k]));
+          }
+        };
+        apply(lq0, z0);
+        if (two) apply(lq, z1);
+        q = q0 - 1;
       }
+
+    } else {
+      // the helper waves: the previous group's update of the rows above this group
+      rank_far(std::integral_constant<int, NRC_BIG>{}, drh, dg0, dg1, NCW, NHW > 0 ? NHW : 1);
+    }
+    if (NHW > 0) __syncthreads();   // the rows above are current before the end of the group rescales any
+    // A fragments of the next group's rows (they land during the end of the group)
+    double au[2][4];
+    {
+      const int rbn = (gn0 > 0 ? gn0 : 0) / 16;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int st = 0; st < 4; ++st) au[i][st] = afrag(rbn + i < NR0 ? rbn + i : NR0 - 1, st, g0, g1);
+    }
 
     // ---- end of group: bound the rank-2G update of the rows above, settle scales ----
     if (owner && g0 > 0) {
@@ -540,6 +673,9 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
         e += qg;
         yb_above = ldexp(yb_above, -qg);
         zng = ldexp(zng, -qg);
+        tnx = ldexp(tnx, -qg);
+        tny = ldexp(tny, -qg);
+        tns = ldexp(tns, -qg);
       }
       ybound = fma(cng, zng, yb_above);
     }
@@ -556,84 +692,43 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
     panel_publish();   // the next group's diagonal block (its loads had the whole group)
 
     // ---- rank-2G update of the rows above the group on the FP64 matrix cores ----
-    // Y[0:g0, :] <- 2^-fcol Y[0:g0, :] + [S | T][0:g0, group] * [-beta z ; alpha z]
-    // B operand entry (k, n): row g0 + (k mod G) of column n, -beta z (k < G) or alpha z
-    // (k >= G), own parts (a pair's real part in its first column, imaginary in its
-    // second); zero for rows past the group and for columns not solved
-    auto bop = [&](int k, int n) -> double {
-      const int i = g0 + (k & (G - 1));
-      const int ir = i <= g1 ? i : g1;   // (rows past the group: read in range, dropped)
-      const int kd = colKind[n];
-      const int np = kd == 1 ? n + 1 : (kd == 2 ? n - 1 : n);
-      const double own = Y[ir * LDY + n], oth = Y[ir * LDY + np];
-      const double zr = kd == 2 ? oth : own, zi = kd == 0 ? 0.0 : (kd == 1 ? oth : own);
-      const double an = colA[n], bn = colB[n];
-      const double v = k < G ? -colBe[n] * own : (kd == 2 ? (bn * zr + an * zi) : (an * zr - bn * zi));
-      return (i <= g1 && colOn[n]) ? v : 0.0;
-    };
-    if (g0 > 0) {
-      const int nrb = (g0 + 15) / 16, ncb = (hw + 15) / 16;
-      constexpr int nw = NTOT / 64;
-      // A wave owns whole column blocks and takes their row blocks in chunks of NRC, the
-      // chunks past the rows above the group skipped (a uniform test); a chunk's row
-      // blocks are independent chains, issued interleaved.  Every operand index is a
-      // constant, so the operands stay in registers: rows at or below the group and
-      // columns past the tile are computed and dropped, and operand columns past the group
-      // meet zero rows of B.
-      constexpr int NR0 = MB / 16;
-      constexpr int NRC = NR0 < 4 ? NR0 : 4;
-      for (int cb = wave; cb < ncb; cb += nw) {
-        const int col = 16 * cb + lane % 16;
-        const int colr = col < NCY ? col : NCY - 1;   // (columns past those held: dropped)
-        const int fs = fcol[colr];
-        const bool cok = col < hw;
-        double bf[4];
-#pragma unroll
-        for (int st = 0; st < 4; ++st) bf[st] = bop(4 * st + lane / 16, colr);
-#pragma unroll
-        for (int ch = 0; ch < NR0 / NRC; ++ch) {
-          if (NRC * ch < nrb) {
-            d4 acc[NRC];
-#pragma unroll
-            for (int i = 0; i < NRC; ++i)
-#pragma unroll
-              for (int v = 0; v < 4; ++v)
-                acc[i][v] = ldexp(Y[(16 * (NRC * ch + i) + lane / 16 + 4 * v) * LDY + colr], -fs);
-#pragma unroll
-            for (int st = 0; st < 4; ++st)
-#pragma unroll
-              for (int i = 0; i < NRC; ++i)
-                acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(psc * af[NRC * ch + i][st], bf[st], acc[i], 0, 0, 0);
-#pragma unroll
-            for (int i = 0; i < NRC; ++i)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) {
-                const int row = 16 * (NRC * ch + i) + lane / 16 + 4 * v;
-                if (row < g0 && cok) Y[row * LDY + col] = acc[i][v];
-              }
-          }
-        }
-      }
+    if (NHW > 0) {
+      // the next group's rows now; the rows above it during that group's blocks
+      rank_near(au, gn0 > 0 ? gn0 : 0, g0, g0, g1);
+      dg0 = g0;
+      dg1 = g1;
+      drh = gn0 > 0 ? gn0 : 0;
+    } else {
+      rank_far(std::integral_constant<int, NRC_BIG>{}, g0, g0, g1, 0, 1);
     }
     __syncthreads();
     g1 = gn1;
     g0 = gn0;
   }
 
-  // the second column of a pair takes the exponent its owner carried
+  // the second column of a pair takes the exponent its owner carried, and each column its
+  // largest |entry|: the maxima its owner kept, or for a column that is not selected, from Y
+  // (no wave runs that loop when every column is selected)
   if (colthr && pair) ecol[lc + 1] = e;
+  if (colthr) {
+    if (selected) {
+      if (kind != 2) {
+        cmax[lc] = tnx;
+        if (pair) cmax[lc + 1] = tny;
+      }
+    } else {
+      double v = 0.0;
+      if (inrange)
+        for (int i = 0; i < hr; ++i) v = fmax(v, fabs(Y[i * LDY + lc]));
+      cmax[lc] = v;
+    }
+  }
   __syncthreads();
   if (kind == 2) e = ecol[lc];
 
   // ---- segment norms and exponent ----
-  double nx = 0.0, ns = 0.0;   // max |x_i|; max |x_i| + |y_i| of a pair (its first column's thread)
-  if (inrange)
-    for (int i = 0; i < hr; ++i) {
-      const double ax = fabs(Y[i * LDY + lc]);
-      nx = fmax(nx, ax);
-      if (pair) ns = fmax(ns, ax + fabs(Y[i * LDY + lc + 1]));
-    }
-  if (colthr) cmax[lc] = nx;
+  const double nx = colthr ? cmax[lc] : 0.0;   // max |x_i| of this column
+  const double ns = owner ? tns : 0.0;         // max |x_i| + |y_i| of a pair (its first column)
   if (own) {
     P.exps[(int64_t)r * m + c] = e;
     P.norms[(int64_t)r * m + c] = nx;
