@@ -63,12 +63,21 @@ def mixed_candidates(m):
 
 
 def time_single(m, mb, band, schedule, Sd, Td, Z, sc, info, reps, precision=0, split=0):
+    """Best of `reps` product calls (rtgevc), HIP events around each call on the stream it
+    runs on (per-launch events would perturb the overlap of the two streams)."""
+    import torch
     from paper_2003_04776_amd import rtgevc as rt
     solver = rt.Solver(m, mb=mb, band=band, schedule=schedule, precision=precision, split=split if split else -1)
-    solver.run_timed(Sd, Td, Z, sc, info)          # warm-up (first launch of each kernel)
+    solver.run(Sd, Td, Z=Z, scales=sc, info=info)   # warm-up (first launch of each kernel)
+    torch.cuda.synchronize()
     best = math.inf
     for _ in range(reps):
-        best = min(best, solver.run_timed(Sd, Td, Z, sc, info)["total_ms"])
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        solver.run(Sd, Td, Z=Z, scales=sc, info=info)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
     return best
 
 

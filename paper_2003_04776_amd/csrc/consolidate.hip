@@ -62,31 +62,38 @@ __device__ __forceinline__ void consolidate_body(const PencilDesc& P) {
       nm = fmax(nm, ldexp(P.segn[(int64_t)k * m + c], P.exps[(int64_t)k * m + c] - E));
     nm = block_max(nm, red);
   }
-  // rescale every segment to the common exponent (and divide by the norm); a thread's
-  // kUnroll rows of a step are loaded before any is stored, so each keeps that many loads
-  // of the column in flight
+  // rescale every segment to the common exponent (and divide by the norm): a step covers
+  // kConsThreads / mb whole segments, thread t row t mod mb of segment t / mb (so its
+  // exponent is one load, not one per row), and a thread's kUnroll steps are loaded before
+  // any is stored, keeping that many loads of the column in flight
   const bool div = P.normalize && nm > 0.0;
   constexpr int kUnroll = 4;
-  for (int64_t i0 = threadIdx.x; i0 < rend; i0 += kUnroll * kConsThreads) {
+  const int mb = P.mb;
+  const int segs = kConsThreads / mb;   // segments per step (mb divides kConsThreads)
+  const int tr = threadIdx.x % mb, ts = threadIdx.x / mb;
+  for (int k0 = 0; k0 <= jt; k0 += kUnroll * segs) {
     double x[kUnroll], y[kUnroll];
     int d[kUnroll];
+    int64_t row[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int64_t i = i0 + u * kConsThreads;
-      const int64_t ir = i < rend ? i : rend - 1;   // (rows past the end: read, not stored)
+      const int k = k0 + u * segs + ts;
+      const int kr = k <= jt ? k : jt;
+      const int64_t i = P.edges[kr] + tr;
+      row[u] = (k <= jt && i < P.edges[kr + 1]) ? i : -1;   // (-1: no row; a valid one is read)
+      const int64_t ir = row[u] >= 0 ? i : P.edges[kr];
       x[u] = zx[ir];
       y[u] = cplx ? zy[ir] : 0.0;
-      d[u] = P.exps[(int64_t)P.tileof[ir] * m + c] - E;
+      d[u] = P.exps[(int64_t)kr * m + c] - E;
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int64_t i = i0 + u * kConsThreads;
-      if (i < rend) {
+      if (row[u] >= 0) {
         const double xs = ldexp(x[u], d[u]);
-        zx[i] = div ? xs / nm : xs;
+        zx[row[u]] = div ? xs / nm : xs;
         if (cplx) {
           const double ys = ldexp(y[u], d[u]);
-          zy[i] = div ? ys / nm : ys;
+          zy[row[u]] = div ? ys / nm : ys;
         }
       }
     }

@@ -214,9 +214,9 @@ def test_noalloc_argument_errors_and_scratch_limit():
     assert call(ldz=3) == -8
     assert call(opts=rt.make_opts(mb=48)) == -11
     assert call(m=0, S=None, T=None, Z=None, lds=1, ldt=1, ldz=1) == 0
-    # the largest FP64 order with default options that fits, and the first that does not
-    assert rt.workspace_size(4096) <= rt.NOALLOC_SCRATCH_BYTES < rt.workspace_size(8192)
-    big = 8192
+    # default FP64 options fit at m = 4096 and not at m = 16384 (where the tuned tile is 128)
+    assert rt.workspace_size(4096) <= rt.NOALLOC_SCRATCH_BYTES < rt.workspace_size(16384)
+    big = 16384
     assert call(m=big, lds=big, ldt=big, ldz=big) == rt.ERR_SCRATCH
     assert "scratch" in rt.strerror(rt.ERR_SCRATCH)
     mixed = rt.make_opts(precision=1)
