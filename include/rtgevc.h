@@ -278,17 +278,25 @@ int rtgevc_timed(int64_t m, const double *S, int64_t lds, const double *T, int64
  * pencil); info is a DEVICE int32[count] (or NULL) receiving each pencil's bits.  Every
  * pencil's arguments obey the rules of rtgevc().  work: device workspace, 256-byte
  * aligned, of at least rtgevc_batched_workspace_size(count, m, opts) bytes.  opts as
- * for rtgevc(); its mb and band, when non-zero, apply to every pencil (band 0: 2); its
- * schedule and precision are not used (the batch runs FP64 tile updates in lock-step).
+ * for rtgevc(); its mb and band, when non-zero, apply to every pencil (band 0: 3); split
+ * (> 0) issues the update of the rows above the next band in launches of about that many
+ * tiles summed over a group's pencils (0 or -1: one launch per step); its schedule and
+ * precision are not used (the batch runs FP64 tile updates in lock-step).
  *
  * Pencils are grouped by tile size (automatic per order unless opts->mb is set); each
- * group runs in lock-step over bands of R tile rows (step t solves the rows of band
- * B_p - 1 - t of every pencil p of the group, bottom-up with the updates inside the band,
- * then applies the band to the rows above it), one launch per part of a step and kernel
- * for the whole group.  The eigenvectors equal those of rtgevc() with the same tile size
- * and band.  The call enqueues kernels only: no allocation, no copy, no synchronisation,
- * so it can be captured in a HIP graph and replayed (the host arrays are read during
- * the call; the device pointers they hold must stay valid for every replay).
+ * group runs in lock-step over bands of R tile rows: step t solves the rows of band
+ * b = B_p - 1 - t of every pencil p of the group, bottom-up with the updates inside the
+ * band, applies the band to the next band's rows, and then, on a second stream of the
+ * library (created on the first call on a device, at default priority, kept until the
+ * process ends), to every row above those while step t + 1 proceeds on the caller's
+ * stream (the look-ahead of rtgevc()'s band schedule, one launch per part of a step and
+ * kernel for the whole group; events order the two streams, and the second stream is
+ * joined back before the call's last kernel).  The eigenvectors equal those of rtgevc()
+ * with the same tile size and band.  The call enqueues kernels and event records and
+ * waits only: no allocation, no copy, no synchronisation, so it can be captured in a HIP
+ * graph and replayed (the host arrays are read during the call; the device pointers they
+ * hold must stay valid for every replay); make the first call on a device outside
+ * capture.  Calls from several host threads are serialised while they enqueue.
  * Returns 0 when enqueued; -i for argument i (1-based; per-pencil violations report
  * the argument that holds them); -1000 - hipError on a launch failure. */
 size_t rtgevc_batched_workspace_size(int32_t count, const int64_t *m, const rtgevc_opts *opts);

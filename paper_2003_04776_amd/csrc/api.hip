@@ -29,7 +29,7 @@ bool launch_update(const PencilDesc& P, int k_lo, int k_hi, int j_lo, int s_lo, 
 void launch_consolidate(const PencilDesc& P, hipStream_t s);
 void launch_preprocess_batched(const PencilDesc* D, int n, int64_t max_m, int max_tiles, hipStream_t s);
 void launch_solve_batched(const PencilDesc* D, int n, int mb, int max_tiles, int R, int t, int io, hipStream_t s);
-void launch_update_batched(const PencilDesc* D, int n, int mb, int max_tiles, int R, int t, int io, int band,
+void launch_update_batched(const PencilDesc* D, int n, int mb, int max_tiles, int R, int t, int part, int a, int c,
                            int kmax, hipStream_t s);
 void launch_consolidate_batched(const PencilDesc* D, int n, int64_t max_m, hipStream_t s);
 void launch_eigvals_out(const PencilDesc& P, double* are, double* aim, double* bet, hipStream_t s);
@@ -261,9 +261,18 @@ __global__ void batch_setup_kernel(BatchSetup su, PencilDesc* table, char* work)
 }
 
 constexpr int kBatchMbs[3] = {32, 64, 128};
-constexpr int kBatchBand = 2;   // source rows per lock-step update of a batch (opts->band overrides)
+constexpr int kBatchBand = 3;   // tile rows per band of a batch's lock-step (opts->band overrides)
+
+// tiles per launch of a batch step's update of the rows above the next band, summed over
+// the group's pencils (opts->split overrides; 0 = one launch per step)
+constexpr int kBatchSplit = 0;
 
 int batch_band(const rtgevc_opts* o) { return (o && o->band) ? o->band : kBatchBand; }
+
+int batch_split(const rtgevc_opts* o) {
+  const int v = o ? o->split : 0;
+  return v > 0 ? v : (v < 0 ? 0 : kBatchSplit);
+}
 
 int batch_mb(int64_t m, const rtgevc_opts* o) {
   if (o && o->mb) return o->mb;
@@ -926,7 +935,10 @@ int rtgevc_batched(int32_t count, const int64_t* m, const double* const* S, cons
   PencilDesc* table = reinterpret_cast<PencilDesc*>(base);
   const int normalize = opts ? opts->normalize : 1;
   const int R = batch_band(opts);
-  hipError_t err = hipSuccess;
+  const int split = batch_split(opts);
+  std::lock_guard<std::mutex> lock(g_aux_mu);
+  Aux* ax = nullptr;
+  hipError_t err = get_aux(&ax);
   int first = 0;
   for (int g = 0; g < 3 && err == hipSuccess; ++g) {
     const int mb = kBatchMbs[g];
@@ -968,22 +980,53 @@ int rtgevc_batched(int32_t count, const int64_t* m, const double* const* S, cons
     }
     const PencilDesc* D = table + first;
     launch_preprocess_batched(D, n, max_m, max_tiles, s);
-    // the device's tile count of a pencil is at most tile_bound, so its band of step t
-    // starts at most at R (ceil(tile_bound / R) - 1 - t)
-    std::vector<int> bands;
-    for (const BatchArg& a : args) bands.push_back((tile_bound(a.m, mb) + R - 1) / R);
+    // Host bounds of the lock-step: the device's tile count of a pencil is at most
+    // tile_bound, so its band of step t starts at most at R (ceil(tile_bound / R) - 1 - t).
     const int steps = (max_tiles + R - 1) / R;
+    std::vector<int> above(steps, 0), cr(steps, 0);
     for (int t = 0; t < steps; ++t) {
-      for (int io = 0; io < R; ++io) {
-        launch_solve_batched(D, n, mb, max_tiles, R, t, io, s);
-        if (io + 1 < R) launch_update_batched(D, n, mb, max_tiles, R, t, io, 0, R - 1, s);
+      int64_t cols = 0;   // tile columns of the step's bands, summed over pencils with rows above
+      for (const BatchArg& a : args) {
+        const int tb = tile_bound(a.m, mb), b = (tb + R - 1) / R - 1 - t;
+        const int nlo = R * b - R;
+        if (nlo <= 0) continue;
+        above[t] = std::max(above[t], nlo);
+        cols += tb - R * b;
       }
-      int kmax = 0;
-      for (int nb : bands) kmax = std::max(kmax, R * (nb - 1 - t));
-      launch_update_batched(D, n, mb, max_tiles, R, t, 0, 1, kmax, s);
+      if (split > 0 && cols > 0) cr[t] = (int)std::max<int64_t>(1, (split + cols - 1) / cols);
     }
+    struct Ops {
+      const PencilDesc* D;
+      int n, mb, max_tiles, R;
+      hipStream_t st[2];
+      hipEvent_t ev[4];
+      hipError_t& err;
+      bool ok(hipError_t e) {
+        if (err == hipSuccess) err = e;
+        return err == hipSuccess;
+      }
+      bool solve(int t, int io, int s) {
+        launch_solve_batched(D, n, mb, max_tiles, R, t, io, st[s]);
+        return true;
+      }
+      bool inband(int t, int io, int s) {
+        launch_update_batched(D, n, mb, max_tiles, R, t, 0, io, 0, R - 1, st[s]);
+        return true;
+      }
+      bool next(int t, int s) {
+        launch_update_batched(D, n, mb, max_tiles, R, t, 1, 0, 0, R, st[s]);
+        return true;
+      }
+      bool above(int t, int off, int cnt, int s) {
+        launch_update_batched(D, n, mb, max_tiles, R, t, 2, off, cnt, cnt, st[s]);
+        return true;
+      }
+      bool record(int e, int s) { return ok(hipEventRecord(ev[e], st[s])); }
+      bool wait(int s, int e) { return ok(hipStreamWaitEvent(st[s], ev[e], 0)); }
+    } ops{D, n, mb, max_tiles, R, {s, ax->side}, {ax->evC, ax->evJ, ax->evU[0], ax->evU[1]}, err};
+    batch_band_schedule(steps, R, cr.data(), above.data(), ops);
     launch_consolidate_batched(D, n, max_m, s);
-    err = hipGetLastError();
+    if (err == hipSuccess) err = hipGetLastError();
     first += n;
   }
   return hip_code(err);
@@ -1008,7 +1051,7 @@ int rtgevc_resolve_opts(int64_t m, int32_t batched, const rtgevc_opts* opts, rtg
   const int sweeps = batched ? 0 : resolve_sweeps(opts);
   out->max_refine = sweeps > 0 ? sweeps : -1;
   out->refine_bits = opts ? opts->refine_bits : 0;
-  const int split = batched ? 0 : resolve_split(m, opts);
+  const int split = batched ? batch_split(opts) : resolve_split(m, opts);
   out->split = split > 0 ? split : -1;
   return 0;
 }

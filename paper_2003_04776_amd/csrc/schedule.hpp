@@ -73,4 +73,49 @@ bool band_schedule(int rows, int R, int split, Ops& ops) {
   return ok;
 }
 
+// The same schedule in lock-step over a batch of pencils: every launch is one part of step
+// t for all pencils of a group, pencil p being in its band b_p = B_p - 1 - t (B_p bands of
+// R tile rows from the top; a step beyond a pencil's bands is a no-op for it).  In pencil
+// p's rows, r_lo = R b_p and r_hi = min(r_lo + R - 1, M_p - 1):
+//   solve(t, io, s)            solves row r_hi - io (when it is >= r_lo);
+//   inband(t, io, s)           source row r_hi - io applied to rows [r_lo, r_hi - io);
+//   next(t, s)                 U1: the band applied to the next band's rows [r_lo - R, r_lo);
+//   above(t, off, cnt, s)      part of U2: the band applied to rows [max(0, hi - cnt), hi),
+//                              hi = r_lo - R - off (rows counted from the bottom).
+// Each pencil sees exactly the launches and dependencies band_schedule gives it (with U2 of
+// step t in launches of cr[t] rows, or one launch for cr[t] <= 0), so the look-ahead is the
+// same: step t + 1's chain overlaps U2 of step t.  steps is the largest B_p; above[t]
+// (t < steps) the largest U2 row count r_lo - R of step t over the group (0: no U2 launch).
+template <class Ops>
+bool batch_band_schedule(int steps, int R, const int* cr, const int* above, Ops& ops) {
+  bool ok = true;
+  auto chk = [&](bool b) { ok = ok && b; };
+  chk(ops.record(kEvC, kStreamA));
+  chk(ops.wait(kStreamB, kEvC));
+  chk(ops.record(kEvU0, kStreamB));
+  chk(ops.record(kEvU1, kStreamB));
+  for (int t = 0; t < steps && ok; ++t) {
+    for (int io = 0; io < R && ok; ++io) {
+      chk(ops.solve(t, io, kStreamA));
+      if (io + 1 < R) chk(ops.inband(t, io, kStreamA));
+    }
+    if (t + 1 < steps && ok) {
+      // U2 of step t - 1 (evU[(t - 1) & 1] was last recorded after it)
+      chk(ops.wait(kStreamA, ((t + 1) & 1) ? kEvU1 : kEvU0));
+      chk(ops.next(t, kStreamA));
+      chk(ops.record(kEvC, kStreamA));
+      const int rows = above[t];
+      if (rows > 0 && ok) {
+        chk(ops.wait(kStreamB, kEvC));
+        const int c = cr[t] > 0 ? cr[t] : rows;
+        for (int off = 0; off < rows && ok; off += c) chk(ops.above(t, off, c, kStreamB));
+        chk(ops.record((t & 1) ? kEvU1 : kEvU0, kStreamB));
+      }
+    }
+  }
+  chk(ops.record(kEvJ, kStreamB));
+  chk(ops.wait(kStreamA, kEvJ));
+  return ok;
+}
+
 }  // namespace rgev

@@ -6,9 +6,9 @@
 
 namespace rgev {
 
-// two workgroups per CU: 2 R C / 4 waves per SIMD
+// UpdShape<MB>::W waves per SIMD
 template <int MB>
-__global__ __launch_bounds__(64 * UpdShape<MB>::R * UpdShape<MB>::C, UpdShape<MB>::R * UpdShape<MB>::C / 2)
+__global__ __launch_bounds__(64 * UpdShape<MB>::R * UpdShape<MB>::C, UpdShape<MB>::W)
 void update_kernel(PencilDesc P, UpdRange U) {
   const int M = P.ctrl->M;
   if (U.j_lo >= M || U.k_hi <= U.k_lo || U.s_lo >= M) return;
@@ -24,36 +24,42 @@ void update_kernel(PencilDesc P, UpdRange U) {
   if (k >= U.k_hi || j >= M) return;
   if (P.rhs && !P.tflag[j]) return;   // correction mode: no column of tile j is refined
   __shared__ UpdSmem<MB, UpdShape<MB>::R> sm;
-  update_tile<MB, UpdShape<MB>::R, UpdShape<MB>::C>(P, U, k, j, sm);
+  update_tile<MB, UpdShape<MB>::R, UpdShape<MB>::C, UpdShape<MB>::S>(P, U, k, j, sm);
 }
 
 // one update of a batch's lock-step t for pencil p = blockIdx.y, in its band B_p - 1 - t
-// (tile rows [r_lo, r_hi]): band = 0: the in-band update after the solve of row
-// r = r_hi - io, targets k in [r_lo, r), j >= r, source r; band = 1: the band applied to
-// every row above it, targets k < r_lo, j >= r_lo, sources r_lo .. r_hi (the ranges of the
-// single-pencil band schedule).  blockIdx.x enumerates (k - k_lo, j - j_lo) with J columns.
+// (tile rows [r_lo, r_hi]); the ranges are those of the single-pencil band schedule:
+//   part 0: the in-band update after the solve of row r = r_hi - a: targets k in [r_lo, r),
+//           j >= r, source r;
+//   part 1: the band applied to the next band's rows, targets [r_lo - R, r_lo), j >= r_lo;
+//   part 2: the band applied to rows [max(0, hi - c), hi) above those, hi = r_lo - R - a.
+// blockIdx.x enumerates (k - k_lo, j - j_lo) with J columns.
 template <int MB>
-__global__ __launch_bounds__(64 * UpdShape<MB>::R * UpdShape<MB>::C, UpdShape<MB>::R * UpdShape<MB>::C / 2)
-void update_batched_kernel(const PencilDesc* __restrict__ D, int R, int t, int io, int band, int J) {
+__global__ __launch_bounds__(64 * BatchUpdShape<MB>::R * BatchUpdShape<MB>::C, BatchUpdShape<MB>::W)
+void update_batched_kernel(const PencilDesc* __restrict__ D, int R, int t, int part, int a, int c, int J) {
   const PencilDesc P = D[blockIdx.y];
   const int M = P.ctrl->M;
   const int b = (M + R - 1) / R - 1 - t;
   if (b < 0) return;
   const int r_lo = R * b, r_hi = min(r_lo + R - 1, M - 1);
   UpdRange U;
-  if (band) {
-    if (r_lo == 0) return;
-    U = UpdRange{0, r_lo, r_lo, r_lo, r_hi};
-  } else {
-    const int r = r_hi - io;
+  if (part == 0) {
+    const int r = r_hi - a;
     if (r <= r_lo) return;
     U = UpdRange{r_lo, r, r, r, r};
+  } else if (part == 1) {
+    if (r_lo == 0) return;
+    U = UpdRange{max(r_lo - R, 0), r_lo, r_lo, r_lo, r_hi};
+  } else {
+    const int hi = r_lo - R - a;
+    if (hi <= 0) return;
+    U = UpdRange{max(hi - c, 0), hi, r_lo, r_lo, r_hi};
   }
   const int kk = (int)blockIdx.x / J, jj = (int)blockIdx.x % J;
   const int k = U.k_lo + kk, j = U.j_lo + jj;
   if (k >= U.k_hi || j >= M) return;
-  __shared__ UpdSmem<MB, UpdShape<MB>::R> sm;
-  update_tile<MB, UpdShape<MB>::R, UpdShape<MB>::C>(P, U, k, j, sm);
+  __shared__ UpdSmem<MB, BatchUpdShape<MB>::R> sm;
+  update_tile<MB, BatchUpdShape<MB>::R, BatchUpdShape<MB>::C, BatchUpdShape<MB>::S>(P, U, k, j, sm);
 }
 
 template <int MB>
@@ -83,19 +89,19 @@ bool launch_update(const PencilDesc& P, int k_lo, int k_hi, int j_lo, int s_lo, 
   return true;
 }
 
-// Batch lock-step t, band R (see update_batched_kernel): kmax bounds the target rows (R - 1
-// in a band; for the band update, the largest first row of the step's bands), and the
-// columns j - j_lo < R (t + 1).
-void launch_update_batched(const PencilDesc* D, int n, int mb, int max_tiles, int R, int t, int io, int band,
+// Batch lock-step t, band R (see update_batched_kernel): kmax bounds the target rows of the
+// part over the group's pencils (R - 1 in a band, R for the next band, c for a part of the
+// rows above), and the columns j - j_lo < R (t + 1).
+void launch_update_batched(const PencilDesc* D, int n, int mb, int max_tiles, int R, int t, int part, int a, int c,
                            int kmax, hipStream_t s) {
   const int64_t J = (R * (t + 1) < max_tiles) ? R * (t + 1) : max_tiles;
   if (kmax <= 0 || J <= 0 || n <= 0) return;
   const dim3 grid((unsigned)(kmax * J), (unsigned)n);
   const int Ji = (int)J;
   switch (mb) {
-    case 32: update_batched_kernel<32><<<grid, 64 * UpdShape<32>::R * UpdShape<32>::C, 0, s>>>(D, R, t, io, band, Ji); break;
-    case 64: update_batched_kernel<64><<<grid, 64 * UpdShape<64>::R * UpdShape<64>::C, 0, s>>>(D, R, t, io, band, Ji); break;
-    default: update_batched_kernel<128><<<grid, 64 * UpdShape<128>::R * UpdShape<128>::C, 0, s>>>(D, R, t, io, band, Ji); break;
+    case 32: update_batched_kernel<32><<<grid, 64 * BatchUpdShape<32>::R * BatchUpdShape<32>::C, 0, s>>>(D, R, t, part, a, c, Ji); break;
+    case 64: update_batched_kernel<64><<<grid, 64 * BatchUpdShape<64>::R * BatchUpdShape<64>::C, 0, s>>>(D, R, t, part, a, c, Ji); break;
+    default: update_batched_kernel<128><<<grid, 64 * BatchUpdShape<128>::R * BatchUpdShape<128>::C, 0, s>>>(D, R, t, part, a, c, Ji); break;
   }
 }
 

@@ -16,7 +16,7 @@
 //
 // One workgroup per target tile (k, j); its waves split the tile into a WGR x WGC grid
 // (2 x 2 for MB = 128: 64 x 64 per wave, 16 independent accumulators, two waves per SIMD
-// when two workgroups share a CU).  Each wave streams its own matrix-core fragments straight from global memory into
+// when two workgroups share a CU; batches: one wave for MB = 64, eight workgroups per CU).  Each wave streams its own matrix-core fragments straight from global memory into
 // registers, with no LDS staging and no barrier in the K loop: an A fragment (16 rows x 4
 // K values of column-major S or T) is four fully used 128-byte lines, a W fragment one
 // 512-byte run of the packed W tile, and the waves sharing rows or columns of the tile
@@ -41,11 +41,16 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kChunk = 16;   // source heights are padded to a multiple of kChunk rows
 
-// wave grid R x C per tile size and S, the register slots of the fragment pipeline
-template <int MB> struct UpdShape;
-template <> struct UpdShape<128> { static constexpr int R = 2, C = 2, S = 3; };
-template <> struct UpdShape<64> { static constexpr int R = 2, C = 2, S = 3; };
-template <> struct UpdShape<32> { static constexpr int R = 2, C = 2, S = 3; };
+// wave grid R x C per tile size, S the register slots of the fragment pipeline and W the
+// waves per SIMD the kernel is compiled for (W = 2: 256 registers per lane).
+//  - UpdShape (one pencil): four waves per tile, so a launch of few tiles (the update of the
+//    next band, on the critical path of the band schedule) ends soon;
+//  - BatchUpdShape (lock-step batches, launches of thousands of tiles, bound by throughput):
+//    a wave holds at most a 64 x 64 block (16 accumulators), so tiles of 64 and 32 are one
+//    wave each and a wave's loads per matrix instruction are as for the tile of 128.
+template <int MB> struct UpdShape { static constexpr int R = 2, C = 2, S = 3, W = 2; };
+template <int MB> struct BatchUpdShape { static constexpr int R = 1, C = 1, S = 3, W = 2; };
+template <> struct BatchUpdShape<128> { static constexpr int R = 2, C = 2, S = 3, W = 2; };
 
 struct UpdRange {
   int k_lo, k_hi;   // target tile rows [k_lo, k_hi)
@@ -114,7 +119,7 @@ struct UpdSmem {
 
 // Update of target tile (k, j) of one pencil by the band of sources in U (a workgroup of
 // 64 WGR WGC threads, the waves on a WGR x WGC grid over the tile).
-template <int MB, int WGR, int WGC>
+template <int MB, int WGR, int WGC, int NS = 3>
 __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange& U, int k, int j,
                                             UpdSmem<MB, WGR>& sm) {
   constexpr int WR = MB / WGR;          // rows per wave
@@ -244,7 +249,6 @@ __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange&
 
   // NS register slots rotate through an unrolled loop: the loads of step t + NS - 1 are in
   // flight while the matrix cores run step t; the step count is rounded up to NS
-  constexpr int NS = UpdShape<MB>::S;
   double af[NS][RB], bf[NS][CB];
   int sgl[NS][CB] = {};
   int src[NS];

@@ -389,11 +389,11 @@ class BatchSolver:
     made once); ``run`` enqueues rtgevc_batched on the current stream and can be captured
     in a CUDA/HIP graph (it only launches kernels)."""
 
-    def __init__(self, ms, mb: int = 0, normalize: bool = True, device="cuda", band: int = 0):
+    def __init__(self, ms, mb: int = 0, normalize: bool = True, device="cuda", band: int = 0, split: int = 0):
         import torch
         self.ms = [int(v) for v in ms]
         self.count = len(self.ms)
-        self.opts = make_opts(mb, normalize, band)
+        self.opts = make_opts(mb, normalize, band, split=split)
         self._m = _i64_array(self.ms)
         self.nbytes = int(load().rtgevc_batched_workspace_size(self.count, self._m, ctypes.byref(self.opts)))
         self.work = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
@@ -428,9 +428,11 @@ class BatchSolver:
         return Z, [sc[:m] for sc, m in zip(scales, self.ms)], info
 
 
-def tgevc_batched(S, T, select=None, normalize: bool = True, mb: int = 0, stream=None, band: int = 0):
+def tgevc_batched(S, T, select=None, normalize: bool = True, mb: int = 0, stream=None, band: int = 0,
+                  split: int = 0):
     """Right eigenvectors of every pencil (S[i], T[i]) in one batched call."""
-    bs = BatchSolver([x.shape[0] for x in S], mb=mb, normalize=normalize, device=S[0].device, band=band)
+    bs = BatchSolver([x.shape[0] for x in S], mb=mb, normalize=normalize, device=S[0].device, band=band,
+                     split=split)
     Z, sc, info = bs.outputs()
     return bs.run(S, T, Z, sc, info, select=select, stream=stream)
 

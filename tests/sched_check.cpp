@@ -15,8 +15,11 @@
 //      order.
 // Data: Z tile (k, j) (the mantissas, exponents and norms of its segments) and the W
 // slot of each source row (2R slots reused cyclically).
-// Usage: sched_check rows R [drop]   (drop = index of a wait to omit: the result shows
-// whether the checks notice; -1 = none).  Prints "OK" or the first violation.
+// Usage: sched_check rows R [drop [split]]   (drop = index of a wait to omit: the result
+// shows whether the checks notice; -1 = none).  Prints "OK" or the first violation.
+//        sched_check batch rows R steps cr [drop]   the batch lock-step schedule
+// (batch_band_schedule) as one pencil of `rows` tile rows sees it inside a group whose
+// largest pencil has `steps` bands, U2 in launches of cr rows (0: one launch).
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -52,6 +55,37 @@ struct Replay {
     launch(Op{2, s, {0, 0}, k_lo, k_hi, j_lo, s_lo, s_hi});
     return true;
   }
+  // the batch schedule's parts, in this pencil's rows (band b = B - 1 - t)
+  int B = 0;
+  bool band_of(int t, int& r_lo, int& r_hi) const {
+    const int b = B - 1 - t;
+    if (b < 0) return false;
+    r_lo = R * b;
+    r_hi = r_lo + R - 1 < rows - 1 ? r_lo + R - 1 : rows - 1;
+    return true;
+  }
+  bool solve(int t, int io, int s) {
+    int r_lo, r_hi;
+    if (band_of(t, r_lo, r_hi) && r_hi - io >= r_lo) solve(r_hi - io, s);
+    return true;
+  }
+  bool inband(int t, int io, int s) {
+    int r_lo, r_hi;
+    if (band_of(t, r_lo, r_hi) && r_hi - io > r_lo) update(r_lo, r_hi - io, r_hi - io, r_hi - io, r_hi - io, s);
+    return true;
+  }
+  bool next(int t, int s) {
+    int r_lo, r_hi;
+    if (band_of(t, r_lo, r_hi) && r_lo > 0) update(r_lo - R > 0 ? r_lo - R : 0, r_lo, r_lo, r_lo, r_hi, s);
+    return true;
+  }
+  bool above(int t, int off, int cnt, int s) {
+    int r_lo, r_hi;
+    if (!band_of(t, r_lo, r_hi)) return true;
+    const int hi = r_lo - R - off;
+    if (hi > 0) update(hi - cnt > 0 ? hi - cnt : 0, hi, r_lo, r_lo, r_hi, s);
+    return true;
+  }
   bool record(int e, int s) {
     ev[e][0] = cur[s][0];
     ev[e][1] = cur[s][1];
@@ -79,13 +113,28 @@ static std::string desc(const Op& o) {
 int main(int argc, char** argv) {
   if (argc < 3) return 2;
   Replay rp;
-  rp.rows = atoi(argv[1]);
-  rp.R = atoi(argv[2]);
-  rp.drop = argc > 3 ? atoi(argv[3]) : -1;
-  const int split = argc > 4 ? atoi(argv[4]) : 0;
+  const bool batch = std::string(argv[1]) == "batch";
+  const int a0 = batch ? 2 : 1;
+  if (argc < a0 + 2 || (batch && argc < 6)) return 2;
+  rp.rows = atoi(argv[a0]);
+  rp.R = atoi(argv[a0 + 1]);
   // pre-processing before and consolidation after, on the caller's stream
   rp.launch(Op{0, 0, {0, 0}, 0, rp.rows, 0, 0, rp.rows - 1});
-  rgev::band_schedule(rp.rows, rp.R, split, rp);
+  if (batch) {
+    const int steps = atoi(argv[4]), cr = atoi(argv[5]);
+    rp.drop = argc > 6 ? atoi(argv[6]) : -1;
+    rp.B = (rp.rows + rp.R - 1) / rp.R;
+    if (steps < rp.B) return 2;
+    // the group's largest U2 row count per step: the largest pencil's (B = steps)
+    std::vector<int> above(steps);
+    for (int t = 0; t < steps; ++t) above[t] = rp.R * (steps - 2 - t) > 0 ? rp.R * (steps - 2 - t) : 0;
+    std::vector<int> crs(steps, cr);
+    rgev::batch_band_schedule(steps, rp.R, crs.data(), above.data(), rp);
+  } else {
+    rp.drop = argc > 3 ? atoi(argv[3]) : -1;
+    const int split = argc > 4 ? atoi(argv[4]) : 0;
+    rgev::band_schedule(rp.rows, rp.R, split, rp);
+  }
   rp.launch(Op{3, 0, {0, 0}, 0, rp.rows, 0, 0, rp.rows - 1});
   const int rows = rp.rows, R = rp.R, WS = 2 * R;
   const std::vector<Op>& ops = rp.ops;

@@ -97,7 +97,7 @@ def test_compiled_table_is_well_formed_and_used():
             lo = int(m_max) + 1
     lo = 1
     for m_max, mb in batch:
-        assert rt.resolve_opts(lo, batched=True) == (int(mb), 2)   # lock-step band
+        assert rt.resolve_opts(lo, batched=True) == (int(mb), 3)   # lock-step band
         if m_max != "INT64_MAX":
             lo = int(m_max) + 1
     # explicit options win

@@ -87,8 +87,9 @@ def test_batched_parity_mixed_sizes(mb):
 
 @pytest.mark.parametrize("band", [1, 3, 4])
 def test_batched_matches_single_calls(band):
-    """A pencil gives the same eigenvectors alone and inside a batch (same tile size and
-    band: the batch's lock-step applies the same tile updates in the same groups)."""
+    """A pencil gives the same eigenvectors alone and inside a batch, bit for bit (same tile
+    size and band: the batch's lock-step applies the same tile updates in the same groups,
+    and a tile's products accumulate in the same order whatever the waves per tile)."""
     torch = _torch()
     from paper_2003_04776_amd import rtgevc as rt
     ms = [300, 129, 700, 64, 1]
@@ -98,11 +99,11 @@ def test_batched_matches_single_calls(band):
     torch.cuda.synchronize()
     assert int(info.abs().sum().item()) == 0
     for i in range(len(ms)):
-        r = rt.tgevc(Sd[i], Td[i], mb=64, band=band)
+        r = rt.tgevc(Sd[i], Td[i], mb=64, band=band, schedule=1)   # (the band wavefront, not the walker)
         torch.cuda.synchronize()
         d = float((Z[i] - r.Z).abs().max())
         _say(f"   band {band} pencil {i} m={ms[i]}: batched vs single {d:.2e}")
-        assert d <= 1e-13
+        assert torch.equal(Z[i], r.Z)   # the same tile operations in the same order
 
 
 def test_batched_stress_select_and_scales():

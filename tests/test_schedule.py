@@ -71,3 +71,42 @@ def test_replay_detects_a_missing_wait(checker):
     u1_u2 = [r for r in races if r.count("update(") == 2]
     # bands 5 .. 1 each have a U1 that must wait for the previous band's U2
     assert len(u1_u2) == 5, races
+
+
+def _run_batch(exe, rows, band, steps, cr, drop=-1):
+    r = subprocess.run([exe, "batch", str(rows), str(band), str(steps), str(cr), str(drop)], capture_output=True,
+                       text=True)
+    return r.returncode, r.stdout.strip()
+
+
+@pytest.mark.parametrize("cr", [0, 1, 3])
+@pytest.mark.parametrize("band", [1, 2, 3, 4])
+def test_batch_schedule_orders_every_conflict(checker, band, cr):
+    """The batch lock-step schedule as each pencil of a group sees it (its own tile rows,
+    inside a group whose largest pencil has up to three bands more): the same checks as for
+    one pencil, with the update of the rows above a band in one launch or in launches of
+    cr tile rows."""
+    for rows in range(1, 41):
+        nb = (rows + band - 1) // band
+        for steps in (nb, nb + 1, nb + 3):
+            rc, out = _run_batch(checker, rows, band, steps, cr)
+            assert rc == 0 and out.startswith("OK"), (rows, band, steps, cr, out)
+
+
+def test_batch_replay_detects_a_missing_wait(checker):
+    """Dropping any one of the batch schedule's waits that order two streams is reported as
+    a race for a pencil with enough bands (each wait is the only order between some pair)."""
+    rows, band = 20, 2
+    steps = (rows + band - 1) // band
+    rc, out = _run_batch(checker, rows, band, steps, 0)
+    assert rc == 0, out
+    n_wait = int(out.split()[-2])
+    raced = 0
+    for d in range(n_wait):
+        rc, out = _run_batch(checker, rows, band, steps, 0, d)
+        if rc != 0:
+            assert out.startswith("RACE"), out
+            raced += 1
+    # every wait is needed but the side stream's start, the first step's wait for a U2 that
+    # does not exist, and the final join (the last U2 is already ordered before the last U1)
+    assert raced == n_wait - 3, (raced, n_wait)
