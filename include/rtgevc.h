@@ -117,7 +117,8 @@ typedef struct rtgevc_opts {
                          computation in any launch, so every value gives the same
                          eigenvectors bit for bit.  The launch boundaries give the chain of
                          tile solves, which runs beside these updates on the caller's
-                         stream, a share of the GPU.                                    */
+                         stream, a share of the GPU.  rtgevc_batched: tiles per launch
+                         summed over a group's pencils (0 or -1: one launch per step). */
 } rtgevc_opts;
 
 /* Bytes of device workspace rtgevc() needs for order m with these options
@@ -307,7 +308,7 @@ int rtgevc_batched(int32_t count, const int64_t *m, const double *const *S, cons
                    void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream);
 
 /* The tile size and band a call with these options would use for order m (batched != 0:
- * as a pencil of rtgevc_batched: its band is opts->band, or 2 when that is 0).  The automatic choices come
+ * as a pencil of rtgevc_batched: its band is opts->band, or 3 when that is 0).  The automatic choices come
  * from a table compiled into the library, written by an autotuning sweep on the GPU
  * (performance parameters only: every choice computes the same eigenvectors).
  * out receives mb, band, schedule, normalize, precision, the refinement sweeps in max_refine
