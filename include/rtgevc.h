@@ -119,6 +119,11 @@ typedef struct rtgevc_opts {
                          tile solves, which runs beside these updates on the caller's
                          stream, a share of the GPU.  rtgevc_batched: tiles per launch
                          summed over a group's pencils (0 or -1: one launch per step). */
+  int32_t grid;       /* schedule 2: workgroups of the persistent walker; 0 = automatic (as
+                         many as are resident on the GPU at once), else at most that many.
+                         Performance only: every count gives the same eigenvectors bit for
+                         bit (tasks are taken in one fixed order by running workgroups).
+                         Must be >= 0.                                                   */
 } rtgevc_opts;
 
 /* Bytes of device workspace rtgevc() needs for order m with these options
@@ -312,7 +317,8 @@ int rtgevc_batched(int32_t count, const int64_t *m, const double *const *S, cons
  * from a table compiled into the library, written by an autotuning sweep on the GPU
  * (performance parameters only: every choice computes the same eigenvectors).
  * out receives mb, band, schedule, normalize, precision, the refinement sweeps in max_refine
- * (-1 when none run), refine_bits as given and split (tiles per launch; -1: one launch).  Returns 0, -1 (m < 0),
+ * (-1 when none run), refine_bits as given, split (tiles per launch; -1: one launch) and grid
+ * as given.  Returns 0, -1 (m < 0),
  * -3 (invalid opts) or -4 (out is NULL).  Host only; touches no GPU. */
 int rtgevc_resolve_opts(int64_t m, int32_t batched, const rtgevc_opts *opts, rtgevc_opts *out);
 

@@ -106,6 +106,7 @@ bool opts_ok(const rtgevc_opts* o) {
   if (o->max_refine < -1 || o->max_refine > 3) return false;
   if (o->refine_bits < 0 || o->refine_bits > 100) return false;
   if (o->split < -1) return false;
+  if (o->grid < 0) return false;
   return true;
 }
 
@@ -417,7 +418,10 @@ PencilDesc make_desc(int64_t m, const double* S, int64_t lds, const double* T, i
   P.split = resolve_split(m, opts);
   P.info = info ? info : &P.ctrl->info_local;
   P.normalize = opts ? opts->normalize : 1;
-  if (walk) walk->spin_limit = (opts && opts->watchdog > 0) ? opts->watchdog : kDefaultSpinLimit;
+  if (walk) {
+    walk->spin_limit = (opts && opts->watchdog > 0) ? opts->watchdog : kDefaultSpinLimit;
+    walk->grid = opts ? opts->grid : 0;
+  }
   return P;
 }
 
@@ -1053,6 +1057,7 @@ int rtgevc_resolve_opts(int64_t m, int32_t batched, const rtgevc_opts* opts, rtg
   out->refine_bits = opts ? opts->refine_bits : 0;
   const int split = batched ? batch_split(opts) : resolve_split(m, opts);
   out->split = split > 0 ? split : -1;
+  out->grid = opts ? opts->grid : 0;
   return 0;
 }
 

@@ -141,7 +141,7 @@ struct WalkDesc {
   int64_t* levels;    // [2 Mmax + 1] first ticket of each level; the last entry is the count
   int32_t* next;      // ticket dispenser
   int32_t spin_limit; // bound on every dependency wait
-  int32_t pad;
+  int32_t grid;       // workgroups to launch (0: as many as are resident at once; capped there)
 };
 
 // number of walker tasks for M tiles: per distance d = j - r, M - d solves and

@@ -134,7 +134,8 @@ __global__ __launch_bounds__(solve_total(MB)) void walker_kernel(PencilDesc P, W
 
 template <int MB>
 static hipError_t launch_walker_t(const PencilDesc& P, const WalkDesc& W, hipStream_t s) {
-  // resident workgroups: as many as fit at once (more would only wait for the end)
+  // resident workgroups: as many as fit at once (more would only wait for the end), or the
+  // caller's smaller count
   static int grid_cache[64] = {0};
   int dev = 0;
   hipError_t err = hipGetDevice(&dev);
@@ -147,7 +148,10 @@ static hipError_t launch_walker_t(const PencilDesc& P, const WalkDesc& W, hipStr
     if (err != hipSuccess) return err;
     grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
   }
-  walker_kernel<MB><<<grid, solve_total(MB), 0, s>>>(P, W);
+  // a requested count below that: the tasks are taken from the ticket dispenser only by
+  // running workgroups, so any count makes progress and computes the same results
+  const int g = (W.grid > 0 && W.grid < grid) ? W.grid : grid;
+  walker_kernel<MB><<<g, solve_total(MB), 0, s>>>(P, W);
   return hipGetLastError();
 }
 

@@ -37,7 +37,8 @@ class RtgevcError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("mb", ctypes.c_int32), ("normalize", ctypes.c_int32), ("band", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("watchdog", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("max_refine", ctypes.c_int32), ("refine_bits", ctypes.c_int32), ("split", ctypes.c_int32)]
+                ("max_refine", ctypes.c_int32), ("refine_bits", ctypes.c_int32), ("split", ctypes.c_int32),
+                ("grid", ctypes.c_int32)]
 
 
 _lib = None
@@ -109,8 +110,9 @@ PRECISION_MIXED = 1    # tile-update contraction on the int8 matrix cores from s
 
 
 def make_opts(mb: int = 0, normalize: bool = True, band: int = 0, schedule: int = 0, watchdog: int = 0,
-              precision: int = 0, max_refine: int = 0, refine_bits: int = 0, split: int = 0) -> Opts:
+              precision: int = 0, max_refine: int = 0, refine_bits: int = 0, split: int = 0, grid: int = 0) -> Opts:
     o = Opts()
+    o.grid = int(grid)
     o.split = int(split)
     o.max_refine = int(max_refine)
     o.refine_bits = int(refine_bits)
@@ -198,11 +200,11 @@ class Solver:
 
     def __init__(self, m: int, mb: int = 0, normalize: bool = True, band: int = 0, device="cuda",
                  schedule: int = 0, watchdog: int = 0, precision: int = 0, left: bool = False,
-                 max_refine: int = 0, refine_bits: int = 0, split: int = 0):
+                 max_refine: int = 0, refine_bits: int = 0, split: int = 0, grid: int = 0):
         import torch
         self.m = int(m)
         self.left = bool(left)
-        self.opts = make_opts(mb, normalize, band, schedule, watchdog, precision, max_refine, refine_bits, split)
+        self.opts = make_opts(mb, normalize, band, schedule, watchdog, precision, max_refine, refine_bits, split, grid)
         size = load().rtgevc_left_workspace_size if self.left else load().rtgevc_workspace_size
         self.nbytes = int(size(self.m, ctypes.byref(self.opts)))
         self.work = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)

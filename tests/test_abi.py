@@ -71,6 +71,7 @@ def test_argument_errors_before_any_gpu_work():
     assert _call(opts=rt.make_opts(precision=1, refine_bits=101)) == -13
     assert _call(opts=rt.make_opts(refine_bits=-1)) == -13
     assert _call(opts=rt.make_opts(split=-2)) == -13
+    assert _call(opts=rt.make_opts(schedule=2, grid=-1)) == -13
     assert _call(opts=rt.make_opts(schedule=3)) == -13
     assert _call(opts=rt.make_opts(watchdog=-1)) == -13
     assert _call(opts=rt.make_opts(precision=2)) == -13
@@ -247,3 +248,19 @@ def test_complex_workspace_and_argument_errors():
     assert call(nbytes=16) == -12
     assert call(opts=rt.make_opts(mb=48)) == -13
     assert call(m=0, S=None, T=None, Z=None, lds=1, ldt=1, ldz=1) == 0
+
+
+def test_opts_layout_matches_the_header(tmp_path):
+    """The Python binding's rtgevc_opts has the C header's size and field offsets (compiled
+    from include/rtgevc.h with the host compiler)."""
+    import subprocess
+    names = [f[0] for f in rt.Opts._fields_]
+    src = tmp_path / "layout.c"
+    body = "".join(f'  printf("%zu\\n", offsetof(rtgevc_opts, {n}));\n' for n in names)
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "rtgevc.h"\n'
+                   'int main(void) {\n  printf("%zu\\n", sizeof(rtgevc_opts));\n' + body + '  return 0;\n}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert out[0] == ctypes.sizeof(rt.Opts)
+    assert out[1:] == [getattr(rt.Opts, n).offset for n in names]

@@ -475,6 +475,23 @@ def test_walker_repeat_is_deterministic():
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("grid", [1, 7, 64])
+def test_walker_grid_counts(grid):
+    """opts->grid: the walker with fewer workgroups than fit (one workgroup takes every task in
+    ticket order) gives the automatic count's eigenvectors bit for bit."""
+    torch = _torch()
+    from paper_2003_04776_amd import rtgevc as rt
+    m = 900
+    S, T, _ = pencils.schur_pencil(m, 413)
+    Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
+    _say(f"[walker grid] m={m} grid={grid}")
+    a = rt.Solver(m, mb=64, schedule=rt.SCHEDULE_WALKER).run(Sd, Td)
+    b = rt.Solver(m, mb=64, schedule=rt.SCHEDULE_WALKER, grid=grid).run(Sd, Td)
+    torch.cuda.synchronize()
+    assert int(a.info.item()) == 0 and int(b.info.item()) == 0
+    assert torch.equal(a.Z, b.Z)
+
+
 def test_walker_watchdog_bit():
     """A dependency-wait bound of one polling round (set from the host) makes waits give
     up: the launch still drains and reports the watchdog bit."""
