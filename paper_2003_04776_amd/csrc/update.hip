@@ -62,11 +62,41 @@ void update_batched_kernel(const PencilDesc* __restrict__ D, int R, int t, int p
   update_tile<MB, BatchUpdShape<MB>::R, BatchUpdShape<MB>::C, BatchUpdShape<MB>::S>(P, U, k, j, sm);
 }
 
+// The same update with BatchUpdShape's tiles (one wave per tile of 64): for launches of at
+// least kFarTiles tiles (the updates of the rows above a band in larger pencils), which are
+// bound by throughput.
+constexpr int64_t kFarTiles = 4096;
+template <int MB>
+__global__ __launch_bounds__(64 * BatchUpdShape<MB>::R * BatchUpdShape<MB>::C, BatchUpdShape<MB>::W)
+void update_far_kernel(PencilDesc P, UpdRange U) {
+  const int M = P.ctrl->M;
+  if (U.j_lo >= M || U.k_hi <= U.k_lo || U.s_lo >= M) return;
+  const int nk = U.k_hi - U.k_lo, nj = M - U.j_lo;
+  const int nbk = (nk + 7) / 8, nbj = (nj + 7) / 8;
+  const int per = (int)(gridDim.x / 8);
+  const int idx = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (idx >= nbk * nbj * 64) return;
+  const int blk = idx / 64, w64 = idx % 64;
+  const int k = U.k_lo + 8 * (blk % nbk) + (w64 % 8);
+  const int j = U.j_lo + 8 * (blk / nbk) + (w64 / 8);
+  if (k >= U.k_hi || j >= M) return;
+  if (P.rhs && !P.tflag[j]) return;
+  __shared__ UpdSmem<MB, BatchUpdShape<MB>::R> sm;
+  update_tile<MB, BatchUpdShape<MB>::R, BatchUpdShape<MB>::C, BatchUpdShape<MB>::S>(P, U, k, j, sm);
+}
+
 template <int MB>
 static void launch_update_t(const PencilDesc& P, const UpdRange& U, hipStream_t s) {
   // upper bound on the 8 x 8 blocked tile range (the true tile count is on the device)
   const int64_t nbk = (U.k_hi - U.k_lo + 7) / 8, nbj = (P.Mmax - U.j_lo + 7) / 8;
   const int64_t grid = nbk * nbj * 64;
+  if constexpr (MB == 64) {
+    // (a launch of fewer tiles ends sooner with four waves per tile)
+    if ((int64_t)(U.k_hi - U.k_lo) * (P.Mmax - U.j_lo) >= kFarTiles) {
+      update_far_kernel<MB><<<(unsigned)grid, 64 * BatchUpdShape<MB>::R * BatchUpdShape<MB>::C, 0, s>>>(P, U);
+      return;
+    }
+  }
   update_kernel<MB><<<(unsigned)grid, 64 * UpdShape<MB>::R * UpdShape<MB>::C, 0, s>>>(P, U);
 }
 
