@@ -534,6 +534,18 @@ def main():
             "flops_per_launch": upd_flops / max(upd_launches, 1),
             "measured_with": "rtgevc_timed (HIP events on the stream of every launch), 2 calls",
         },
+        # the same kernel's launches on the side stream alone (the updates of the rows above the
+        # next band, most of the flops), beside the roofline over every launch
+        "side_stream_updates": None if res_sched == 2 else {
+            "what": "update_kernel launches of the side stream (the rows above the next band)",
+            "launches": int(sum(s["n_side_update"] for s in stats)),
+            "share_of_update_flops": round(sum(s["side_update_flops"] for s in stats) / max(upd_flops, 1.0), 4),
+            "avg_launch_ms": round(sum(s["side_update_ms"] for s in stats) / max(sum(s["n_side_update"] for s in stats), 1), 4),
+            "achieved": round(sum(s["side_update_flops"] for s in stats)
+                              / max(sum(s["side_update_ms"] for s in stats) * 1e-3, 1e-12) / 1e12, 3),
+            "frac": round(sum(s["side_update_flops"] for s in stats)
+                          / max(sum(s["side_update_ms"] for s in stats) * 1e-3, 1e-12) / 1e12 / FP64_MFMA_PEAK, 4),
+        },
         "phases_ms": {k: round(st0[k], 3) for k in ("pre_ms", "solve_ms", "update_ms", "consolidate_ms",
                                                      "refine_ms", "total_ms")},
         "info": info_v,

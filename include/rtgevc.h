@@ -268,8 +268,11 @@ int rtgevc_backtransform(int64_t m, const double *S, int64_t lds, const double *
  *   [9] algorithmic flops of the tile updates, sum over k < r <= j of 4 h_k h_r h_j
  *   [10] number of tiles M;  [11] tile size mb
  *   [12] device time of the refinement sweeps (mixed precision), ms;  [13] sweeps
+ *   [14..16] the tile-update launches of the side stream alone (the band schedule's updates
+ *          of the rows above the next band): summed device time, ms; their algorithmic
+ *          flops (the same sum over their target rows, sources and columns); their number
  * Returns 0, a negative argument code as rtgevc() (-15: stats), or -1000 - hipError. */
-#define RTGEVC_TIMED_NSTATS 14
+#define RTGEVC_TIMED_NSTATS 17
 int rtgevc_timed(int64_t m, const double *S, int64_t lds, const double *T, int64_t ldt,
                  const int32_t *select, double *Z, int64_t ldz, int32_t *scales, int32_t *info,
                  void *work, size_t work_bytes, const rtgevc_opts *opts, void *stream,

@@ -328,8 +328,9 @@ hipError_t get_aux(Aux** out) {
 
 // The blocked back-substitution for tile rows [0, rows): the band wavefront schedule
 // (schedule.hpp) enqueued on the caller's stream sa and the side stream.  mark(kind,
-// before, stream) brackets each launch (kind 1 = solve, 2 = update); rows at or beyond
-// the device's tile count M are no-ops in the kernels.
+// before, stream, range) brackets each launch (kind 1 = solve, 2 = update with its range
+// {k_lo, k_hi, j_lo, s_lo, s_hi}, nullptr for a solve); rows at or beyond the device's tile
+// count M are no-ops in the kernels.
 template <class Mark>
 hipError_t enqueue_rows(const PencilDesc& P, int rows, hipStream_t sa, Aux& ax, Mark&& mark) {
   hipError_t err = hipSuccess;
@@ -344,15 +345,16 @@ hipError_t enqueue_rows(const PencilDesc& P, int rows, hipStream_t sa, Aux& ax, 
       return err == hipSuccess;
     }
     bool solve(int i, int s) {
-      mark(1, true, st[s]);
+      mark(1, true, st[s], nullptr);
       launch_solve(P, i, st[s]);
-      mark(1, false, st[s]);
+      mark(1, false, st[s], nullptr);
       return err == hipSuccess;
     }
     bool update(int k_lo, int k_hi, int j_lo, int s_lo, int s_hi, int s) {
-      mark(2, true, st[s]);
+      const int rng[5] = {k_lo, k_hi, j_lo, s_lo, s_hi};
+      mark(2, true, st[s], rng);
       launch_update(P, k_lo, k_hi, j_lo, s_lo, s_hi, st[s]);
-      mark(2, false, st[s]);
+      mark(2, false, st[s], rng);
       return err == hipSuccess;
     }
     bool record(int e, int s) { return ok(hipEventRecord(ev[e], st[s])); }
@@ -529,10 +531,10 @@ hipError_t enqueue_right(int64_t m, const double* S, int64_t lds, const double* 
   hipError_t err = get_aux(&ax);
   if (err != hipSuccess) return err;
   launch_preprocess(P, s);
-  err = enqueue_rows(P, P.Mmax, s, *ax, [](int, bool, hipStream_t) {});
+  err = enqueue_rows(P, P.Mmax, s, *ax, [](int, bool, hipStream_t, const int*) {});
   if (err == hipSuccess && sweeps > 0)
     err = enqueue_refine(P, R, sweeps, s, [&](const PencilDesc& C) {
-      return enqueue_rows(C, C.Mmax, s, *ax, [](int, bool, hipStream_t) {});
+      return enqueue_rows(C, C.Mmax, s, *ax, [](int, bool, hipStream_t, const int*) {});
     });
   launch_consolidate(P, s);
   return err == hipSuccess ? hipGetLastError() : err;
@@ -821,13 +823,13 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
     if (err == hipSuccess) err = e;
   };
   auto mark = [&]() { mark_on(s); };
-  struct Span { int cls, e0, e1; };
+  struct Span { int cls, e0, e1, side; int rng[5]; };
   Span* spans = new Span[nlaunch];
   int nsp = 0;
   mark();
   launch_preprocess(P, s);
   mark();
-  spans[nsp++] = Span{0, 0, 1};
+  spans[nsp++] = Span{0, 0, 1, 0, {}};
   int32_t M = 0;
   err = hipMemcpyAsync(&M, &P.ctrl->M, sizeof(int32_t), hipMemcpyDeviceToHost, s);
   if (err == hipSuccess) err = hipStreamSynchronize(s);
@@ -837,12 +839,14 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
     mark();
     err = launch_walk(P, W, s);
     mark();
-    spans[nsp++] = Span{2, e0, e0 + 1};
+    spans[nsp++] = Span{2, e0, e0 + 1, 0, {}};
   } else if (err == hipSuccess) {
-    const hipError_t e = enqueue_rows(P, M, s, *ax, [&](int kind, bool before, hipStream_t st) {
+    const hipError_t e = enqueue_rows(P, M, s, *ax, [&](int kind, bool before, hipStream_t st, const int* rng) {
       mark_on(st);
       if (!before && nsp < nlaunch) {
-        spans[nsp] = Span{kind, used - 2, used - 1};
+        spans[nsp] = Span{kind, used - 2, used - 1, st == ax->side ? 1 : 0, {}};
+        if (rng)
+          for (int q = 0; q < 5; ++q) spans[nsp].rng[q] = rng[q];
         ++nsp;
       }
     });
@@ -853,16 +857,16 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
     const int f0 = used;
     mark();
     err = enqueue_refine(P, R, sweeps, s, [&](const PencilDesc& C) {
-      return enqueue_rows(C, M, s, *ax, [](int, bool, hipStream_t) {});
+      return enqueue_rows(C, M, s, *ax, [](int, bool, hipStream_t, const int*) {});
     });
     mark();
-    spans[nsp++] = Span{4, f0, f0 + 1};
+    spans[nsp++] = Span{4, f0, f0 + 1, 0, {}};
   }
   const int c0 = used;
   mark();
   launch_consolidate(P, s);
   mark();
-  spans[nsp++] = Span{3, c0, c0 + 1};
+  spans[nsp++] = Span{3, c0, c0 + 1, 0, {}};
   if (err == hipSuccess) err = hipGetLastError();
   if (err == hipSuccess) err = hipStreamSynchronize(s);
   int32_t* edges = new int32_t[M + 1];
@@ -879,6 +883,21 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
       }
       stats[1 + spans[i].cls] += ms;
       stats[5 + spans[i].cls] += 1.0;
+      if (spans[i].cls == 2 && spans[i].side) {
+        // the side stream's update launches: time, count and algorithmic flops of their
+        // ranges (target rows [k_lo, k_hi), columns j >= j_lo, sources s_lo .. min(s_hi, j))
+        const int* g = spans[i].rng;
+        const int k1 = g[1] < M ? g[1] : M, s1 = g[4] < M - 1 ? g[4] : M - 1;
+        double fl = 0.0;
+        if (g[0] < k1)
+          for (int r = g[3]; r <= s1; ++r) {
+            const int j0 = g[2] > r ? g[2] : r;
+            fl += 4.0 * (double)(edges[k1] - edges[g[0]]) * (edges[r + 1] - edges[r]) * (edges[M] - edges[j0]);
+          }
+        stats[14] += ms;
+        stats[15] += fl;
+        stats[16] += 1.0;
+      }
     }
     stats[13] = sweeps;
     // algorithmic flops of the tile updates: sum over k < r <= j of 2 h_k (2 h_r) h_j

@@ -98,7 +98,7 @@ EXPORTED = ("rtgevc_workspace_size", "rtgevc", "rtgevc_eigvals", "rtgevc_timed",
             "rtgevc_noalloc", "rtgevc_complex_workspace_size", "rtgevc_complex")
 NOALLOC_SCRATCH_BYTES = 64 << 20   # RTGEVC_NOALLOC_SCRATCH_BYTES
 ERR_SCRATCH = -2000                # RTGEVC_ERR_SCRATCH
-TIMED_NSTATS = 14
+TIMED_NSTATS = 17
 
 
 SCHEDULE_BANDS = 1     # band wavefront with look-ahead (default)
@@ -248,7 +248,8 @@ class Solver:
                                  ctypes.byref(self.opts), _stream_ptr(stream), st, TIMED_NSTATS)
         _check(rc, "rtgevc_timed")
         keys = ("total_ms", "pre_ms", "solve_ms", "update_ms", "consolidate_ms", "n_pre", "n_solve",
-                "n_update", "n_consolidate", "update_flops", "M", "mb", "refine_ms", "sweeps")
+                "n_update", "n_consolidate", "update_flops", "M", "mb", "refine_ms", "sweeps",
+                "side_update_ms", "side_update_flops", "n_side_update")
         return dict(zip(keys, list(st)))
 
     def eigvals(self, S, T, stream=None):

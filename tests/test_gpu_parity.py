@@ -337,6 +337,28 @@ def test_timed_with_many_launches():
     assert torch.equal(Z, ref.Z)
 
 
+def test_timed_side_stream_updates():
+    """The timed entry point's side-stream figures: one launch per band with rows above the next
+    band (one launch per band update, split 0), most of the update flops, never more than all."""
+    torch = _torch()
+    from paper_2003_04776_amd import rtgevc as rt
+    m, band = 2000, 2
+    S, T, _ = pencils.schur_pencil(m, 31)
+    Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
+    sv = rt.Solver(m, mb=64, band=band, split=-1, schedule=1)
+    Z = rt.colmajor_empty(m)
+    sc = torch.zeros(m, dtype=torch.int32, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    st = sv.run_timed(Sd, Td, Z, sc, info)
+    torch.cuda.synchronize()
+    M = int(st["M"])
+    _say(f"[timed side] M={M} side launches {st['n_side_update']:.0f}, flops {st['side_update_flops']:.3e} "
+         f"of {st['update_flops']:.3e}")
+    assert int(st["n_side_update"]) == max(0, (M - 1) // band - 1)
+    assert 0.5 * st["update_flops"] < st["side_update_flops"] <= st["update_flops"]
+    assert 0.0 < st["side_update_ms"] <= st["update_ms"]
+
+
 def test_repeat_is_deterministic():
     m = 600
     S, T, _ = pencils.schur_pencil(m, 27)
