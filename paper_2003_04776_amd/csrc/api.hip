@@ -25,6 +25,7 @@
 namespace rgev {
 void launch_preprocess(const PencilDesc& P, hipStream_t s);
 void launch_solve(const PencilDesc& P, int r, hipStream_t s);
+void launch_band_chain(const PencilDesc& P, int r_lo, int r_hi, hipStream_t s);
 bool launch_update(const PencilDesc& P, int k_lo, int k_hi, int j_lo, int s_lo, int s_hi, hipStream_t s);
 void launch_consolidate(const PencilDesc& P, hipStream_t s);
 void launch_preprocess_batched(const PencilDesc* D, int n, int64_t max_m, int max_tiles, hipStream_t s);
@@ -93,6 +94,10 @@ int resolve_split(int64_t m, const rtgevc_opts* o) {
   if (resolve_mb(m, o) != (mx ? t.mb_mixed : t.mb) || resolve_band(m, o) != (mx ? t.band_mixed : t.band)) return 0;
   return mx ? t.split_mixed : t.split;
 }
+
+// C(b) of the band schedule as one launch (band_chain_kernel) for FP64 tile updates and bands
+// of more than one row; the mixed mode keeps its in-band updates on the int8 kernel
+bool use_chain(const PencilDesc& P) { return P.precision == 0 && P.band > 1; }
 
 bool opts_ok(const rtgevc_opts* o) {
   if (!o) return true;
@@ -357,6 +362,13 @@ hipError_t enqueue_rows(const PencilDesc& P, int rows, hipStream_t sa, Aux& ax, 
       mark(2, false, st[s], rng);
       return err == hipSuccess;
     }
+    bool chain(int r_lo, int r_hi, int s) {
+      if (!use_chain(P)) return chain_steps(r_lo, r_hi, s, *this);
+      mark(1, true, st[s], nullptr);   // (timed as a solve launch: it holds the band's solves)
+      launch_band_chain(P, r_lo, r_hi, st[s]);
+      mark(1, false, st[s], nullptr);
+      return err == hipSuccess;
+    }
     bool record(int e, int s) { return ok(hipEventRecord(ev[e], st[s])); }
     bool wait(int s, int e) { return ok(hipStreamWaitEvent(st[s], ev[e], 0)); }
   } ops{P, {sa, ax.side}, {ax.evC, ax.evJ, ax.evU[0], ax.evU[1]}, mark, err};
@@ -459,6 +471,11 @@ hipError_t enqueue_rows_one_stream(const PencilDesc& P, int rows, hipStream_t s)
     }
     bool update(int k_lo, int k_hi, int j_lo, int s_lo, int s_hi, int) {
       launch_update(P, k_lo, k_hi, j_lo, s_lo, s_hi, s);
+      return true;
+    }
+    bool chain(int r_lo, int r_hi, int st) {
+      if (!use_chain(P)) return chain_steps(r_lo, r_hi, st, *this);
+      launch_band_chain(P, r_lo, r_hi, s);
       return true;
     }
     bool record(int, int) { return true; }
@@ -796,12 +813,18 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
   // events bracket every launch on the stream it runs on: the schedule's launches for the
   // largest tile count (a dry run of the same schedule), plus the few outside it
   struct Count {
+    bool fused;
     int n = 0;
     bool solve(int, int) { ++n; return true; }
     bool update(int, int, int, int, int, int) { ++n; return true; }
+    bool chain(int r_lo, int r_hi, int s) {
+      if (!fused) return chain_steps(r_lo, r_hi, s, *this);
+      ++n;
+      return true;
+    }
     bool record(int, int) { return true; }
     bool wait(int, int) { return true; }
-  } cnt;
+  } cnt{use_chain(P)};
   band_schedule(P.Mmax, P.band, P.split, cnt);
   const int nlaunch = cnt.n + 8;
   const int nev = 2 * nlaunch;
@@ -883,9 +906,9 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
       }
       stats[1 + spans[i].cls] += ms;
       stats[5 + spans[i].cls] += 1.0;
-      if (spans[i].cls == 2 && spans[i].side) {
-        // the side stream's update launches: time, count and algorithmic flops of their
-        // ranges (target rows [k_lo, k_hi), columns j >= j_lo, sources s_lo .. min(s_hi, j))
+      if (spans[i].cls == 2 && !walker) {
+        // an update launch: algorithmic flops of its range (target rows [k_lo, k_hi), columns
+        // j >= j_lo, sources s_lo .. min(s_hi, j)); the side stream's launches also apart
         const int* g = spans[i].rng;
         const int k1 = g[1] < M ? g[1] : M, s1 = g[4] < M - 1 ? g[4] : M - 1;
         double fl = 0.0;
@@ -894,21 +917,26 @@ int rtgevc_timed(int64_t m, const double* S, int64_t lds, const double* T, int64
             const int j0 = g[2] > r ? g[2] : r;
             fl += 4.0 * (double)(edges[k1] - edges[g[0]]) * (edges[r + 1] - edges[r]) * (edges[M] - edges[j0]);
           }
-        stats[14] += ms;
-        stats[15] += fl;
-        stats[16] += 1.0;
+        stats[9] += fl;
+        if (spans[i].side) {
+          stats[14] += ms;
+          stats[15] += fl;
+          stats[16] += 1.0;
+        }
       }
     }
     stats[13] = sweeps;
-    // algorithmic flops of the tile updates: sum over k < r <= j of 2 h_k (2 h_r) h_j
-    double fl = 0.0;
-    for (int r = M - 1; r >= 1; --r) {
-      const double hr = edges[r + 1] - edges[r];
-      const double hj_sum = (double)(edges[M] - edges[r]);   // columns of tiles j >= r
-      const double hk_sum = (double)edges[r];                // rows of tiles k < r
-      fl += 4.0 * hk_sum * hr * hj_sum;
+    if (walker) {
+      // algorithmic flops of the tile updates: sum over k < r <= j of 2 h_k (2 h_r) h_j
+      double fl = 0.0;
+      for (int r = M - 1; r >= 1; --r) {
+        const double hr = edges[r + 1] - edges[r];
+        const double hj_sum = (double)(edges[M] - edges[r]);   // columns of tiles j >= r
+        const double hk_sum = (double)edges[r];                // rows of tiles k < r
+        fl += 4.0 * hk_sum * hr * hj_sum;
+      }
+      stats[9] = fl;
     }
-    stats[9] = fl;
     stats[10] = M;
     stats[11] = P.mb;
   }

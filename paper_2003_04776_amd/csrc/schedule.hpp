@@ -7,7 +7,8 @@
 // Tile rows [0, rows) are grouped into bands of R rows, band b = rows [R b, R b + R - 1].
 // For each band from the bottom:
 //   C(b)   on the caller's stream A: the band's rows from the bottom up, each solve
-//          followed by the small update of the band rows above it;
+//          followed by the small update of the band rows above it (one launch per step, or
+//          one launch for all of them: ops.chain);
 //   U1(b)  on A: the band applied to the next band's rows [R (b - 1), R b);
 //   U2(b)  on the side stream B: the band applied to every row above, [0, R (b - 1)), in
 //          launches of about `split` tiles each (whole tile rows, from the bottom; 0: one
@@ -34,8 +35,22 @@ enum SchedEvent { kEvC = 0, kEvJ = 1, kEvU0 = 2, kEvU1 = 3 };
 
 // Ops:  solve(i, stream)                              solve tile row i (all columns j >= i)
 //       update(k_lo, k_hi, j_lo, s_lo, s_hi, stream)  sources [s_lo, s_hi] -> rows [k_lo, k_hi)
+//       chain(r_lo, r_hi, stream)                     C(b): rows r_hi .. r_lo, each solve(i)
+//                                                     followed by update(r_lo, i, i, i, i) (as
+//                                                     these launches, or fused in one launch)
 //       record(event, stream), wait(stream, event)    event order between the streams
 // Each returns false on failure, which stops the enqueue.
+
+// C(b) as separate launches, for the Ops that have no fused form
+template <class Ops>
+bool chain_steps(int r_lo, int r_hi, int stream, Ops& ops) {
+  bool ok = true;
+  for (int i = r_hi; i >= r_lo && ok; --i) {
+    ok = ops.solve(i, stream);
+    if (i > r_lo && ok) ok = ops.update(r_lo, i, i, i, i, stream);
+  }
+  return ok;
+}
 template <class Ops>
 bool band_schedule(int rows, int R, int split, Ops& ops) {
   bool ok = true;
@@ -47,10 +62,7 @@ bool band_schedule(int rows, int R, int split, Ops& ops) {
   chk(ops.record(kEvU1, kStreamB));
   for (int b = (rows - 1) / R; b >= 0 && ok; --b) {
     const int r_lo = R * b, r_hi = R * b + R - 1;
-    for (int i = (r_hi < rows ? r_hi : rows - 1); i >= r_lo && ok; --i) {
-      chk(ops.solve(i, kStreamA));
-      if (i > r_lo) chk(ops.update(r_lo, i, i, i, i, kStreamA));
-    }
+    chk(ops.chain(r_lo, r_hi < rows ? r_hi : rows - 1, kStreamA));
     if (r_lo > 0 && ok) {
       const int nlo = r_lo > R ? r_lo - R : 0;
       // U2(b + 1): evU[(b + 1) & 1] was last recorded after it

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include "solve_tile.hpp"
+#include "update_tile.hpp"
 
 namespace rgev {
 
@@ -17,6 +18,61 @@ __global__ __launch_bounds__(solve_total(MB), solve_waves_per_simd(MB)) __attrib
   constexpr int CS = SolveShape<MB>::CS;
   __shared__ SolveSmem<MB> sm;
   solve_tile<MB>(P, r, r + (int)blockIdx.x / CS, (int)blockIdx.x % CS, sm);
+}
+
+// The chain of one band, C(b) of the band schedule, in one launch: the band's rows r_hi ..
+// r_lo, each solve followed by the update of the band's rows above it by that row.  For a
+// tile column j these steps read and write only column j's tiles (and the band's tiles of S
+// and T), so one workgroup per tile column j = r_lo + blockIdx.x runs them in order, and the
+// launch has to be placed on the GPU once rather than once per step.  Every tile gets the
+// same operations in the same order as with one launch per step, so the results are the same
+// bit for bit.  The update runs on the workgroup's own waves (a 2 x 2 wave grid for tiles
+// of 128, 1 x 2 for 64, one wave for 32) with its shared memory in the solve's.
+template <int MB> struct ChainUpdShape;
+template <> struct ChainUpdShape<32> { static constexpr int R = 1, C = 1; };
+template <> struct ChainUpdShape<64> { static constexpr int R = 1, C = 2; };
+template <> struct ChainUpdShape<128> { static constexpr int R = 2, C = 2; };
+
+template <int MB>
+union ChainSmem {
+  SolveSmem<MB> s;
+  UpdSmem<MB, ChainUpdShape<MB>::R> u;
+};
+
+template <int MB>
+__global__ __launch_bounds__(solve_total(MB), solve_waves_per_simd(MB)) __attribute__((amdgpu_num_vgpr(256))) void band_chain_kernel(PencilDesc P, int r_lo, int r_hi) {
+  constexpr int WGR = ChainUpdShape<MB>::R, WGC = ChainUpdShape<MB>::C;
+  static_assert(64 * WGR * WGC == solve_total(MB), "chain workgroup size");
+  static_assert(SolveShape<MB>::CS == 1, "one workgroup per tile");
+  __shared__ ChainSmem<MB> sm;
+  const int M = P.ctrl->M;
+  const int j = r_lo + (int)blockIdx.x;
+  if (j >= M) return;
+  // (correction mode: tile columns with no refined column take no update, as in the
+  // update kernels; their solves still run)
+  const bool upd = !(P.rhs && !P.tflag[j]);
+  const int top = min(r_hi, j);
+  for (int r = top; r >= r_lo; --r) {
+    solve_tile<MB>(P, r, j, 0, sm.s);
+    if (r > r_lo && upd) {
+      const UpdRange U{r_lo, r, r, r, r};
+      for (int k = r_lo; k < r; ++k) {
+        __syncthreads();   // the solve's (or the previous update's) shared memory is free
+        update_tile<MB, WGR, WGC>(P, U, k, j, sm.u);
+      }
+    }
+    __syncthreads();   // every store of the step is visible to the workgroup's next step
+  }
+}
+
+void launch_band_chain(const PencilDesc& P, int r_lo, int r_hi, hipStream_t s) {
+  const int grid = P.Mmax - r_lo;
+  if (grid <= 0) return;
+  switch (P.mb) {
+    case 32: band_chain_kernel<32><<<grid, solve_total(32), 0, s>>>(P, r_lo, r_hi); break;
+    case 64: band_chain_kernel<64><<<grid, solve_total(64), 0, s>>>(P, r_lo, r_hi); break;
+    default: band_chain_kernel<128><<<grid, solve_total(128), 0, s>>>(P, r_lo, r_hi); break;
+  }
 }
 
 // one solve of a batch's lock-step t: in band B_p - 1 - t of every pencil p = blockIdx.y

@@ -55,6 +55,8 @@ struct Replay {
     launch(Op{2, s, {0, 0}, k_lo, k_hi, j_lo, s_lo, s_hi});
     return true;
   }
+  // a fused C(b) is the same steps in one launch: on one stream with nothing between them
+  bool chain(int r_lo, int r_hi, int s) { return rgev::chain_steps(r_lo, r_hi, s, *this); }
   // the batch schedule's parts, in this pencil's rows (band b = B - 1 - t)
   int B = 0;
   bool band_of(int t, int& r_lo, int& r_hi) const {
