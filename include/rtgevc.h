@@ -160,7 +160,7 @@ int rtgevc(int64_t m, const double *S, int64_t lds, const double *T, int64_t ldt
  * the array.
  *   Arguments as for rtgevc() (argument numbers: 11 = opts, 12 = stream).
  *   Returns RTGEVC_ERR_SCRATCH, with nothing enqueued, when rtgevc_workspace_size(m, opts)
- *   exceeds RTGEVC_NOALLOC_SCRATCH_BYTES (with default options FP64 fits up to m = 11466).
+ *   exceeds RTGEVC_NOALLOC_SCRATCH_BYTES (with default options FP64 fits up to m = 9212).
  * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (different
  * streams, or host threads, without ordering between them) race and give wrong results;
  * order them on one stream.  The array keeps the last call's contents; everything that must

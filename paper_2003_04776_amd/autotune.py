@@ -140,12 +140,22 @@ def choose_single(results, mixed=None, splits=None):
 
 
 def choose_batch(results):
-    """results: {(lo, hi): {mb: ms}} -> entries (m_max, mb), buckets ascending."""
+    """results: {(lo, hi): {mb: ms}} -> entries (m_max, mb), buckets ascending.  One tile size
+    for every bucket, the one with the least summed time over the buckets (that every bucket
+    timed): a batch runs its pencils in groups by tile size, one group after the other, so
+    mixing tile sizes adds whole lock-step sequences (per-bucket choices measured 44.0 ms on
+    the 512-pencil batch of orders U{64..2048} against 41.7 ms with tile 64 throughout)."""
     buckets = sorted(results)
+    if not buckets:
+        return []
+    common = set.intersection(*(set(results[b]) for b in buckets))
+    if common:
+        mb = min(sorted(common), key=lambda t: sum(results[b][t] for b in buckets))
+        return [(hi if i + 1 < len(buckets) else None, mb) for i, (lo, hi) in enumerate(buckets)]
     out = []
     for i, (lo, hi) in enumerate(buckets):
-        mb, _ = min(results[(lo, hi)].items(), key=lambda kv: kv[1])
-        out.append((hi if i + 1 < len(buckets) else None, mb))
+        mbi, _ = min(results[(lo, hi)].items(), key=lambda kv: kv[1])
+        out.append((hi if i + 1 < len(buckets) else None, mbi))
     return out
 
 

@@ -22,10 +22,12 @@ def test_choose_single_and_batch():
     # sizes without split timings take one launch per band (0)
     assert ch == [(1024, 128, 4, 1, 0, 128, 1, 0), (11585, 128, 1, 2, 0, 128, 1, 0),
                   (None, 128, 4, 1, 0, 128, 8, 2048)]
-    chb = autotune.choose_batch({(64, 128): {32: 1.0, 64: 2.0}, (128, 256): {64: 1.0, 128: 3.0}})
-    assert chb == [(128, 32), (None, 64)]
+    # one tile size for every bucket: the least summed time over the buckets that timed it
+    chb = autotune.choose_batch({(64, 128): {32: 1.0, 64: 2.0}, (128, 256): {32: 5.0, 64: 1.0, 128: 3.0}})
+    assert chb == [(128, 64), (None, 64)]
+    assert autotune.choose_batch({(64, 128): {32: 1.0}, (128, 256): {64: 1.0}}) == [(128, 32), (None, 64)]
     text = autotune.render_inc(ch, chb, "test")
-    assert "{INT64_MAX, 128, 4, 1, 0, 128, 8, 2048}" in text and "{128, 32}" in text
+    assert "{INT64_MAX, 128, 4, 1, 0, 128, 8, 2048}" in text and "{128, 64}" in text
 
 
 def test_choose_split_keeps_one_launch_within_noise():
