@@ -262,10 +262,13 @@ int rtgevc_backtransform(int64_t m, const double *S, int64_t lds, const double *
  * for graph capture.  On success stats (host double[nstats], nstats >=
  * RTGEVC_TIMED_NSTATS) holds:
  *   [0] total device time, ms (first to last event)
- *   [1..4] summed device time of the pre-processing, diagonal-solve, tile-update and
+ *   [1..4] summed device time of the pre-processing, diagonal-solve (a band's chain launch,
+ *          its solves with the in-band updates, counts here), tile-update and
  *          consolidation launches, ms
  *   [5..8] number of launches of each of those four classes
- *   [9] algorithmic flops of the tile updates, sum over k < r <= j of 4 h_k h_r h_j
+ *   [9] algorithmic flops of the tile-update launches: over their target rows k, sources r
+ *          and columns j >= r, the sum of 4 h_k h_r h_j (the persistent walker: of all tile
+ *          updates, sum over k < r <= j)
  *   [10] number of tiles M;  [11] tile size mb
  *   [12] device time of the refinement sweeps (mixed precision), ms;  [13] sweeps
  *   [14..16] the tile-update launches of the side stream alone (the band schedule's updates
