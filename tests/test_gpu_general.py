@@ -107,7 +107,7 @@ def test_general_walker(src, m, mb, seed):
     S, T, blk = _pencil(src, m, seed)
     Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
     rw = rt.Solver(m, mb=mb, schedule=rt.SCHEDULE_WALKER).run(Sd, Td)
-    rb = rt.Solver(m, mb=mb, band=1).run(Sd, Td)
+    rb = rt.Solver(m, mb=mb, band=1, schedule=1).run(Sd, Td)
     torch.cuda.synchronize()
     Zw = rw.Z.cpu().numpy()
     assert int(rw.info.item()) == 0
