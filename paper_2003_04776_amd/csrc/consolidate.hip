@@ -5,8 +5,9 @@
 // gap exceeds the exponent range).  Optionally each eigenvector is then divided by
 // max_i (|x_i| + |y_i|), which comes from the per-segment maxima the solves recorded
 // (segn, scaled by the same powers of two), so Z is read and written once.  Rows below
-// the eigenvector's tile and unselected columns are zeroed.  One workgroup per
-// eigenvalue (a complex pair is handled as one).
+// the eigenvector's tile and unselected columns are zeroed (for one pencil by a second
+// launch, one workgroup per column).  One workgroup per eigenvalue (a complex pair is
+// handled as one).
 #include <hip/hip_runtime.h>
 
 #include "layout.hpp"
@@ -27,22 +28,25 @@ __device__ __forceinline__ double block_max(double v, double* red) {
   return r;
 }
 
-__device__ __forceinline__ void consolidate_body(const PencilDesc& P) {
+// kZeros: the workgroup also writes the column's zeros (the batched kernel); otherwise
+// zero_below_kernel writes them.
+template <bool kZeros>
+__device__ __forceinline__ void consolidate_body(const PencilDesc& P, int64_t c) {
   __shared__ double red[kConsThreads / 64];
-  const int64_t c = blockIdx.x;
   const int64_t m = P.m;
   if (c >= m) return;
   const int kind = P.blk[c];
   if (kind == 2) return;
   const bool cplx = kind == 1;
   const int jt = P.tileof[c];
-  const int64_t rend = P.edges[jt + 1];
   double* zx = P.Z + c * P.ldz;
   double* zy = cplx ? zx + P.ldz : nullptr;
   if (!P.sel[c]) {
-    for (int64_t i = threadIdx.x; i < m; i += kConsThreads) {
-      zx[i] = 0.0;
-      if (cplx) zy[i] = 0.0;
+    if (kZeros) {
+      for (int64_t i = threadIdx.x; i < m; i += kConsThreads) {
+        zx[i] = 0.0;
+        if (cplx) zy[i] = 0.0;
+      }
     }
     if (threadIdx.x == 0 && P.scales) {
       P.scales[c] = 0;
@@ -98,9 +102,11 @@ __device__ __forceinline__ void consolidate_body(const PencilDesc& P) {
       }
     }
   }
-  for (int64_t i = rend + threadIdx.x; i < m; i += kConsThreads) {
-    zx[i] = 0.0;
-    if (cplx) zy[i] = 0.0;
+  if (kZeros) {
+    for (int64_t i = P.edges[jt + 1] + threadIdx.x; i < m; i += kConsThreads) {
+      zx[i] = 0.0;
+      if (cplx) zy[i] = 0.0;
+    }
   }
   if (threadIdx.x == 0 && P.scales) {
     const int sc = P.normalize ? 0 : E;
@@ -109,16 +115,47 @@ __device__ __forceinline__ void consolidate_body(const PencilDesc& P) {
   }
 }
 
-__global__ __launch_bounds__(kConsThreads) void consolidate_kernel(PencilDesc P) { consolidate_body(P); }
+// The zeros of column c: rows below the tile of its eigenvalue, or the whole column when the
+// eigenvalue is not selected (a complex pair follows its first column).  For one pencil they
+// are written by a launch of their own: with the rescaling and the zeros of a column in one
+// workgroup, m = 32768 took 3.44 ms where the two launches take 2.13 + 0.81 ms.  A batch of
+// short columns (orders up to 2048) keeps them in the rescaling workgroup: there the second
+// launch made the consolidation 3.54 ms per call against 3.08 ms.
+__device__ __forceinline__ void zero_below_body(const PencilDesc& P) {
+  const int64_t c = blockIdx.x;
+  const int64_t m = P.m;
+  if (c >= m) return;
+  const int64_t c1 = P.blk[c] == 2 ? c - 1 : c;
+  const int64_t lo = P.sel[c1] ? P.edges[P.tileof[c1] + 1] : 0;
+  double* z = P.Z + c * P.ldz;
+  for (int64_t i = lo + threadIdx.x; i < m; i += kConsThreads) z[i] = 0.0;
+}
+
+// Column of workgroup b: workgroups go to the eight XCDs in turn, and each XCD takes runs of
+// 32 adjacent columns (XCD x the runs x, x + 8, ...), so the segment tables' lines (32
+// exponents, 16 maxima) are read into one XCD's L2 once rather than into all eight (with
+// column = b, 0.7 GB more was read at m = 32768).  The blocks past the last whole group of
+// 256 keep their own column.
+__device__ __forceinline__ int64_t cons_column(int64_t b, int64_t n) {
+  if (b >= n / 256 * 256) return b;
+  const int64_t x = b % 8, i = b / 8;
+  return 256 * (i / 32) + 32 * x + i % 32;
+}
+
+__global__ __launch_bounds__(kConsThreads) void consolidate_kernel(PencilDesc P) {
+  consolidate_body<false>(P, cons_column(blockIdx.x, gridDim.x));
+}
+__global__ __launch_bounds__(kConsThreads) void zero_below_kernel(PencilDesc P) { zero_below_body(P); }
 
 // one pencil per blockIdx.y of a table
 __global__ __launch_bounds__(kConsThreads) void consolidate_batched(const PencilDesc* __restrict__ D) {
   const PencilDesc P = D[blockIdx.y];
-  consolidate_body(P);
+  consolidate_body<true>(P, blockIdx.x);
 }
 
 void launch_consolidate(const PencilDesc& P, hipStream_t s) {
   consolidate_kernel<<<(unsigned)P.m, kConsThreads, 0, s>>>(P);
+  zero_below_kernel<<<(unsigned)P.m, kConsThreads, 0, s>>>(P);
 }
 
 void launch_consolidate_batched(const PencilDesc* D, int n, int64_t max_m, hipStream_t s) {
