@@ -215,6 +215,38 @@ def test_select_subset(mb, precision):
     assert not Zg[:, ~on].any()
 
 
+@pytest.mark.parametrize("normalize", [True, False])
+def test_select_consolidation_ld(normalize):
+    """Consolidation with a selection and a padded output: five groups of 256 columns and a tail
+    (the rescaling workgroups take their columns in runs of 32 per XCD), unselected columns and
+    the rows below each eigenvalue's tile zero, the padding rows of Z untouched."""
+    torch = _torch()
+    from paper_2003_04776_amd import rtgevc as rt
+    m, ldz = 1300, 1303
+    S, T, blk = pencils.schur_pencil(m, 29)
+    rng = np.random.default_rng(5)
+    sel = (rng.random(m) < 0.3).astype(np.int32)
+    Sd, Td = rt.colmajor_to_device(S), rt.colmajor_to_device(T)
+    Zbuf = torch.full((m, ldz), 7.0, dtype=torch.float64, device="cuda")   # column-major, ld = ldz
+    Z = Zbuf.t()[:m]
+    r = rt.Solver(m, mb=64, band=2, schedule=1, normalize=normalize).run(
+        Sd, Td, select=sel, Z=Z)
+    torch.cuda.synchronize()
+    Zg = Z.cpu().numpy()
+    assert (Zbuf[:, m:].cpu().numpy() == 7.0).all()
+    Zo, _, io = oracle.tgevc(S, T, select=sel)
+    assert int(r.info.item()) == io
+    on = sel.astype(bool) | np.roll(sel.astype(bool) & (blk == 1), 1) | np.roll(sel.astype(bool) & (blk == 2), -1)
+    assert not Zg[:, ~on].any()
+    if normalize:
+        assert np.max(np.abs(Zg - Zo)) <= TOL
+    else:   # 2^scales[c] Z[:, c] represents the eigenvector: normalised, it is the oracle's
+        for c in np.nonzero(on)[0]:
+            p = c - 1 if blk[c] == 2 else c
+            n = (np.abs(Zg[:, p]) + np.abs(Zg[:, p + 1])).max() if blk[p] == 1 else np.abs(Zg[:, p]).max()
+            assert np.max(np.abs(Zg[:, c] / n - Zo[:, c])) <= TOL
+
+
 def test_eigvals_entry_point():
     torch = _torch()
     from paper_2003_04776_amd import rtgevc as rt
