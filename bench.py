@@ -35,7 +35,7 @@ METRIC = "FP64-equiv TFLOP/s + time for all eigvecs at m=32768; mixed/FP64 speed
 # WRITE_SIZE, scaled by what the counters read for a plain 1 GiB device copy), for the default
 # workload; valid only while the kernel's sources hash to the value they had when the counters
 # were taken (profiles/update_kernel_m32768_fp64_traffic.md).
-TRAFFIC = {"sources_sha256_16": "2909cc6af338a845", "bytes_per_launch": 4.403e9,
+TRAFFIC = {"sources_sha256_16": "01be4bf30fb4bffd", "bytes_per_launch": 4.403e9,
            "workload": (32768, 128, 4, 1)}   # m, mb, band, schedule
 
 

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librtgevc.so")
-SOURCES = ["api.hip", "preprocess.hip", "solve.hip", "update.hip", "update_i8.hip", "walker.hip", "consolidate.hip",
+SOURCES = ["api.hip", "preprocess.hip", "solve.hip", "chain128.hip", "update.hip", "update_i8.hip", "walker.hip", "consolidate.hip",
            "backtransform.hip", "left.hip", "refine.hip", "complex.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
@@ -23,7 +23,8 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
          "-I", os.path.join(ROOT, "include")]
 # per-source flags: the solve kernels keep the matrix instruction's accumulators in ordinary
 # vector registers, so that the 256-register cap of those kernels holds every register
-EXTRA = {"solve.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+EXTRA = {"solve.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+         "chain128.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _compile(src: str) -> str:

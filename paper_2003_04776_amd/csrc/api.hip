@@ -25,7 +25,7 @@
 namespace rgev {
 void launch_preprocess(const PencilDesc& P, hipStream_t s);
 void launch_solve(const PencilDesc& P, int r, hipStream_t s);
-void launch_band_chain(const PencilDesc& P, int r_lo, int r_hi, hipStream_t s);
+hipError_t launch_band_chain(const PencilDesc& P, int r_lo, int r_hi, hipStream_t s);
 bool launch_update(const PencilDesc& P, int k_lo, int k_hi, int j_lo, int s_lo, int s_hi, hipStream_t s);
 void launch_consolidate(const PencilDesc& P, hipStream_t s);
 void launch_preprocess_batched(const PencilDesc* D, int n, int64_t max_m, int max_tiles, hipStream_t s);
@@ -365,7 +365,7 @@ hipError_t enqueue_rows(const PencilDesc& P, int rows, hipStream_t sa, Aux& ax, 
     bool chain(int r_lo, int r_hi, int s) {
       if (!use_chain(P)) return chain_steps(r_lo, r_hi, s, *this);
       mark(1, true, st[s], nullptr);   // (timed as a solve launch: it holds the band's solves)
-      launch_band_chain(P, r_lo, r_hi, st[s]);
+      ok(launch_band_chain(P, r_lo, r_hi, st[s]));
       mark(1, false, st[s], nullptr);
       return err == hipSuccess;
     }
@@ -475,14 +475,14 @@ hipError_t enqueue_rows_one_stream(const PencilDesc& P, int rows, hipStream_t s)
     }
     bool chain(int r_lo, int r_hi, int st) {
       if (!use_chain(P)) return chain_steps(r_lo, r_hi, st, *this);
-      launch_band_chain(P, r_lo, r_hi, s);
-      return true;
+      return launch_band_chain(P, r_lo, r_hi, s) == hipSuccess;
     }
     bool record(int, int) { return true; }
     bool wait(int, int) { return true; }
   } ops{P, s};
-  band_schedule(rows, P.band, 0, ops);   // (one stream: no other launches to let in)
-  return hipGetLastError();
+  const bool ok = band_schedule(rows, P.band, 0, ops);   // (one stream: no other launches to let in)
+  const hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : (ok ? hipSuccess : hipErrorLaunchFailure);
 }
 
 // Refinement sweeps of a mixed-precision result (refine.hip): estimate and flag, FP64

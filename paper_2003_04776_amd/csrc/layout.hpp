@@ -155,6 +155,15 @@ __host__ __device__ inline int64_t walk_tasks(int64_t M) {
 // W tile of one (source row, tile column) pair: 2*MB K-rows x MB columns.
 __host__ __device__ constexpr int64_t w_tile_doubles(int mb) { return 2LL * mb * mb; }
 
+// The thread's index in the workgroup through a move the compiler cannot see through: each
+// call is a new value, so a kernel that runs several tiles in a loop keeps nothing derived from
+// the index live from one tile to the next (it recomputes it).
+__device__ __forceinline__ int opaque_tid() {
+  int t;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+  return t;
+}
+
 __host__ __device__ constexpr int tile_bound(int64_t m, int mb) {
   return m <= 0 ? 0 : (int)((m + (mb - 2)) / (mb - 1)) + 1;
 }

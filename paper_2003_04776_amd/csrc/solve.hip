@@ -4,6 +4,7 @@
 
 #include "solve_tile.hpp"
 #include "update_tile.hpp"
+#include "chain.hpp"
 
 namespace rgev {
 
@@ -27,18 +28,8 @@ __global__ __launch_bounds__(solve_total(MB), solve_waves_per_simd(MB)) __attrib
 // launch has to be placed on the GPU once rather than once per step.  Every tile gets the
 // same operations in the same order as with one launch per step, so the results are the same
 // bit for bit.  The update runs on the workgroup's own waves (a 2 x 2 wave grid for tiles
-// of 128, 1 x 2 for 64, one wave for 32) with its shared memory in the solve's.
-template <int MB> struct ChainUpdShape;
-template <> struct ChainUpdShape<32> { static constexpr int R = 1, C = 1; };
-template <> struct ChainUpdShape<64> { static constexpr int R = 1, C = 2; };
-template <> struct ChainUpdShape<128> { static constexpr int R = 2, C = 2; };
-
-template <int MB>
-union ChainSmem {
-  SolveSmem<MB> s;
-  UpdSmem<MB, ChainUpdShape<MB>::R> u;
-};
-
+// of 128, 1 x 2 for 64, one wave for 32) with its shared memory in the solve's.  Tiles of
+// 128 run band_chain_kernel_128 (chain128.hip), held to 256 registers a lane.
 template <int MB>
 __global__ __launch_bounds__(solve_total(MB), solve_waves_per_simd(MB)) __attribute__((amdgpu_num_vgpr(256))) void band_chain_kernel(PencilDesc P, int r_lo, int r_hi) {
   constexpr int WGR = ChainUpdShape<MB>::R, WGC = ChainUpdShape<MB>::C;
@@ -65,13 +56,13 @@ __global__ __launch_bounds__(solve_total(MB), solve_waves_per_simd(MB)) __attrib
   }
 }
 
-void launch_band_chain(const PencilDesc& P, int r_lo, int r_hi, hipStream_t s) {
+hipError_t launch_band_chain(const PencilDesc& P, int r_lo, int r_hi, hipStream_t s) {
   const int grid = P.Mmax - r_lo;
-  if (grid <= 0) return;
+  if (grid <= 0) return hipSuccess;
   switch (P.mb) {
-    case 32: band_chain_kernel<32><<<grid, solve_total(32), 0, s>>>(P, r_lo, r_hi); break;
-    case 64: band_chain_kernel<64><<<grid, solve_total(64), 0, s>>>(P, r_lo, r_hi); break;
-    default: band_chain_kernel<128><<<grid, solve_total(128), 0, s>>>(P, r_lo, r_hi); break;
+    case 32: band_chain_kernel<32><<<grid, solve_total(32), 0, s>>>(P, r_lo, r_hi); return hipSuccess;
+    case 64: band_chain_kernel<64><<<grid, solve_total(64), 0, s>>>(P, r_lo, r_hi); return hipSuccess;
+    default: return launch_band_chain_128(P, r_lo, r_hi, grid, s);
   }
 }
 

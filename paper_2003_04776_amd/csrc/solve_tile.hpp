@@ -210,8 +210,9 @@ struct SolveSmem {
 };
 
 // Solve of column slice z of tile (r, j) of one pencil (a workgroup of solve_total(MB)
-// threads; slices z = 0 .. SolveShape<MB>::CS - 1).
-template <int MB>
+// threads; slices z = 0 .. SolveShape<MB>::CS - 1).  kOpaque: the thread index is read
+// through opaque_tid (for a caller that runs several tiles in a loop).
+template <int MB, bool kOpaque = false>
 __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, int z, SolveSmem<MB>& sm) {
   constexpr int NTOT = solve_total(MB);
   constexpr int SW = SolveShape<MB>::SW, NCY = SolveShape<MB>::NCY;
@@ -254,7 +255,7 @@ __device__ __forceinline__ void solve_tile(const PencilDesc& P, int r, int j, in
   const double* T = P.T;
   const int64_t lds = P.lds, ldt = P.ldt, ldz = P.ldz;
 
-  const int lc = threadIdx.x;            // column thread lc holds tile column lo + lc
+  const int lc = kOpaque ? opaque_tid() : (int)threadIdx.x;   // column thread lc holds tile column lo + lc
   const int wave = lc / 64, lane = lc % 64;
   const bool inrange = lc < hw;
   const bool colthr = lc < NCY;

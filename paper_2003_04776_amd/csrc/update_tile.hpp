@@ -118,8 +118,8 @@ struct UpdSmem {
 };
 
 // Update of target tile (k, j) of one pencil by the band of sources in U (a workgroup of
-// 64 WGR WGC threads, the waves on a WGR x WGC grid over the tile).
-template <int MB, int WGR, int WGC, int NS = 3>
+// 64 WGR WGC threads, the waves on a WGR x WGC grid over the tile; kOpaque as for solve_tile).
+template <int MB, int WGR, int WGC, int NS = 3, bool kOpaque = false>
 __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange& U, int k, int j,
                                             UpdSmem<MB, WGR>& sm) {
   constexpr int WR = MB / WGR;          // rows per wave
@@ -158,7 +158,7 @@ __device__ __forceinline__ void update_tile(const PencilDesc& P, const UpdRange&
     es[i + 1] = i < ns ? ev[i + 1] : es[i];
     cs[i + 1] = cs[i] + 2 * ((es[i + 1] - es[i] + 15) & ~15) / kChunk;
   }
-  const int tid = threadIdx.x;
+  const int tid = kOpaque ? opaque_tid() : (int)threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int wr = wave / WGC, wc = wave % WGC;
   const int li = lane % 16, lk = lane / 16;
