@@ -157,7 +157,9 @@ int rtgevc(int64_t m, const double *S, int64_t lds, const double *T, int64_t ldt
  * library of RTGEVC_NOALLOC_SCRATCH_BYTES bytes, one per GPU the library runs on, held until
  * the process ends.  The call allocates and frees nothing, creates no stream or event and
  * never synchronises; on its first call on a device it looks up that device's address of
- * the array.
+ * the array (with tiles of 128 and bands of more than one row it also raises, once per device,
+ * the band-chain kernel's dynamic shared-memory limit; that kernel's four spilled registers
+ * use the per-lane private memory the HIP runtime provides with the queue).
  *   Arguments as for rtgevc() (argument numbers: 11 = opts, 12 = stream).
  *   Returns RTGEVC_ERR_SCRATCH, with nothing enqueued, when rtgevc_workspace_size(m, opts)
  *   exceeds RTGEVC_NOALLOC_SCRATCH_BYTES (with default options FP64 fits up to m = 9212).
