@@ -475,14 +475,16 @@ hipError_t enqueue_rows_one_stream(const PencilDesc& P, int rows, hipStream_t s)
     }
     bool chain(int r_lo, int r_hi, int st) {
       if (!use_chain(P)) return chain_steps(r_lo, r_hi, st, *this);
-      return launch_band_chain(P, r_lo, r_hi, s) == hipSuccess;
+      err = launch_band_chain(P, r_lo, r_hi, s);
+      return err == hipSuccess;
     }
     bool record(int, int) { return true; }
     bool wait(int, int) { return true; }
+    hipError_t err = hipSuccess;   // the chain launch's set-up error, if any
   } ops{P, s};
-  const bool ok = band_schedule(rows, P.band, 0, ops);   // (one stream: no other launches to let in)
+  band_schedule(rows, P.band, 0, ops);   // (one stream: no other launches to let in)
   const hipError_t e = hipGetLastError();
-  return e != hipSuccess ? e : (ok ? hipSuccess : hipErrorLaunchFailure);
+  return ops.err != hipSuccess ? ops.err : e;
 }
 
 // Refinement sweeps of a mixed-precision result (refine.hip): estimate and flag, FP64
